@@ -1,0 +1,302 @@
+"""Pins of the oracle's PSL source: ROI selection (Sec. 2.3.3, Fig. 1),
+allocation (Eq. 1-4) and sampling (Sec. 2.2, 2.3.3, 2.4), against exact
+rational arithmetic, integer closed forms and brute force."""
+import math
+from fractions import Fraction as Fr
+
+import numpy as np
+import pytest
+
+import psl_synth as S
+
+
+# ---------------------------------------------------------------- ROI -----
+def _roi_exact(lo, hi, zj, sad, zp):
+    lo, hi, zj, sad, zp = map(Fr, (lo, hi, zj, sad, zp))
+    c = (lo + hi) / 2
+    f = (sad - zp) / (sad - zj)
+    return c + (lo * zj / sad - c) * f, c + (hi * zj / sad - c) * f
+
+
+def test_roi_worked_example(oracle_lib):
+    # symmetric 10x10 cm field: the X jaw edge sits at 5 * 37/100 = 1.85 cm,
+    # the back-projection from the isocentre through it reaches the PSL
+    # plane at 1.85 * 75/63 = 2.2023809... cm
+    lo, hi = oracle_lib.roi(-5.0, 5.0, 37.0, 100.0, 25.0)
+    assert hi == pytest.approx(1.85 * 75.0 / 63.0, rel=1e-15)
+    assert lo == pytest.approx(-1.85 * 75.0 / 63.0, rel=1e-15)
+    # an off-centre field: centre at 4 cm, edges 2 and 6 at SAD
+    lo, hi = oracle_lib.roi(2.0, 6.0, 28.0, 100.0, 25.0)
+    elo, ehi = _roi_exact(2.0, 6.0, 28.0, 100.0, 25.0)
+    assert lo == pytest.approx(float(elo), abs=1e-13)
+    assert hi == pytest.approx(float(ehi), abs=1e-13)
+    # centre 4 + (0.56 - 4) * 75/72 = 0.41666..., 4 + (1.68 - 4) * 75/72
+    assert float(elo) == pytest.approx(4 + (0.56 - 4) * 75 / 72, abs=1e-12)
+
+
+def test_cull_matches_exact_overlap(oracle_lib):
+    rng = np.random.default_rng(5)
+    grid = S.clinical_grid()
+    geom = {"sad": 100.0, "z_x": 37.0, "z_y": 28.0}
+    fields = []
+    for i in range(40):
+        X1, X2, Y1, Y2 = S.random_jaws(500 + i)
+        fields.append(S.Field(X1, X2, Y1, Y2))
+    fields.append(S.square_field(4.0))
+    fields.append(S.square_field(30.0))
+    mask = oracle_lib.cull(fields, grid, True, geom)
+    for fi, f in enumerate(fields):
+        xlo, xhi = _roi_exact(f.X1, f.X2, 37.0, 100.0, grid.z_plane)
+        ylo, yhi = _roi_exact(f.Y1, f.Y2, 28.0, 100.0, grid.z_plane)
+        for iy in range(grid.n_y):
+            for ix in range(grid.n_x):
+                ex = (Fr(float(grid.x_edges[ix])) < xhi and
+                      Fr(float(grid.x_edges[ix + 1])) > xlo and
+                      Fr(float(grid.y_edges[iy])) < yhi and
+                      Fr(float(grid.y_edges[iy + 1])) > ylo)
+                assert mask[fi, iy * grid.n_x + ix] == int(ex), (fi, ix, iy)
+    # no cull / no jaws keep everything
+    assert oracle_lib.cull(fields[:2], grid, False, geom).all()
+    nj = S.Field(-1, 1, -1, 1, jaws=False)
+    assert oracle_lib.cull([nj], grid, True, geom).all()
+
+
+def test_cull_is_lossless_for_point_source(oracle_lib):
+    """With a point source (sigma 0) every particle that passes the jaws
+    lies in a selected position bin."""
+    ps = S.phase_space(200_000, 9, 20.0, S.Z_PSL, sigma_src=0.0)
+    grid = S.clinical_grid()
+    ph = S.water_phantom((16, 16, 16), 2.0, (-16.0, -16.0, 100.0))
+    geom = oracle_lib.geometry(ph)
+    perm, off, _ = oracle_lib.build_psl(ps, grid)
+    sps = ps.subset(perm)
+    for f in [S.square_field(4.0), S.Field(-3.0, 7.0, -12.0, 1.0),
+              S.square_field(30.0)]:
+        mask_all = oracle_lib.cull([f], grid, False, geom)
+        N, g, _ = oracle_lib.alloc([f], 0, int(off[-1]), off, mask_all, grid)
+        # one history per particle: every particle read exactly once
+        assert np.all(N[0] == np.diff(off))
+        smp = oracle_lib.sample([f], geom, off, N, g, 0, 1, sps)
+        acc = smp["status"] != 0
+        mask = oracle_lib.cull([f], grid, True, geom)[0]
+        pos = smp["key"] % (grid.n_x * grid.n_y)
+        assert acc.sum() > 0
+        assert np.all(mask[pos[acc]] == 1)
+
+
+# -------------------------------------------------------------- alloc -----
+def _alloc_exact(fields, mode, n_sim, offsets, mask, grid):
+    n_keys = grid.n_keys
+    npos = grid.n_x * grid.n_y
+    nk = [int(offsets[k + 1] - offsets[k]) for k in range(n_keys)]
+    C = [sum(nk[k] for k in range(n_keys) if mask[f][k % npos])
+         for f in range(len(fields))]
+    if mode == 0:
+        ideal = [Fr(n_sim * sum(C[:i + 1]), sum(C)) for i in range(len(C))]
+    else:
+        # MU prefix in double, as the reading states
+        m, pre = 0.0, []
+        tot = sum(f.MU for f in fields)
+        for f in fields:
+            m += f.MU
+            pre.append(math.floor(float(n_sim) * m / tot))
+        ideal = pre
+    F = [math.floor(v) for v in ideal]
+    F[-1] = n_sim
+    NF = [F[0]] + [F[i] - F[i - 1] for i in range(1, len(F))]
+    N = np.zeros((len(fields), n_keys), np.int64)
+    for f in range(len(fields)):
+        S_, prev = 0, 0
+        for k in range(n_keys):
+            if not mask[f][k % npos] or C[f] == 0:
+                continue
+            S_ += nk[k]
+            Fk = (NF[f] * S_) // C[f]
+            N[f, k] = Fk - prev
+            prev = Fk
+    return N, NF, C
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_alloc_matches_integer_closed_form(oracle_lib, mode):
+    ps = S.phase_space(100_000, 11, 20.0, S.Z_PSL)
+    grid = S.clinical_grid()
+    geom = {"sad": 100.0, "z_x": 37.0, "z_y": 28.0}
+    _, off, _ = oracle_lib.build_psl(ps, grid)
+    fields = [S.square_field(4.0, MU=17.5), S.square_field(10.0, MU=3.25),
+              S.Field(-2, 9, -7, 1, MU=60.0)]
+    mask = oracle_lib.cull(fields, grid, True, geom)
+    n_sim = 1_234_567
+    N, g, NF = oracle_lib.alloc(fields, mode, n_sim, off, mask, grid)
+    eN, eNF, C = _alloc_exact(fields, mode, n_sim, off, mask, grid)
+    np.testing.assert_array_equal(N, eN)
+    np.testing.assert_array_equal(NF, eNF)
+    assert N.sum() == n_sim
+    for f in range(len(fields)):
+        assert N[f].sum() == NF[f]
+        nk = np.diff(off)
+        sel = N[f] > 0
+        ideal = NF[f] * nk / C[f]
+        assert np.all(N[f][sel] >= np.floor(ideal[sel]))
+        assert np.all(N[f][sel] <= np.ceil(ideal[sel]))
+        # unbiasedness identity: sum over histories of g equals
+        # (MU_f / MU_tot) times the selected population
+        mu = fields[f].MU / sum(x.MU for x in fields)
+        assert (N[f] * g[f]).sum() == pytest.approx(mu * C[f], rel=1e-12)
+
+
+# ------------------------------------------------------------- sample -----
+def test_splitmix64_published_sequence(oracle_lib):
+    # the generator's reference output for seed 1234567 (Vigna's
+    # splitmix64.c), as successive states seed + k * golden gamma
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    s = 1234567
+    for w in want:
+        assert oracle_lib.splitmix64(s) == w
+        s = (s + 0x9E3779B97F4A7C15) % 2**64
+
+
+def _sample_brute(fields, geom, off, N, g, batch, seed, ps, oracle):
+    """Pure-Python reading of the sampling rules, exact rationals for the
+    jaw and fluence decisions."""
+    F, n_keys = N.shape
+    out = []
+    for f, fd in enumerate(fields):
+        for k in range(n_keys):
+            if N[f, k] == 0:
+                continue
+            nk = int(off[k + 1] - off[k])
+            Tk = int(N[:, k].sum())
+            before = int(N[:f, k].sum())
+            sk = oracle.splitmix64(seed ^ k) % nk
+            c = batch * Tk + before
+            for r in range(int(N[f, k])):
+                p = int(off[k]) + (sk + c + r) % nk
+                x, y = Fr(float(ps.x[p])), Fr(float(ps.y[p]))
+                u, v, w = (Fr(float(ps.u[p])), Fr(float(ps.v[p])),
+                           Fr(float(ps.w[p])))
+                zp = Fr(geom["z_psl"])
+                st = 1
+                if fd.jaws:
+                    xj = x + u / w * (Fr(geom["z_x"]) - zp)
+                    yj = y + v / w * (Fr(geom["z_y"]) - zp)
+                    sx = Fr(geom["z_x"]) / Fr(geom["sad"])
+                    sy = Fr(geom["z_y"]) / Fr(geom["sad"])
+                    if not (Fr(fd.X1) * sx <= xj <= Fr(fd.X2) * sx and
+                            Fr(fd.Y1) * sy <= yj <= Fr(fd.Y2) * sy):
+                        st = 0
+                if st and fd.fluence is not None:
+                    xs = x + u / w * (Fr(geom["sad"]) - zp)
+                    ys = y + v / w * (Fr(geom["sad"]) - zp)
+                    ix = math.floor((xs - Fr(fd.f_x0)) / Fr(fd.f_pix))
+                    iy = math.floor((ys - Fr(fd.f_y0)) / Fr(fd.f_pix))
+                    nfy, nfx = fd.fluence.shape
+                    if 0 <= ix < nfx and 0 <= iy < nfy and \
+                            fd.fluence[iy, ix] > 0:
+                        pass
+                    else:
+                        st = 2
+                out.append((p, f, st))
+    return out
+
+
+def test_sample_matches_brute_force(oracle_lib):
+    ps = S.phase_space(3000, 13, 20.0, S.Z_PSL)
+    grid = S.Grid(S.log_edges(0.1, 6.0, 4), S.linear_edges(-5.5, 5.5, 4),
+                  S.linear_edges(-5.5, 5.5, 4), S.Z_PSL)
+    ph = S.water_phantom((16, 16, 16), 2.0, (-16.0, -16.0, 100.0))
+    geom = oracle_lib.geometry(ph)
+    perm, off, _ = oracle_lib.build_psl(ps, grid)
+    sps = ps.subset(perm)
+    fl = S.fluence_map(3)
+    fl[::3, ::4] = 0.0
+    fields = [S.Field(-4, 6, -8, 3, MU=2.0, fluence=fl),
+              S.Field(-10, 10, -10, 10, MU=1.0)]
+    mask = oracle_lib.cull(fields, grid, True, geom)
+    N, g, _ = oracle_lib.alloc(fields, 1, 7001, off, mask, grid)
+    for batch in (0, 3):
+        smp = oracle_lib.sample(fields, geom, off, N, g, batch, 77, sps)
+        want = _sample_brute(fields, geom, off, N, g, batch, 77, sps,
+                             oracle_lib)
+        got = list(zip(smp["src"].tolist(), smp["field"].tolist(),
+                       [0 if s == 0 else (2 if s == 2 else 1)
+                        for s in smp["status"].tolist()]))
+        assert got == want
+        # the phantom sits under the whole field: nothing misses
+        assert not np.any(smp["status"] == 3)
+
+
+def test_cyclic_usage_counts(oracle_lib):
+    """Over consecutive batches each PSL is read cyclically from its random
+    start, so after T histories from a PSL of n particles every particle has
+    been used floor(T/n) or ceil(T/n) times."""
+    ps = S.phase_space(5000, 17, 20.0, S.Z_PSL)
+    grid = S.Grid(S.log_edges(0.1, 6.0, 3), S.linear_edges(-5.5, 5.5, 3),
+                  S.linear_edges(-5.5, 5.5, 3), S.Z_PSL)
+    ph = S.water_phantom((16, 16, 16), 2.0, (-16.0, -16.0, 100.0))
+    geom = oracle_lib.geometry(ph)
+    perm, off, _ = oracle_lib.build_psl(ps, grid)
+    sps = ps.subset(perm)
+    fields = [S.square_field(10.0, MU=1.0), S.square_field(6.0, MU=2.0)]
+    mask = oracle_lib.cull(fields, grid, True, geom)
+    N, g, _ = oracle_lib.alloc(fields, 1, 12_345, off, mask, grid)
+    use = np.zeros(off[-1], np.int64)
+    B = 4
+    for b in range(B):
+        smp = oracle_lib.sample(fields, geom, off, N, g, b, 5, sps)
+        np.add.at(use, smp["src"], 1)
+    for k in range(grid.n_keys):
+        nk = off[k + 1] - off[k]
+        T = B * N[:, k].sum()
+        if nk == 0 or T == 0:
+            continue
+        u = use[off[k]:off[k + 1]]
+        assert u.sum() == T
+        assert u.min() >= T // nk and u.max() <= -(-T // nk)
+
+
+def test_sample_state_rotation_and_projection(oracle_lib):
+    """Gantry rotation about the isocentre and the move to the phantom
+    surface, checked against an independent construction: the rotated
+    particle lies on the rotated ray and on the box surface."""
+    ps = S.phase_space(4000, 19, 20.0, S.Z_PSL)
+    grid = S.clinical_grid()
+    ph = S.water_phantom((32, 32, 32), 1.0, (-16.0, -16.0, 84.0))
+    geom = oracle_lib.geometry(ph)
+    perm, off, _ = oracle_lib.build_psl(ps, grid)
+    sps = ps.subset(perm)
+    for gdeg in (0.0, 51.43, 180.0, 300.0):
+        f = S.Field(-8, 8, -8, 8, gantry_deg=gdeg)
+        mask = oracle_lib.cull([f], grid, True, geom)
+        N, g, _ = oracle_lib.alloc([f], 0, 3000, off, mask, grid)
+        smp = oracle_lib.sample([f], geom, off, N, g, 0, 3, sps)
+        ok = smp["status"] == 1
+        st = smp["state"][ok]
+        src = smp["src"][ok]
+        th = math.radians(gdeg)
+        R = np.array([[math.cos(th), 0, math.sin(th)], [0, 1, 0],
+                      [-math.sin(th), 0, math.cos(th)]])
+        iso = np.array([0, 0, 100.0])
+        p0 = np.stack([sps.x[src], sps.y[src],
+                       np.full(len(src), 25.0)], 1).astype(np.float64)
+        d0 = np.stack([sps.u[src], sps.v[src], sps.w[src]], 1).astype(
+            np.float64)
+        p1 = (p0 - iso) @ R.T + iso
+        d1 = d0 @ R.T
+        np.testing.assert_allclose(st[:, 4:7], d1, atol=1e-12)
+        # on the ray: (p - p1) parallel to d1 and forward
+        dp = st[:, 1:4] - p1
+        t = (dp * d1).sum(1)
+        assert np.all(t >= -1e-9)
+        np.testing.assert_allclose(dp, t[:, None] * d1, atol=1e-9)
+        # on the box surface
+        lo, hi = np.array(geom["box_lo"]), np.array(geom["box_hi"])
+        on = np.isclose(st[:, 1:4], lo, atol=1e-9) | \
+            np.isclose(st[:, 1:4], hi, atol=1e-9)
+        assert np.all(on.any(1))
+        assert np.all(st[:, 1:4] >= lo - 1e-9) and \
+            np.all(st[:, 1:4] <= hi + 1e-9)
+        # weight: g of the PSL, unit fluence and phase-space weight
+        key = smp["key"][ok]
+        np.testing.assert_allclose(st[:, 7], g[0, key], rtol=1e-15)
