@@ -1,0 +1,321 @@
+/*
+ * psl.h - C ABI of the phase-space-let (PSL) Monte Carlo dose library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Townson et al., "GPU-based Monte Carlo radiotherapy dose
+ * calculation using phase-space sources" (gDPM v3.0), Method 3.
+ *
+ * Conventions for every call:
+ *  - Units: cm, kinetic MeV, g/cm^3, degrees.  Beam frame: the source is at
+ *    the origin, the beam runs along +z, the isocentre is at z = SAD.
+ *  - Pointers named d_* and the arrays inside the structs below are DEVICE
+ *    pointers unless marked "host".  The caller owns every buffer; the
+ *    library never allocates or frees device memory.  Scratch memory comes
+ *    from a caller-provided workspace whose size the matching
+ *    *_workspace_bytes() query returns.
+ *  - Calls only enqueue work on `stream` (a hipStream_t; NULL = the null
+ *    stream) and return; none synchronises.  Results that the host needs
+ *    (counts, statistics) are written to device memory the caller reads
+ *    after synchronising.
+ *  - Every call validates its arguments before enqueuing anything and
+ *    returns a psl_status; on failure nothing was enqueued and
+ *    psl_last_error() (thread-local) describes the problem.  No C++
+ *    exception crosses this interface.
+ */
+#ifndef PSL_H
+#define PSL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSL_ABI_VERSION 1
+
+typedef int32_t psl_status;
+#define PSL_OK 0
+#define PSL_EINVAL 1         /* bad argument (null pointer, bad size, ...)  */
+#define PSL_ENOSPC 2         /* workspace or queue capacity too small       */
+#define PSL_EHIP 3           /* HIP runtime or launch error                 */
+#define PSL_EUNSUPPORTED 4   /* current device is not gfx950                */
+
+#define PSL_MAX_EBINS 64     /* energy bins of a PSL grid                   */
+#define PSL_MAX_POSBINS 128  /* position bins per axis of a PSL grid        */
+#define PSL_MAX_QBUCKETS 16  /* energy buckets of the electron queue        */
+
+/* Human-readable description of the last failure on this thread. */
+const char *psl_last_error(void);
+int32_t psl_version(void);
+
+/* ------------------------------------------------------------------------ */
+/* Phase space (structure of arrays, device).                               */
+/* ------------------------------------------------------------------------ */
+typedef struct psl_phsp {
+    int64_t n;          /* particles (input) or capacity (output)           */
+    uint8_t *type;      /* 0 photon, 1 electron or positron (merged)        */
+    float *E;           /* kinetic energy, MeV                              */
+    float *x, *y;       /* position at the grid plane, cm                   */
+    float *u, *v, *w;   /* direction cosines                                */
+    float *wt;          /* statistical weight                               */
+} psl_phsp;
+
+/* PSL bin grid (host struct, passed by pointer, copied by value).  Edges
+ * must be strictly increasing.  Bin k of an axis is [edge_k, edge_k+1),
+ * the last bin closed on top; values outside [edge_0, edge_n] are outside
+ * the grid. */
+typedef struct psl_grid {
+    int32_t n_e, n_x, n_y, pad;
+    double z_plane;                         /* z of the PSL plane, cm       */
+    float e_edges[PSL_MAX_EBINS + 1];
+    float x_edges[PSL_MAX_POSBINS + 1];
+    float y_edges[PSL_MAX_POSBINS + 1];
+} psl_grid;
+
+/*
+ * psl_build - PSL generation (Sec. 2.3.2): split the phase space by particle
+ * type (photons; electrons and positrons merged, Sec. 2.1), by energy bin
+ * and by position bin, i.e. a stable sort on
+ *     key = ((type * n_e + e) * n_y + iy) * n_x + ix,
+ * keeping input order inside each PSL.
+ *   in        device SoA of in->n particles (read only); n < 2^31.
+ *   out       device SoA with out->n >= in->n; receives the kept particles
+ *             in PSL order (entries past the kept count are untouched).
+ *   d_offsets device int64[2 * n_e * n_x * n_y + 1]: PSL k holds
+ *             out[d_offsets[k] .. d_offsets[k+1]).
+ *   d_n_dropped device int64[1]: particles of unknown type (> 1), NaN, or
+ *             outside the grid; they are not copied.
+ * Errors: PSL_EINVAL for bad sizes or edges, PSL_ENOSPC if ws_bytes <
+ * psl_build_workspace_bytes(in->n, g).
+ */
+size_t psl_build_workspace_bytes(int64_t n, const psl_grid *g);
+psl_status psl_build(const psl_phsp *in, const psl_grid *g, psl_phsp *out,
+                     int64_t *d_offsets, int64_t *d_n_dropped, void *d_ws,
+                     size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Source sampling.                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* One treatment field or IMRT segment (host struct). */
+typedef struct psl_field {
+    double X1, X2, Y1, Y2;      /* jaw edges projected to the SAD plane, cm  */
+    double gantry_deg;          /* rotation about +y through the isocentre   */
+    double MU;                  /* monitor units, > 0                        */
+    const float *fluence;       /* device [nfy][nfx] map at the SAD plane,   */
+                                /* NULL = no modulation                      */
+    int32_t nfx, nfy;
+    double f_x0, f_y0, f_pix;   /* map origin (corner) and pixel size, cm   */
+    int32_t jaws_on;            /* 0: no jaw model and no ROI for this field */
+    int32_t pad;
+} psl_field;
+
+#define PSL_ALLOC_COUNTS 0      /* field totals in proportion to the        */
+                                /* particles of their selected PSLs (Eq.1-2) */
+#define PSL_ALLOC_MU 1          /* field totals in proportion to MU          */
+
+typedef struct psl_sample_cfg {
+    uint64_t seed;              /* random starts of the PSLs                 */
+    int64_t batch;              /* batch index b >= 0 (cursor and uids)      */
+    int64_t n_histories;        /* histories in this batch, all fields       */
+    int32_t cull;               /* 1: ROI selection of PSLs (Sec. 2.3.3)     */
+    int32_t alloc_mode;         /* PSL_ALLOC_COUNTS or PSL_ALLOC_MU          */
+    double sad, z_jaw_x, z_jaw_y;   /* cm; the PSL plane is grid.z_plane     */
+    double iso[3];              /* isocentre, world frame, cm                */
+    double box_lo[3], box_hi[3];/* phantom bounding box, world frame, cm     */
+} psl_sample_cfg;
+
+/* Particle queue entries (structure of arrays, device). */
+typedef struct psl_particles {
+    int64_t capacity;
+    float *E, *x, *y, *z, *u, *v, *w, *wt;
+    uint64_t *uid;              /* history id: batch * n_histories + h       */
+    uint32_t *ctr;              /* random-number identity (see transport)    */
+} psl_particles;
+
+/* Transport queues.  Electrons are kept in n_ebuckets regions of
+ * el.capacity / n_ebuckets entries each, one per kinetic-energy bucket
+ * [e_bucket_edges[b], e_bucket_edges[b+1]).  d_counts (device uint32,
+ * PSL_QCOUNTS entries): [0] photons queued, [1 + b] electrons in bucket b,
+ * [PSL_QCOUNTS - 1] entries lost because a region was full (a batch with a
+ * non-zero value here is invalid and must be re-run with more capacity). */
+#define PSL_QCOUNTS (PSL_MAX_QBUCKETS + 2)
+typedef struct psl_queue {
+    psl_particles ph;
+    psl_particles el;
+    int32_t n_ebuckets, pad;
+    float e_bucket_edges[PSL_MAX_QBUCKETS + 1];
+    uint32_t *d_counts;
+} psl_queue;
+
+/* Device statistics (zeroed by psl_sample, accumulated by the later calls
+ * of the same batch). */
+typedef struct psl_stats {
+    uint64_t histories;         /* sampled histories (Eq. 5 N_simulated)     */
+    uint64_t jaw_rejected;
+    uint64_t fluence_zero;
+    uint64_t missed;            /* accepted but missing the phantom          */
+    uint64_t photons;           /* queued source photons                     */
+    uint64_t electrons;         /* queued source electrons                   */
+    uint64_t lost;              /* queue overflow (batch invalid if > 0)     */
+    uint64_t interactions;      /* real photon interactions                  */
+    uint64_t secondaries;       /* Compton electrons queued                  */
+    uint64_t segments;          /* electron voxel segments                   */
+    uint64_t flights;           /* photon free flights (real + virtual)      */
+    uint64_t runaway;           /* particles stopped by the loop guard       */
+    double e_in;                /* sum E*wt of queued source particles       */
+    double e_escaped;           /* sum E*wt leaving the phantom              */
+    double reserved[2];
+} psl_stats;
+
+/*
+ * psl_sample - the PSL source for one batch (Sec. 2.2, 2.3.3, 2.4).
+ *  1. ROI selection: per field, a position bin is selected when its
+ *     rectangle overlaps with positive area the ROI obtained by
+ *     back-projecting from the field centre at SAD through the jaw edges to
+ *     the PSL plane (Sec. 2.3.3, Fig. 1).
+ *  2. Histories per (field i, PSL k), Eq. (1)-(4): field totals by
+ *     prefix-floor of n_histories over fields (alloc_mode), then
+ *     N_ik = floor(N_i S_k / C_i) - floor(N_i S_k-1 / C_i) with S_k the
+ *     running selected population; weight factor
+ *     g_ik = (MU_i / MU_total) * n_k / N_ik.
+ *  3. History r of PSL k reads particle off_k + ((s_k + c + r) mod n_k):
+ *     s_k = splitmix64(seed ^ k) mod n_k is the random start of PSL k and c
+ *     the particles already read from it by earlier batches and earlier
+ *     fields (reading wraps to the start, Sec. 2.3.3).
+ *  4. Jaw model (perfect collimators at z_jaw_x / z_jaw_y, Sec. 2.2);
+ *     fluence weight of the map pixel the ray crosses at the SAD plane
+ *     (Sec. 2.4); w' = w * fluence * g_ik (Eq. 4); gantry rotation; move
+ *     along the ray to the phantom box.
+ *  5. Accepted photons go to q->ph, electrons to the bucket of q->el that
+ *     holds their energy; queue counts are reset first.
+ *   grid, fields, cfg are host pointers (copied); fields has n_fields
+ *   entries (1 .. 4096).  d_offsets comes from psl_build over `sorted`.
+ *   d_mask (optional, device uint8 [n_fields][n_y*n_x]) receives the ROI
+ *   selection; d_alloc (optional, device int64 [n_fields][n_keys])
+ *   receives N_ik.  d_stats (device) is zeroed and filled.
+ * Errors: PSL_EINVAL (sizes, jaws X1 > X2, MU <= 0, z_jaw >= sad, ...),
+ * PSL_ENOSPC if the workspace is too small or the photon queue cannot hold
+ * n_histories entries.
+ */
+size_t psl_sample_workspace_bytes(const psl_grid *g, int32_t n_fields);
+psl_status psl_sample(const psl_phsp *sorted, const int64_t *d_offsets,
+                      const psl_grid *g, const psl_field *fields,
+                      int32_t n_fields, const psl_sample_cfg *cfg,
+                      psl_queue *q, uint8_t *d_mask, int64_t *d_alloc,
+                      psl_stats *d_stats, void *d_ws, size_t ws_bytes,
+                      void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Transport.                                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct psl_phantom {
+    int32_t nx, ny, nz, pad;
+    double dx, dy, dz;          /* voxel size, cm                             */
+    double x0, y0, z0;          /* corner of voxel (0,0,0), world frame, cm   */
+    const float *density;       /* device [nz][ny][nx], g/cm^3, x fastest     */
+    float rho_max;              /* >= max density (Woodcock majorant)         */
+    int32_t pad2;
+} psl_phantom;
+
+#define PSL_FLAG_FIRST_COLLISION 1   /* photons stop after one interaction, */
+                                     /* recoil energy deposited locally     */
+#define PSL_FLAG_NO_MSC 2            /* electrons are not deflected          */
+
+typedef struct psl_physics {
+    double n_e;                 /* electrons / cm^3 at 1 g/cm^3 (water)      */
+    double I_eV;                /* mean excitation energy                    */
+    double X0;                  /* radiation length, g/cm^2                  */
+    double step;                /* electron step, cm                         */
+    double p_cut, t_cut;        /* kinetic cut-offs, MeV                     */
+    double e_max;               /* highest energy the tables cover, MeV      */
+    int32_t flags;
+    int32_t pad;
+} psl_physics;
+
+/* Device tables built by psl_physics_init (opaque, PSL_TABLE_BYTES). */
+#define PSL_TABLE_BYTES (64 * 1024)
+
+/*
+ * psl_physics_init - builds the transport tables for `phys` into d_tables
+ * (device, PSL_TABLE_BYTES): Compton attenuation per unit density
+ * n_e sigma_KN(E) on a log energy grid, and the CSDA residual range above
+ * t_cut of the Bethe collision stopping power with its inverse.  The host
+ * computes them in double and enqueues one copy; phys->e_max must cover the
+ * highest particle energy.
+ */
+psl_status psl_physics_init(const psl_physics *phys, void *d_tables,
+                            void *stream);
+
+/* Dose accumulator: energy x weight per voxel for the current batch. */
+#define PSL_ACC_F64 0           /* double, MeV                               */
+#define PSL_ACC_FIXED64 1       /* uint64, MeV * 2^frac_bits                 */
+typedef struct psl_dose_acc {
+    int32_t mode;
+    int32_t frac_bits;          /* FIXED64 only, 16..40                      */
+    void *data;                 /* device [nz*ny*nx]                         */
+} psl_dose_acc;
+
+/* Launch shape.  NULL selects defaults; the autotuner chooses values. */
+typedef struct psl_launch {
+    int32_t block;              /* threads per block: 64..1024, multiple 64 */
+    int32_t blocks_per_cu;      /* resident blocks per CU to launch         */
+    int32_t n_cu;               /* CUs to assume (0 = query the device)     */
+    int32_t pad;
+} psl_launch;
+
+/*
+ * transport_batch - transports every queued particle to exhaustion and adds
+ * energy x weight per voxel to acc.  Physics (the paper defers to gDPM;
+ * this is the model of the workloads): photons undergo Compton scattering
+ * only (Klein-Nishina, free electrons at rest), tracked by Woodcock delta
+ * tracking with majorant rho_max; a recoil electron above t_cut is queued in
+ * its energy bucket, otherwise deposited on the spot; photons below p_cut
+ * deposit on the spot.  Electrons slow down continuously (CSDA, Bethe
+ * collision stopping power, I = I_eV, no density effect) in steps of
+ * `step` cm split at voxel faces, each piece depositing its energy loss in
+ * its voxel, deflected after each step by Highland's angle; at t_cut the
+ * remainder is deposited.  Particles leaving the box are tallied in
+ * stats.e_escaped.  FP32 arithmetic; tallies in FP64 or 64-bit fixed point.
+ * Random numbers: Philox4x32-10 keyed by seed, counter (uid, ctr, tag), so
+ * results do not depend on scheduling.  Photons are processed first, then
+ * electron buckets from the highest energy down.  Queues are consumed
+ * (counts zeroed).
+ * Errors: PSL_EINVAL (sizes, null pointers, bad acc mode), PSL_ENOSPC
+ * (workspace too small).
+ */
+size_t transport_batch_workspace_bytes(const psl_queue *q);
+psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
+                           const psl_physics *phys, const void *d_tables,
+                           uint64_t seed, psl_dose_acc *acc,
+                           psl_stats *d_stats, const psl_launch *launch,
+                           void *d_ws, size_t ws_bytes, void *stream);
+
+/*
+ * dose_tally - batch statistics and normalisation (Sec. 2.3.3, Eq. 5).
+ *  PSL_TALLY_FOLD: s1 += a, s2 += a^2 (double, per voxel) for the batch
+ *    tally a (MeV), then a = 0.
+ *  PSL_TALLY_FINALIZE: over n_batches >= 2 folded batches,
+ *    dose  = (s1 / B) * c_v,
+ *    sigma = sqrt(max(0, s2 - s1^2 / B) / (B - 1) / B) * c_v,
+ *    c_v = 1.602176634e-10 / (rho_v dx dy dz) * norm  [Gy per MeV];
+ *    norm = 1 / N_incident (dose per incident particle, Eq. 5 with the
+ *    history weights g_ik already carrying N_total / N_simulated).
+ *    Voxels of zero density get 0.
+ * d_s1, d_s2: device double [voxels]; d_dose, d_sigma: device float
+ * [voxels] (FINALIZE only).
+ */
+#define PSL_TALLY_FOLD 0
+#define PSL_TALLY_FINALIZE 1
+psl_status dose_tally(psl_dose_acc *acc, double *d_s1, double *d_s2,
+                      int32_t op, int32_t n_batches, const psl_phantom *ph,
+                      double norm, float *d_dose, float *d_sigma,
+                      void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSL_H */

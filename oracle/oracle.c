@@ -365,8 +365,8 @@ void oracle_sample(int n_fields, const ofield *fields, const ogeom *G,
                     double ys = py + (dv / dw) * (G->sad - pz);
                     double fx = floor((xs - F->f_x0) / F->f_pix);
                     double fy = floor((ys - F->f_y0) / F->f_pix);
-                    if (fx < 0.0 || fy < 0.0 || fx >= (double)F->nfx ||
-                        fy >= (double)F->nfy)
+                    if (!(fx >= 0.0 && fy >= 0.0 && fx < (double)F->nfx &&
+                          fy < (double)F->nfy))
                         fl = 0.0;
                     else
                         fl = (double)F->fluence[(int64_t)fy * F->nfx +

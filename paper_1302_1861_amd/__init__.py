@@ -1,0 +1,313 @@
+"""Python binding of the PSL dose library (libpsl.so, gfx950).
+
+Argument marshalling only: every step of the dose path runs in the HIP
+kernels behind the C ABI declared in include/psl.h.  PyTorch provides device
+memory and the current HIP stream.  The functions below carry the C names
+(psl_build, psl_sample, transport_batch, dose_tally, ...) and take torch
+tensors; ``Engine`` allocates the buffers one workload needs and chains the
+calls.  There is no CPU fallback: if the library is missing or the device is
+not a gfx950, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpsl.so")
+
+PSL_OK, PSL_EINVAL, PSL_ENOSPC, PSL_EHIP, PSL_EUNSUPPORTED = 0, 1, 2, 3, 4
+PSL_MAX_EBINS = 64
+PSL_MAX_POSBINS = 128
+PSL_MAX_QBUCKETS = 16
+PSL_QCOUNTS = PSL_MAX_QBUCKETS + 2
+PSL_TABLE_BYTES = 64 * 1024
+PSL_ALLOC_COUNTS, PSL_ALLOC_MU = 0, 1
+PSL_ACC_F64, PSL_ACC_FIXED64 = 0, 1
+PSL_TALLY_FOLD, PSL_TALLY_FINALIZE = 0, 1
+PSL_FLAG_FIRST_COLLISION, PSL_FLAG_NO_MSC = 1, 2
+
+EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
+           "psl_build", "psl_sample_workspace_bytes", "psl_sample",
+           "psl_physics_init", "transport_batch_workspace_bytes",
+           "transport_batch", "dose_tally"]
+
+
+class PslError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("psl status %d: %s" % (status, msg))
+        self.status = status
+
+
+# --------------------------------------------------------------- structs --
+class psl_phsp(C.Structure):
+    _fields_ = [("n", C.c_int64), ("type", C.c_void_p), ("E", C.c_void_p),
+                ("x", C.c_void_p), ("y", C.c_void_p), ("u", C.c_void_p),
+                ("v", C.c_void_p), ("w", C.c_void_p), ("wt", C.c_void_p)]
+
+
+class psl_grid(C.Structure):
+    _fields_ = [("n_e", C.c_int32), ("n_x", C.c_int32), ("n_y", C.c_int32),
+                ("pad", C.c_int32), ("z_plane", C.c_double),
+                ("e_edges", C.c_float * (PSL_MAX_EBINS + 1)),
+                ("x_edges", C.c_float * (PSL_MAX_POSBINS + 1)),
+                ("y_edges", C.c_float * (PSL_MAX_POSBINS + 1))]
+
+
+class psl_field(C.Structure):
+    _fields_ = [("X1", C.c_double), ("X2", C.c_double), ("Y1", C.c_double),
+                ("Y2", C.c_double), ("gantry_deg", C.c_double),
+                ("MU", C.c_double), ("fluence", C.c_void_p),
+                ("nfx", C.c_int32), ("nfy", C.c_int32), ("f_x0", C.c_double),
+                ("f_y0", C.c_double), ("f_pix", C.c_double),
+                ("jaws_on", C.c_int32), ("pad", C.c_int32)]
+
+
+class psl_sample_cfg(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("batch", C.c_int64),
+                ("n_histories", C.c_int64), ("cull", C.c_int32),
+                ("alloc_mode", C.c_int32), ("sad", C.c_double),
+                ("z_jaw_x", C.c_double), ("z_jaw_y", C.c_double),
+                ("iso", C.c_double * 3), ("box_lo", C.c_double * 3),
+                ("box_hi", C.c_double * 3)]
+
+
+class psl_particles(C.Structure):
+    _fields_ = [("capacity", C.c_int64)] + \
+        [(k, C.c_void_p) for k in ("E", "x", "y", "z", "u", "v", "w", "wt",
+                                   "uid", "ctr")]
+
+
+class psl_queue(C.Structure):
+    _fields_ = [("ph", psl_particles), ("el", psl_particles),
+                ("n_ebuckets", C.c_int32), ("pad", C.c_int32),
+                ("e_bucket_edges", C.c_float * (PSL_MAX_QBUCKETS + 1)),
+                ("d_counts", C.c_void_p)]
+
+
+STATS_FIELDS = ["histories", "jaw_rejected", "fluence_zero", "missed",
+                "photons", "electrons", "lost", "interactions", "secondaries",
+                "segments", "flights", "runaway"]
+
+
+class psl_stats(C.Structure):
+    _fields_ = [(k, C.c_uint64) for k in STATS_FIELDS] + \
+        [("e_in", C.c_double), ("e_escaped", C.c_double),
+         ("reserved", C.c_double * 2)]
+
+
+class psl_phantom(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("pad", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
+                ("dz", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
+                ("z0", C.c_double), ("density", C.c_void_p),
+                ("rho_max", C.c_float), ("pad2", C.c_int32)]
+
+
+class psl_physics(C.Structure):
+    _fields_ = [("n_e", C.c_double), ("I_eV", C.c_double),
+                ("X0", C.c_double), ("step", C.c_double),
+                ("p_cut", C.c_double), ("t_cut", C.c_double),
+                ("e_max", C.c_double), ("flags", C.c_int32),
+                ("pad", C.c_int32)]
+
+
+class psl_dose_acc(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("frac_bits", C.c_int32),
+                ("data", C.c_void_p)]
+
+
+class psl_launch(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("n_cu", C.c_int32), ("pad", C.c_int32)]
+
+
+# ------------------------------------------------------------------ load --
+_lib = None
+
+
+def lib():
+    """The loaded libpsl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                "libpsl.so is not built; run "
+                "`python -m paper_1302_1861_amd.build_lib` (or "
+                "__graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, sz, u64, d = (C.c_void_p, C.c_int32, C.c_int64,
+                                     C.c_size_t, C.c_uint64, C.c_double)
+        L.psl_last_error.restype = C.c_char_p
+        L.psl_version.restype = i32
+        L.psl_build_workspace_bytes.argtypes = [i64, vp]
+        L.psl_build_workspace_bytes.restype = sz
+        L.psl_build.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+        L.psl_build.restype = i32
+        L.psl_sample_workspace_bytes.argtypes = [vp, i32]
+        L.psl_sample_workspace_bytes.restype = sz
+        L.psl_sample.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
+                                 sz, vp]
+        L.psl_sample.restype = i32
+        L.psl_physics_init.argtypes = [vp, vp, vp]
+        L.psl_physics_init.restype = i32
+        L.transport_batch_workspace_bytes.argtypes = [vp]
+        L.transport_batch_workspace_bytes.restype = sz
+        L.transport_batch.argtypes = [vp, vp, vp, vp, u64, vp, vp, vp, vp, sz,
+                                      vp]
+        L.transport_batch.restype = i32
+        L.dose_tally.argtypes = [vp, vp, vp, i32, i32, vp, d, vp, vp, vp]
+        L.dose_tally.restype = i32
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != PSL_OK:
+        raise PslError(status, lib().psl_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------- marshals --
+def make_grid(e_edges, x_edges, y_edges, z_plane) -> psl_grid:
+    g = psl_grid()
+    e, x, y = (np.asarray(a, np.float32) for a in (e_edges, x_edges, y_edges))
+    if len(e) - 1 > PSL_MAX_EBINS or len(x) - 1 > PSL_MAX_POSBINS or \
+            len(y) - 1 > PSL_MAX_POSBINS:
+        raise ValueError("grid too large for psl_grid")
+    g.n_e, g.n_x, g.n_y = len(e) - 1, len(x) - 1, len(y) - 1
+    g.z_plane = float(z_plane)
+    for i, v in enumerate(e):
+        g.e_edges[i] = float(v)
+    for i, v in enumerate(x):
+        g.x_edges[i] = float(v)
+    for i, v in enumerate(y):
+        g.y_edges[i] = float(v)
+    return g
+
+
+PHSP_KEYS = ("type", "E", "x", "y", "u", "v", "w", "wt")
+PART_KEYS = ("E", "x", "y", "z", "u", "v", "w", "wt", "uid", "ctr")
+
+
+def make_phsp(t: Dict, n: Optional[int] = None) -> psl_phsp:
+    p = psl_phsp()
+    p.n = int(t["E"].shape[0] if n is None else n)
+    for k in PHSP_KEYS:
+        setattr(p, k, t[k].data_ptr())
+    return p
+
+
+def make_particles(t: Dict) -> psl_particles:
+    p = psl_particles()
+    p.capacity = int(t["E"].shape[0])
+    for k in PART_KEYS:
+        setattr(p, k, t[k].data_ptr())
+    return p
+
+
+def make_fields(fields, fluence_tensors) -> "C.Array":
+    arr = (psl_field * len(fields))()
+    for i, f in enumerate(fields):
+        a = arr[i]
+        a.X1, a.X2, a.Y1, a.Y2 = f.X1, f.X2, f.Y1, f.Y2
+        a.gantry_deg, a.MU = f.gantry_deg, f.MU
+        fl = fluence_tensors[i]
+        if fl is not None:
+            a.fluence = fl.data_ptr()
+            a.nfy, a.nfx = fl.shape
+        else:
+            a.fluence, a.nfx, a.nfy = None, 0, 0
+        a.f_x0, a.f_y0, a.f_pix = f.f_x0, f.f_y0, f.f_pix
+        a.jaws_on = 1 if f.jaws else 0
+    return arr
+
+
+def make_phantom(density_t, voxel, origin, rho_max=None) -> psl_phantom:
+    p = psl_phantom()
+    p.nz, p.ny, p.nx = density_t.shape
+    p.dx, p.dy, p.dz = (float(v) for v in voxel)
+    p.x0, p.y0, p.z0 = (float(v) for v in origin)
+    p.density = density_t.data_ptr()
+    p.rho_max = float(rho_max if rho_max is not None
+                      else density_t.max().item())
+    return p
+
+
+def make_physics(n_e=3.343e23, I_eV=75.0, X0=36.08, step=0.1, p_cut=0.010,
+                 t_cut=0.700 - 0.51099895, e_max=6.0, flags=0) -> psl_physics:
+    y = psl_physics()
+    y.n_e, y.I_eV, y.X0, y.step, y.p_cut, y.t_cut, y.e_max = (
+        n_e, I_eV, X0, step, p_cut, t_cut, e_max)
+    y.flags = flags
+    return y
+
+
+# ------------------------------------------------------- the C functions --
+def psl_build(in_phsp: Dict, grid: psl_grid, out_phsp: Dict, offsets,
+              n_dropped, ws, stream=None):
+    i, o = make_phsp(in_phsp), make_phsp(out_phsp)
+    _check(lib().psl_build(C.byref(i), C.byref(grid), C.byref(o),
+                           _ptr(offsets), _ptr(n_dropped), _ptr(ws),
+                           ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def psl_sample(sorted_phsp: Dict, offsets, grid: psl_grid, fields_arr,
+               cfg: psl_sample_cfg, queue: psl_queue, stats, ws, mask=None,
+               alloc=None, n_sorted=None, stream=None):
+    s = make_phsp(sorted_phsp, n_sorted)
+    _check(lib().psl_sample(C.byref(s), _ptr(offsets), C.byref(grid),
+                            fields_arr, len(fields_arr), C.byref(cfg),
+                            C.byref(queue), _ptr(mask), _ptr(alloc),
+                            _ptr(stats), _ptr(ws),
+                            ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def psl_physics_init(phys: psl_physics, tables, stream=None):
+    _check(lib().psl_physics_init(C.byref(phys), _ptr(tables),
+                                  _stream(stream)))
+
+
+def transport_batch(queue: psl_queue, phantom: psl_phantom,
+                    phys: psl_physics, tables, seed: int, acc: psl_dose_acc,
+                    stats, ws, launch: Optional[psl_launch] = None,
+                    stream=None):
+    _check(lib().transport_batch(
+        C.byref(queue), C.byref(phantom), C.byref(phys), _ptr(tables),
+        C.c_uint64(seed), C.byref(acc), _ptr(stats),
+        C.byref(launch) if launch is not None else None, _ptr(ws),
+        ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def dose_tally(acc: Optional[psl_dose_acc], s1, s2, op, n_batches,
+               phantom: psl_phantom, norm=1.0, dose=None, sigma=None,
+               stream=None):
+    _check(lib().dose_tally(C.byref(acc) if acc is not None else None,
+                            _ptr(s1), _ptr(s2), op, n_batches,
+                            C.byref(phantom), float(norm), _ptr(dose),
+                            _ptr(sigma), _stream(stream)))
+
+
+def stats_to_dict(stats_t) -> Dict:
+    raw = stats_t.cpu().numpy().tobytes()
+    s = psl_stats.from_buffer_copy(raw[:C.sizeof(psl_stats)])
+    d = {k: int(getattr(s, k)) for k in STATS_FIELDS}
+    d["e_in"], d["e_escaped"] = s.e_in, s.e_escaped
+    d["e_killed"] = s.reserved[0]
+    return d
+
+
+from .engine import Engine, Buffers  # noqa: E402,F401

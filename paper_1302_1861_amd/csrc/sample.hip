@@ -1,0 +1,545 @@
+// psl_sample: the PSL source of one batch (Sec. 2.2, 2.3.3, 2.4).
+//
+//   k_cull          ROI selection per (field, position bin)
+//   k_field_pop     C_i: particles in the selected PSLs of field i (Eq. 1)
+//   k_field_totals  N_i by prefix-floor over fields (Eq. 2 or MU)
+//   k_key_alloc     N_ik by prefix-floor over keys, g_ik (Eq. 2-4)
+//   k_cursor        particles already read from each PSL (cyclic cursor)
+//   scan            history ranges of (field, PSL)
+//   k_sample        one thread per history: read, jaw test, fluence, weight,
+//                   gantry, projection, wave-aggregated push to the queues
+//
+// The per-history decisions (jaw acceptance, fluence pixel, hitting the
+// phantom) are taken in double precision with floating-point contraction
+// disabled, so they are reproducible operation by operation.
+#include "common.hpp"
+#include "scan.hpp"
+
+#include <cmath>
+#include <vector>
+
+namespace psl {
+
+psl_status validate_grid_public(const psl_grid *g);
+
+namespace {
+
+struct FieldDev {
+    double X1, X2, Y1, Y2;
+    double cos_g, sin_g, MU;
+    const float *fluence;
+    int32_t nfx, nfy, jaws_on, pad;
+    double f_x0, f_y0, f_pix;
+};
+
+struct Geo {
+    double sad, z_x, z_y, z_psl;
+    double iso[3], lo[3], hi[3];
+};
+
+__global__ void k_sample_init(psl_stats *stats, uint32_t *counts) {
+    int t = threadIdx.x;
+    if (t < (int)(sizeof(psl_stats) / 8))
+        reinterpret_cast<uint64_t *>(stats)[t] = 0;
+    if (t < PSL_QCOUNTS) counts[t] = 0;
+}
+
+// ROI at the PSL plane from the field centre at SAD through the jaw edges
+// (Sec. 2.3.3, Fig. 1); a bin is kept when it overlaps the ROI with
+// positive area.
+__device__ void roi(double lo_sad, double hi_sad, double z_jaw, double sad,
+                    double z_psl, double *lo, double *hi) {
+#pragma clang fp contract(off)
+    double c = (lo_sad + hi_sad) * 0.5;
+    double f = (sad - z_psl) / (sad - z_jaw);
+    double a_lo = lo_sad * z_jaw / sad;
+    double a_hi = hi_sad * z_jaw / sad;
+    *lo = c + (a_lo - c) * f;
+    *hi = c + (a_hi - c) * f;
+}
+
+__global__ void __launch_bounds__(256)
+k_cull(const FieldDev *__restrict__ fields, int n_fields, Geo geo,
+       psl_grid g, int cull, uint8_t *__restrict__ mask) {
+#pragma clang fp contract(off)
+    const int P = g.n_x * g.n_y;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_fields * P) return;
+    int f = (int)(i / P), p = (int)(i % P);
+    int ix = p % g.n_x, iy = p / g.n_x;
+    const FieldDev F = fields[f];
+    uint8_t keep = 1;
+    if (cull && F.jaws_on) {
+        double xlo, xhi, ylo, yhi;
+        roi(F.X1, F.X2, geo.z_x, geo.sad, geo.z_psl, &xlo, &xhi);
+        roi(F.Y1, F.Y2, geo.z_y, geo.sad, geo.z_psl, &ylo, &yhi);
+        keep = ((double)g.x_edges[ix] < xhi) &&
+               ((double)g.x_edges[ix + 1] > xlo) &&
+               ((double)g.y_edges[iy] < yhi) &&
+               ((double)g.y_edges[iy + 1] > ylo);
+    }
+    mask[i] = keep;
+}
+
+constexpr int kAllocBlock = 1024;
+
+__global__ void __launch_bounds__(kAllocBlock)
+k_field_pop(const int64_t *__restrict__ off, int64_t n_keys, int P,
+            const uint8_t *__restrict__ mask, int64_t *__restrict__ C) {
+    __shared__ uint64_t s_wave[kAllocBlock / 64];
+    const int f = blockIdx.x;
+    const uint8_t *m = mask + (int64_t)f * P;
+    uint64_t s = 0;
+    for (int64_t k = threadIdx.x; k < n_keys; k += kAllocBlock)
+        if (m[k % P]) s += (uint64_t)(off[k + 1] - off[k]);
+    uint64_t tot;
+    block_exclusive_scan<kAllocBlock>(s, &tot, s_wave);
+    if (threadIdx.x == 0) C[f] = (int64_t)tot;
+}
+
+// Field totals by prefix-floor (one thread; fields are few).
+__global__ void k_field_totals(const FieldDev *__restrict__ fields,
+                               int n_fields, const int64_t *__restrict__ C,
+                               int mode, int64_t n_sim,
+                               int64_t *__restrict__ NF,
+                               double *__restrict__ mu_tot_out) {
+#pragma clang fp contract(off)
+    double mu_tot = 0.0;
+    for (int f = 0; f < n_fields; ++f) mu_tot += fields[f].MU;
+    *mu_tot_out = mu_tot;
+    int64_t prev = 0;
+    if (mode == PSL_ALLOC_COUNTS) {
+        int64_t c_all = 0;
+        for (int f = 0; f < n_fields; ++f) c_all += C[f];
+        int64_t acc = 0;
+        for (int f = 0; f < n_fields; ++f) {
+            acc += C[f];
+            int64_t F = (f == n_fields - 1 || c_all == 0)
+                            ? (f == n_fields - 1 && c_all ? n_sim : 0)
+                            : (int64_t)(((unsigned __int128)n_sim * acc) /
+                                        (uint64_t)c_all);
+            NF[f] = F - prev;
+            prev = F;
+        }
+    } else {
+        double m = 0.0;
+        for (int f = 0; f < n_fields; ++f) {
+            m += fields[f].MU;
+            int64_t F = (f == n_fields - 1)
+                            ? n_sim
+                            : (int64_t)floor((double)n_sim * m / mu_tot);
+            NF[f] = F - prev;
+            prev = F;
+        }
+    }
+}
+
+// N_ik = floor(N_i S_k / C_i) - floor(N_i S_k-1 / C_i); one block per field,
+// a block scan over the keys in chunks.
+__global__ void __launch_bounds__(kAllocBlock)
+k_key_alloc(const FieldDev *__restrict__ fields, const int64_t *__restrict__ off,
+            int64_t n_keys, int P, const uint8_t *__restrict__ mask,
+            const int64_t *__restrict__ C, const int64_t *__restrict__ NF,
+            const double *__restrict__ mu_tot, int64_t *__restrict__ N,
+            double *__restrict__ g) {
+#pragma clang fp contract(off)
+    __shared__ uint64_t s_wave[kAllocBlock / 64];
+    const int f = blockIdx.x;
+    const uint8_t *m = mask + (int64_t)f * P;
+    const uint64_t Cf = (uint64_t)C[f];
+    const uint64_t Ni = (uint64_t)NF[f];
+    const double wmu = fields[f].MU / *mu_tot;
+    uint64_t carry = 0;
+    for (int64_t k0 = 0; k0 < n_keys; k0 += kAllocBlock) {
+        int64_t k = k0 + threadIdx.x;
+        uint64_t nk = 0;
+        bool sel = false;
+        if (k < n_keys) {
+            nk = (uint64_t)(off[k + 1] - off[k]);
+            sel = m[k % P] != 0;
+        }
+        uint64_t v = sel ? nk : 0;
+        uint64_t tot;
+        uint64_t ex = block_exclusive_scan<kAllocBlock>(v, &tot, s_wave);
+        if (k < n_keys) {
+            int64_t idx = (int64_t)f * n_keys + k;
+            int64_t Nik = 0;
+            if (sel && Cf > 0) {
+                uint64_t Sk = carry + ex + v, Sp = carry + ex;
+                uint64_t a = (uint64_t)(((unsigned __int128)Ni * Sk) / Cf);
+                uint64_t b = (uint64_t)(((unsigned __int128)Ni * Sp) / Cf);
+                Nik = (int64_t)(a - b);
+            }
+            N[idx] = Nik;
+            g[idx] = Nik > 0 ? wmu * ((double)nk / (double)Nik) : 0.0;
+        }
+        carry += tot;
+    }
+}
+
+// Per PSL: particles read by earlier fields of a batch, and per batch.
+__global__ void k_cursor(const int64_t *__restrict__ N, int n_fields,
+                         int64_t n_keys, int64_t *__restrict__ before,
+                         int64_t *__restrict__ T) {
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_keys) return;
+    int64_t run = 0;
+    for (int f = 0; f < n_fields; ++f) {
+        before[(int64_t)f * n_keys + k] = run;
+        run += N[(int64_t)f * n_keys + k];
+    }
+    T[k] = run;
+}
+
+struct QueueDev {
+    psl_particles ph, el;
+    int32_t n_b;
+    int64_t cap_b;
+    uint32_t *counts;
+};
+
+__device__ __forceinline__ void push(const psl_particles &P, int64_t slot,
+                                     float E, float x, float y, float z,
+                                     float u, float v, float w, float wt,
+                                     uint64_t uid, uint32_t ctr) {
+    P.E[slot] = E;
+    P.x[slot] = x;
+    P.y[slot] = y;
+    P.z[slot] = z;
+    P.u[slot] = u;
+    P.v[slot] = v;
+    P.w[slot] = w;
+    P.wt[slot] = wt;
+    P.uid[slot] = uid;
+    P.ctr[slot] = ctr;
+}
+
+constexpr uint32_t kSourceElectronCtr = 0xFFFFFFFFu;
+
+__global__ void __launch_bounds__(256)
+k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
+         const FieldDev *__restrict__ fields, Geo geo,
+         const int64_t *__restrict__ H, int64_t n_ranges,
+         const uint64_t *__restrict__ h_total_p,
+         const int64_t *__restrict__ before, const int64_t *__restrict__ T,
+         const double *__restrict__ g, uint64_t seed, int64_t batch,
+         QueueDev q, psl_queue qcfg, psl_stats *__restrict__ stats) {
+#pragma clang fp contract(off)
+    __shared__ float s_edges[PSL_MAX_QBUCKETS + 1];
+    if (threadIdx.x <= PSL_MAX_QBUCKETS)
+        s_edges[threadIdx.x] = qcfg.e_bucket_edges[threadIdx.x];
+    __syncthreads();
+    const int64_t h_total = (int64_t)*h_total_p;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // loop bound uniform per wave so that wave-level pushes see all lanes
+    const int64_t h_end = ((h_total + 63) / 64) * 64;
+    for (int64_t h0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+         h0 < h_end; h0 += stride) {
+        const bool live = h0 < h_total;
+        int status = -1;  // 0 jaw, 2 fluence, 3 miss, 1 accepted
+        float oE = 0, ox = 0, oy = 0, oz = 0, ou = 0, ov = 0, ow = 0, owt = 0;
+        uint8_t type = 0;
+        if (live) {
+            // range containing h: last idx with H[idx] <= h
+            int64_t lo = 0, hi = n_ranges;  // H[lo] <= h < H[hi]
+            while (hi - lo > 1) {
+                int64_t mid = (lo + hi) >> 1;
+                if (H[mid] <= h0) lo = mid; else hi = mid;
+            }
+            const int64_t idx = lo;
+            const int f = (int)(idx / n_keys);
+            const int64_t k = idx % n_keys;
+            const int64_t r = h0 - H[idx];
+            const uint64_t nk = (uint64_t)(off[k + 1] - off[k]);
+            const uint64_t sk = splitmix64(seed ^ (uint64_t)k) % nk;
+            const uint64_t c = (uint64_t)batch * (uint64_t)T[k] +
+                               (uint64_t)before[idx];
+            const int64_t p = off[k] + (int64_t)((sk + c + (uint64_t)r) % nk);
+            const FieldDev F = fields[f];
+            type = ps.type[p];
+            const double px = ps.x[p], py = ps.y[p], pz = geo.z_psl;
+            const double du = ps.u[p], dv = ps.v[p], dw = ps.w[p];
+            status = 1;
+            if (F.jaws_on) {
+                if (!(dw > 0.0)) {
+                    status = 0;
+                } else {
+                    double tx = du / dw, ty = dv / dw;
+                    double xj = px + tx * (geo.z_x - pz);
+                    double yj = py + ty * (geo.z_y - pz);
+                    double xlo = F.X1 * geo.z_x / geo.sad;
+                    double xhi = F.X2 * geo.z_x / geo.sad;
+                    double ylo = F.Y1 * geo.z_y / geo.sad;
+                    double yhi = F.Y2 * geo.z_y / geo.sad;
+                    if (!(xj >= xlo && xj <= xhi && yj >= ylo && yj <= yhi))
+                        status = 0;
+                }
+            }
+            double fl = 1.0;
+            if (status == 1 && F.nfx > 0) {
+                if (!(dw > 0.0)) {
+                    status = 2;
+                } else {
+                    double xs = px + (du / dw) * (geo.sad - pz);
+                    double ys = py + (dv / dw) * (geo.sad - pz);
+                    double fx = floor((xs - F.f_x0) / F.f_pix);
+                    double fy = floor((ys - F.f_y0) / F.f_pix);
+                    if (!(fx >= 0.0 && fy >= 0.0 && fx < (double)F.nfx &&
+                          fy < (double)F.nfy))
+                        fl = 0.0;
+                    else
+                        fl = (double)F.fluence[(int64_t)fy * F.nfx +
+                                               (int64_t)fx];
+                    if (!(fl > 0.0)) status = 2;
+                }
+            }
+            if (status == 1) {
+                double wgt = (double)ps.wt[p] * fl * g[idx];
+                double rx = px - geo.iso[0], ry = py - geo.iso[1],
+                       rz = pz - geo.iso[2];
+                double qx = F.cos_g * rx + F.sin_g * rz + geo.iso[0];
+                double qy = ry + geo.iso[1];
+                double qz = -F.sin_g * rx + F.cos_g * rz + geo.iso[2];
+                double eu = F.cos_g * du + F.sin_g * dw;
+                double ev = dv;
+                double ew = -F.sin_g * du + F.cos_g * dw;
+                double pos[3] = {qx, qy, qz}, dir[3] = {eu, ev, ew};
+                double tn = -INFINITY, tf = INFINITY;
+                bool miss = false;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (dir[a] != 0.0) {
+                        double t1 = (geo.lo[a] - pos[a]) / dir[a];
+                        double t2 = (geo.hi[a] - pos[a]) / dir[a];
+                        double l = t1 < t2 ? t1 : t2, u = t1 < t2 ? t2 : t1;
+                        if (l > tn) tn = l;
+                        if (u < tf) tf = u;
+                    } else if (pos[a] < geo.lo[a] || pos[a] > geo.hi[a]) {
+                        miss = true;
+                    }
+                }
+                if (miss || tn > tf || tf <= 0.0) {
+                    status = 3;
+                } else {
+                    double t = tn > 0.0 ? tn : 0.0;
+                    oE = ps.E[p];
+                    ox = (float)(pos[0] + t * dir[0]);
+                    oy = (float)(pos[1] + t * dir[1]);
+                    oz = (float)(pos[2] + t * dir[2]);
+                    ou = (float)eu;
+                    ov = (float)ev;
+                    ow = (float)ew;
+                    owt = (float)wgt;
+                }
+            }
+        }
+        // queue selection: 0 photons, 1 + b electron bucket b
+        const bool acc = status == 1;
+        int which = 0;
+        if (acc && type != 0) {
+            int b = 0;
+            for (int j = 1; j < q.n_b; ++j)
+                if (oE >= s_edges[j]) b = j;
+            which = 1 + b;
+        }
+        uint32_t slot = wave_reserve(q.counts, which, acc);
+        bool lost = false;
+        if (acc) {
+            const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
+                                 (uint64_t)h0;
+            if (which == 0) {
+                push(q.ph, slot, oE, ox, oy, oz, ou, ov, ow, owt, uid, 0u);
+            } else if ((int64_t)slot < q.cap_b) {
+                push(q.el, (int64_t)(which - 1) * q.cap_b + slot, oE, ox, oy,
+                     oz, ou, ov, ow, owt, uid, kSourceElectronCtr);
+            } else {
+                lost = true;
+            }
+        }
+        wave_add_u64(&stats->histories, live ? 1 : 0);
+        wave_add_u64(&stats->jaw_rejected, status == 0 ? 1 : 0);
+        wave_add_u64(&stats->fluence_zero, status == 2 ? 1 : 0);
+        wave_add_u64(&stats->missed, status == 3 ? 1 : 0);
+        wave_add_u64(&stats->photons, acc && which == 0 ? 1 : 0);
+        wave_add_u64(&stats->electrons, acc && which != 0 && !lost ? 1 : 0);
+        wave_add_u64(&stats->lost, lost ? 1 : 0);
+        wave_add_f64(&stats->e_in, acc && !lost ? (double)oE * owt : 0.0);
+        if (lost) atomicAdd(&q.counts[PSL_QCOUNTS - 1], 1u);
+    }
+}
+
+struct SampleWs {
+    FieldDev *fields;
+    uint8_t *mask;
+    int64_t *C, *NF, *N, *H, *before, *T;
+    double *g, *mu_tot;
+    uint64_t *chunks, *h_total;
+    size_t bytes;
+};
+
+SampleWs carve_sample(void *base, int64_t n_keys, int P, int F) {
+    Carver c(base);
+    SampleWs w;
+    w.fields = c.take<FieldDev>(F);
+    w.mask = c.take<uint8_t>((int64_t)F * P);
+    w.C = c.take<int64_t>(F);
+    w.NF = c.take<int64_t>(F);
+    w.mu_tot = c.take<double>(1);
+    w.N = c.take<int64_t>((int64_t)F * n_keys);
+    w.g = c.take<double>((int64_t)F * n_keys);
+    w.H = c.take<int64_t>((int64_t)F * n_keys + 1);
+    w.before = c.take<int64_t>((int64_t)F * n_keys);
+    w.T = c.take<int64_t>(n_keys);
+    w.chunks = c.take<uint64_t>(scan_chunks((int64_t)F * n_keys + 1) + 1);
+    w.h_total = c.take<uint64_t>(1);
+    w.bytes = c.used;
+    return w;
+}
+
+psl_status validate_particles(const psl_particles &p, const char *name) {
+    PSL_REQUIRE(p.capacity >= 0, "%s capacity < 0", name);
+    if (p.capacity > 0)
+        PSL_REQUIRE(p.E && p.x && p.y && p.z && p.u && p.v && p.w && p.wt &&
+                        p.uid && p.ctr,
+                    "NULL array in %s", name);
+    return PSL_OK;
+}
+
+}  // namespace
+
+psl_status validate_queue(const psl_queue *q) {
+    PSL_REQUIRE(q && q->d_counts, "queue or its counts are NULL");
+    psl_status s;
+    if ((s = validate_particles(q->ph, "photon queue"))) return s;
+    if ((s = validate_particles(q->el, "electron queue"))) return s;
+    PSL_REQUIRE(q->n_ebuckets >= 1 && q->n_ebuckets <= PSL_MAX_QBUCKETS,
+                "n_ebuckets = %d outside 1..%d", q->n_ebuckets,
+                PSL_MAX_QBUCKETS);
+    for (int b = 0; b + 1 < q->n_ebuckets; ++b)
+        PSL_REQUIRE(q->e_bucket_edges[b] < q->e_bucket_edges[b + 1],
+                    "bucket edges not increasing at %d", b);
+    PSL_REQUIRE(q->ph.capacity < (int64_t)0xFFFFFFFF &&
+                    q->el.capacity / q->n_ebuckets < (int64_t)0xFFFFFFFF,
+                "queue capacity must stay below 2^32 per region");
+    return PSL_OK;
+}
+
+}  // namespace psl
+
+using namespace psl;
+
+extern "C" size_t psl_sample_workspace_bytes(const psl_grid *g,
+                                             int32_t n_fields) {
+    if (!g || n_fields < 1) return 0;
+    int64_t n_keys = 2LL * g->n_e * g->n_x * g->n_y;
+    return carve_sample(nullptr, n_keys, g->n_x * g->n_y, n_fields).bytes;
+}
+
+extern "C" psl_status psl_sample(const psl_phsp *sorted,
+                                 const int64_t *d_offsets, const psl_grid *g,
+                                 const psl_field *fields, int32_t n_fields,
+                                 const psl_sample_cfg *cfg, psl_queue *q,
+                                 uint8_t *d_mask, int64_t *d_alloc,
+                                 psl_stats *d_stats, void *d_ws,
+                                 size_t ws_bytes, void *stream) {
+    PSL_REQUIRE(sorted && d_offsets && fields && cfg && q && d_stats,
+                "NULL argument");
+    psl_status s = validate_grid_public(g);
+    if (s) return s;
+    if ((s = validate_queue(q))) return s;
+    PSL_REQUIRE(n_fields >= 1 && n_fields <= 4096, "n_fields = %d",
+                n_fields);
+    PSL_REQUIRE(sorted->n >= 1, "empty phase space");
+    PSL_REQUIRE(sorted->type && sorted->E && sorted->x && sorted->y &&
+                    sorted->u && sorted->v && sorted->w && sorted->wt,
+                "NULL phase-space array");
+    PSL_REQUIRE(cfg->batch >= 0, "batch < 0");
+    PSL_REQUIRE(cfg->n_histories >= 0 &&
+                    cfg->n_histories < (int64_t)0x7fffffff,
+                "n_histories = %lld outside 0 .. 2^31-2",
+                (long long)cfg->n_histories);
+    PSL_REQUIRE(cfg->alloc_mode == PSL_ALLOC_COUNTS ||
+                    cfg->alloc_mode == PSL_ALLOC_MU,
+                "alloc_mode = %d", cfg->alloc_mode);
+    PSL_REQUIRE(cfg->sad > 0, "sad must be positive");
+    bool any_jaws = false;
+    for (int i = 0; i < n_fields; ++i) any_jaws |= fields[i].jaws_on != 0;
+    PSL_REQUIRE(!any_jaws || (cfg->z_jaw_x < cfg->sad &&
+                              cfg->z_jaw_y < cfg->sad &&
+                              g->z_plane < cfg->z_jaw_x &&
+                              g->z_plane < cfg->z_jaw_y),
+                "fields with jaws need z_psl < z_jaw < sad");
+    for (int a = 0; a < 3; ++a)
+        PSL_REQUIRE(cfg->box_lo[a] < cfg->box_hi[a], "empty phantom box");
+    PSL_REQUIRE(q->ph.capacity >= cfg->n_histories,
+                "photon queue capacity %lld < n_histories %lld",
+                (long long)q->ph.capacity, (long long)cfg->n_histories);
+    // products N_i * S_k must stay in 64 bits
+    PSL_REQUIRE((unsigned __int128)cfg->n_histories * (uint64_t)sorted->n <
+                    ((unsigned __int128)1 << 63),
+                "n_histories * n_particles overflows 64 bits");
+    std::vector<FieldDev> fd(n_fields);
+    for (int i = 0; i < n_fields; ++i) {
+        const psl_field &f = fields[i];
+        PSL_REQUIRE(f.MU > 0, "field %d: MU <= 0", i);
+        PSL_REQUIRE(!f.jaws_on || (f.X1 <= f.X2 && f.Y1 <= f.Y2),
+                    "field %d: jaw X1 > X2 or Y1 > Y2", i);
+        PSL_REQUIRE(!f.fluence || (f.nfx > 0 && f.nfy > 0 && f.f_pix > 0),
+                    "field %d: bad fluence map", i);
+        double th = f.gantry_deg * (M_PI / 180.0);
+        fd[i] = FieldDev{f.X1, f.X2, f.Y1, f.Y2, std::cos(th), std::sin(th),
+                         f.MU, f.fluence, f.fluence ? f.nfx : 0,
+                         f.fluence ? f.nfy : 0, f.jaws_on ? 1 : 0, 0,
+                         f.f_x0, f.f_y0, f.f_pix};
+    }
+    const int64_t n_keys = 2LL * g->n_e * g->n_x * g->n_y;
+    const int P = g->n_x * g->n_y;
+    SampleWs need = carve_sample(nullptr, n_keys, P, n_fields);
+    if (!d_ws || ws_bytes < need.bytes) {
+        set_error("workspace %zu bytes < %zu required", ws_bytes, need.bytes);
+        return PSL_ENOSPC;
+    }
+    if ((s = check_device())) return s;
+    hipStream_t st = (hipStream_t)stream;
+    SampleWs w = carve_sample(d_ws, n_keys, P, n_fields);
+    uint8_t *mask = d_mask ? d_mask : w.mask;
+    int64_t *N = d_alloc ? d_alloc : w.N;
+    PSL_HIP(hipMemcpyAsync(w.fields, fd.data(), sizeof(FieldDev) * n_fields,
+                           hipMemcpyHostToDevice, st));
+    Geo geo{cfg->sad, cfg->z_jaw_x, cfg->z_jaw_y, g->z_plane,
+            {cfg->iso[0], cfg->iso[1], cfg->iso[2]},
+            {cfg->box_lo[0], cfg->box_lo[1], cfg->box_lo[2]},
+            {cfg->box_hi[0], cfg->box_hi[1], cfg->box_hi[2]}};
+    hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, d_stats,
+                       q->d_counts);
+    int64_t nm = (int64_t)n_fields * P;
+    hipLaunchKernelGGL(k_cull, dim3((unsigned)((nm + 255) / 256)), dim3(256),
+                       0, st, w.fields, n_fields, geo, *g, cfg->cull, mask);
+    hipLaunchKernelGGL(k_field_pop, dim3(n_fields), dim3(kAllocBlock), 0, st,
+                       d_offsets, n_keys, P, mask, w.C);
+    hipLaunchKernelGGL(k_field_totals, dim3(1), dim3(1), 0, st, w.fields,
+                       n_fields, w.C, cfg->alloc_mode, cfg->n_histories, w.NF,
+                       w.mu_tot);
+    hipLaunchKernelGGL(k_key_alloc, dim3(n_fields), dim3(kAllocBlock), 0, st,
+                       w.fields, d_offsets, n_keys, P, mask, w.C, w.NF,
+                       w.mu_tot, N, w.g);
+    hipLaunchKernelGGL(k_cursor, dim3((unsigned)((n_keys + 255) / 256)),
+                       dim3(256), 0, st, N, n_fields, n_keys, w.before, w.T);
+    const int64_t n_ranges = (int64_t)n_fields * n_keys;
+    if ((s = exclusive_scan<int64_t, int64_t>(N, w.H, n_ranges, w.chunks,
+                                              w.h_total, st)))
+        return s;
+    QueueDev qd{q->ph, q->el, q->n_ebuckets, q->el.capacity / q->n_ebuckets,
+                q->d_counts};
+    if (cfg->n_histories > 0) {
+        int cu = device_cu_count();
+        int64_t blocks = std::min<int64_t>((cfg->n_histories + 255) / 256,
+                                           (int64_t)cu * 16);
+        hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks), dim3(256), 0, st,
+                           *sorted, d_offsets, n_keys, w.fields, geo, w.H,
+                           n_ranges, w.h_total, w.before, w.T, w.g, cfg->seed,
+                           cfg->batch, qd, *q, d_stats);
+    }
+    PSL_LAUNCHED();
+    return PSL_OK;
+}

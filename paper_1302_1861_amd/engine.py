@@ -1,0 +1,218 @@
+"""Buffer management and call sequencing for one workload.
+
+``Engine`` owns the device buffers (torch tensors) of a workload and chains
+the C calls: psl_build once, then per batch psl_sample -> transport_batch ->
+dose_tally(FOLD), and dose_tally(FINALIZE) at the end.  No arithmetic of the
+method happens here.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import (PART_KEYS, PHSP_KEYS, PSL_ACC_F64, PSL_ACC_FIXED64,
+               PSL_ALLOC_COUNTS, PSL_MAX_QBUCKETS, PSL_QCOUNTS,
+               PSL_TABLE_BYTES, PSL_TALLY_FINALIZE, PSL_TALLY_FOLD, lib,
+               make_fields, make_grid, make_particles, make_phantom,
+               make_physics, make_phsp, psl_build, psl_dose_acc,
+               psl_launch, psl_physics_init, psl_queue, psl_sample,
+               psl_sample_cfg, psl_stats, dose_tally, transport_batch,
+               stats_to_dict)
+
+DEFAULT_BUCKET_EDGES = (0.0, 0.3, 0.5, 0.8, 1.2, 1.8, 2.6, 3.8)
+
+
+class Buffers:
+    """Device tensors of a particle SoA."""
+
+    @staticmethod
+    def phsp(n, device):
+        import torch
+        t = {"type": torch.zeros(max(n, 1), dtype=torch.uint8, device=device)}
+        for k in PHSP_KEYS[1:]:
+            t[k] = torch.zeros(max(n, 1), dtype=torch.float32, device=device)
+        return t
+
+    @staticmethod
+    def phsp_from_numpy(ps, device):
+        import torch
+        return {k: torch.from_numpy(np.ascontiguousarray(getattr(ps, k))).to(
+            device) for k in PHSP_KEYS}
+
+    @staticmethod
+    def particles(n, device):
+        import torch
+        t = {}
+        for k in PART_KEYS:
+            dt = torch.int64 if k == "uid" else (
+                torch.int32 if k == "ctr" else torch.float32)
+            t[k] = torch.zeros(max(n, 1), dtype=dt, device=device)
+        return t
+
+
+def _ws(nbytes, device):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8,
+                       device=device)
+
+
+class Engine:
+    """All buffers and calls for one workload on one GPU."""
+
+    def __init__(self, wl, device="cuda", histories_per_batch=None,
+                 n_ebuckets=8, bucket_edges=DEFAULT_BUCKET_EDGES,
+                 electron_factor=1.5, frac_bits=32, phys_flags=0,
+                 launch: Optional[psl_launch] = None, iso=(0.0, 0.0, 100.0),
+                 sad=100.0, z_jaw_x=37.0, z_jaw_y=28.0, seed=None):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.wl = wl
+        self.launch = launch
+        self.seed = wl.seed if seed is None else seed
+        lib()
+        # phase space and PSL build
+        ps = wl.phsp
+        self.n_phsp = ps.n
+        self.grid = make_grid(wl.grid.e_edges, wl.grid.x_edges,
+                              wl.grid.y_edges, wl.grid.z_plane)
+        self.n_keys = 2 * self.grid.n_e * self.grid.n_x * self.grid.n_y
+        raw = Buffers.phsp_from_numpy(ps, device)
+        self.sorted = Buffers.phsp(ps.n, device)
+        self.offsets = torch.zeros(self.n_keys + 1, dtype=torch.int64,
+                                   device=device)
+        self.n_dropped = torch.zeros(1, dtype=torch.int64, device=device)
+        from . import lib as _l
+        ws = _ws(_l().psl_build_workspace_bytes(ps.n, C.byref(self.grid)),
+                 device)
+        psl_build(raw, self.grid, self.sorted, self.offsets, self.n_dropped,
+                  ws)
+        del ws, raw
+        # fields
+        self.fluence = [None if f.fluence is None else
+                        torch.from_numpy(np.ascontiguousarray(
+                            f.fluence, np.float32)).to(device)
+                        for f in wl.fields]
+        self.fields = make_fields(wl.fields, self.fluence)
+        # phantom and physics
+        ph = wl.phantom
+        self.density = torch.from_numpy(
+            np.ascontiguousarray(ph.density, np.float32)).to(device)
+        self.phantom = make_phantom(self.density, ph.voxel, ph.origin,
+                                    float(ph.density.max()))
+        e_max = float(max(6.0, float(ps.E.max()) if ps.n else 6.0))
+        self.phys = make_physics(e_max=e_max, flags=phys_flags)
+        self.tables = torch.zeros(PSL_TABLE_BYTES, dtype=torch.uint8,
+                                  device=device)
+        psl_physics_init(self.phys, self.tables)
+        # batches and queues
+        self.batches = wl.batches
+        self.hpb = int(wl.histories // wl.batches if histories_per_batch is None
+                       else histories_per_batch)
+        self.cfg = psl_sample_cfg()
+        self.cfg.seed = self.seed
+        self.cfg.n_histories = self.hpb
+        self.cfg.cull = 1 if wl.cull else 0
+        self.cfg.alloc_mode = wl.alloc_mode
+        self.cfg.sad, self.cfg.z_jaw_x, self.cfg.z_jaw_y = sad, z_jaw_x, \
+            z_jaw_y
+        nz, ny, nx = ph.density.shape
+        lo = np.array(ph.origin, np.float64)
+        hi = lo + np.array([nx, ny, nz], np.float64) * np.array(ph.voxel)
+        for a in range(3):
+            self.cfg.iso[a] = iso[a]
+            self.cfg.box_lo[a] = lo[a]
+            self.cfg.box_hi[a] = hi[a]
+        self.n_ebuckets = n_ebuckets
+        per_bucket = int(math.ceil(electron_factor * self.hpb)) + 64
+        self.ph_buf = Buffers.particles(self.hpb, device)
+        self.el_buf = Buffers.particles(per_bucket * n_ebuckets, device)
+        self.counts = torch.zeros(PSL_QCOUNTS, dtype=torch.int32,
+                                  device=device)
+        self.queue = psl_queue()
+        self.queue.ph = make_particles(self.ph_buf)
+        self.queue.ph.capacity = self.hpb
+        self.queue.el = make_particles(self.el_buf)
+        self.queue.el.capacity = per_bucket * n_ebuckets
+        self.queue.n_ebuckets = n_ebuckets
+        edges = list(bucket_edges[:n_ebuckets]) + [1e30]
+        for i, e in enumerate(edges):
+            self.queue.e_bucket_edges[i] = e
+        self.queue.d_counts = self.counts.data_ptr()
+        # tallies
+        self.nvox = nx * ny * nz
+        self.acc_mode = PSL_ACC_FIXED64 if wl.fixed_point else PSL_ACC_F64
+        self.acc_t = torch.zeros(self.nvox, dtype=torch.int64 if
+                                 wl.fixed_point else torch.float64,
+                                 device=device)
+        self.acc = psl_dose_acc()
+        self.acc.mode = self.acc_mode
+        self.acc.frac_bits = frac_bits
+        self.acc.data = self.acc_t.data_ptr()
+        self.s1 = torch.zeros(self.nvox, dtype=torch.float64, device=device)
+        self.s2 = torch.zeros(self.nvox, dtype=torch.float64, device=device)
+        self.dose = torch.zeros(self.nvox, dtype=torch.float32, device=device)
+        self.sigma = torch.zeros(self.nvox, dtype=torch.float32,
+                                 device=device)
+        self.stats = torch.zeros(C.sizeof(psl_stats), dtype=torch.uint8,
+                                 device=device)
+        self.ws_sample = _ws(lib().psl_sample_workspace_bytes(
+            C.byref(self.grid), len(wl.fields)), device)
+        self.ws_transport = _ws(lib().transport_batch_workspace_bytes(
+            C.byref(self.queue)), device)
+        self.n_kept = None
+        self.folded = 0
+
+    # -------------------------------------------------------------------
+    def kept(self) -> int:
+        if self.n_kept is None:
+            self.n_kept = int(self.offsets[-1].item())
+        return self.n_kept
+
+    def sample(self, batch, mask=None, alloc=None):
+        self.cfg.batch = batch
+        psl_sample(self.sorted, self.offsets, self.grid, self.fields,
+                   self.cfg, self.queue, self.stats, self.ws_sample,
+                   mask=mask, alloc=alloc, n_sorted=self.kept())
+
+    def transport(self, batch):
+        transport_batch(self.queue, self.phantom, self.phys, self.tables,
+                        self.seed, self.acc, self.stats, self.ws_transport,
+                        self.launch)
+
+    def fold(self):
+        dose_tally(self.acc, self.s1, self.s2, PSL_TALLY_FOLD, 0,
+                   self.phantom)
+        self.folded += 1
+
+    def step(self, batch):
+        """One batch of the whole hot path: sample, transport, fold."""
+        self.sample(batch)
+        self.transport(batch)
+        self.fold()
+
+    def finalize(self, norm=None):
+        norm = 1.0 / self.n_phsp if norm is None else norm
+        dose_tally(None, self.s1, self.s2, PSL_TALLY_FINALIZE, self.folded,
+                   self.phantom, norm, self.dose, self.sigma)
+        return self.dose, self.sigma
+
+    def reset_tally(self):
+        self.s1.zero_()
+        self.s2.zero_()
+        self.acc_t.zero_()
+        self.folded = 0
+
+    def run(self, batches=None):
+        for b in range(batches or self.batches):
+            self.step(b)
+        return self.finalize()
+
+    def stats_dict(self):
+        return stats_to_dict(self.stats)
+
+    def queue_counts(self):
+        return self.counts.cpu().numpy().view(np.uint32).copy()

@@ -1,0 +1,264 @@
+"""GPU transport and tally: closed forms, energy conservation,
+reproducibility, and statistical parity of the dose with the oracle."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import psl_synth as S
+from oracle import analysis
+from gpu_util import phase_space_arrays
+
+pytestmark = pytest.mark.gpu
+
+ME = 0.51099895
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _engine(wl, hpb, **kw):
+    import paper_1302_1861_amd as P
+    return P.Engine(wl, histories_per_batch=hpb, **kw)
+
+
+def _wl(ps, grid, phantom, fields, hist, batches, fixed=True, cull=False,
+        mode=0, seed=77, name="custom"):
+    return S.Workload(name, ps, grid, phantom, fields, hist, batches, fixed,
+                      cull, mode, seed)
+
+
+def _single_bin_grid(ps, half=20.0):
+    return S.Grid(S.linear_edges(0.0, float(ps.E.max()) * 1.001 + 1e-3, 1),
+                  S.linear_edges(-half, half, 1),
+                  S.linear_edges(-half, half, 1), ps.z_plane)
+
+
+# ------------------------------------------------------------- tally ------
+def test_fold_and_finalize_match_numpy():
+    import torch
+    import paper_1302_1861_amd as P
+    rng = np.random.default_rng(1)
+    shape = (7, 9, 11)
+    rho = rng.uniform(0.2, 2.0, shape).astype(np.float32)
+    rho[0, 0, :3] = 0.0
+    rho_t = torch.from_numpy(rho).cuda()
+    ph = P.make_phantom(rho_t, (0.3, 0.4, 0.5), (0, 0, 0), 2.0)
+    n = rho.size
+    s1 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s1)
+    B = 6
+    frac = 32
+    ref1 = np.zeros(n)
+    ref2 = np.zeros(n)
+    for b in range(B):
+        a = rng.integers(0, 2**50, n).astype(np.int64)
+        acc_t = torch.from_numpy(a).cuda()
+        acc = P.psl_dose_acc()
+        acc.mode, acc.frac_bits, acc.data = P.PSL_ACC_FIXED64, frac, \
+            acc_t.data_ptr()
+        P.dose_tally(acc, s1, s2, P.PSL_TALLY_FOLD, 0, ph)
+        torch.cuda.synchronize()
+        assert int(acc_t.abs().sum().item()) == 0
+        x = a.astype(np.float64) * 2.0 ** -frac
+        ref1 += x
+        ref2 += x * x
+    np.testing.assert_allclose(s1.cpu().numpy(), ref1, rtol=1e-15)
+    np.testing.assert_allclose(s2.cpu().numpy(), ref2, rtol=1e-14)
+    dose = torch.zeros(n, dtype=torch.float32, device="cuda")
+    sig = torch.zeros_like(dose)
+    P.dose_tally(None, s1, s2, P.PSL_TALLY_FINALIZE, B, ph, 1e-3, dose, sig)
+    torch.cuda.synchronize()
+    phantom = S.Phantom(rho, (0.3, 0.4, 0.5), (0, 0, 0))
+    wd, ws = oracle.finalize(ref1, ref2, B, phantom, 1e-3)
+    np.testing.assert_allclose(dose.cpu().numpy(), wd, rtol=1e-6, atol=0)
+    np.testing.assert_allclose(sig.cpu().numpy(), ws, rtol=1e-5, atol=1e-30)
+
+
+# ------------------------------------------------- closed-form transport --
+def test_first_collision_dose_closed_form():
+    """Broad parallel 1.25 MeV beam over the whole face of a water block,
+    first collision only, recoil energy deposited on the spot: layer sums
+    follow N E (sigma_tr/sigma) (exp(-mu z_j) - exp(-mu z_j+1))."""
+    from scipy import integrate
+    E = 1.25
+    n = 400_000
+    rng = np.random.default_rng(4)
+    x = rng.uniform(-4, 4, n)
+    y = rng.uniform(-4, 4, n)
+    ps = phase_space_arrays(np.zeros(n), np.full(n, E), x, y, np.zeros(n),
+                            np.zeros(n), np.ones(n), 100.0)
+    ph = S.water_phantom((8, 8, 20), 1.0, (-4.0, -4.0, 100.0))
+    f = S.Field(-4, 4, -4, 4, jaws=False)
+    wl = _wl(ps, _single_bin_grid(ps, 4.0), ph, [f], n * 2, 2, fixed=False)
+    import paper_1302_1861_amd as P
+    eng = _engine(wl, n, phys_flags=P.PSL_FLAG_FIRST_COLLISION)
+    eng.step(0)
+    import torch
+    torch.cuda.synchronize()
+    st = eng.stats_dict()
+    assert st["histories"] == n and st["photons"] == n
+    acc = eng.s1.cpu().numpy()
+    layer = acc.reshape(20, 8, 8).sum((1, 2))
+    mu = 3.343e23 * oracle.kn_sigma(E)
+
+    def dsig(c):
+        Pr = 1.0 / (1.0 + E / ME * (1.0 - c))
+        return Pr * Pr * (Pr + 1.0 / Pr - (1.0 - c * c))
+    tr = integrate.quad(lambda c: dsig(c) * (1 - 1 / (1 + E / ME * (1 - c))),
+                        -1, 1)[0] / integrate.quad(dsig, -1, 1)[0]
+    z = np.arange(21.0)
+    # weight g = n_k / N_k = 1 (one history per particle)
+    want = n * E * tr * (np.exp(-mu * z[:-1]) - np.exp(-mu * z[1:]))
+    sd = np.sqrt(want * E)
+    _say("layers", layer[:4], want[:4])
+    assert np.all(np.abs(layer - want) < 5 * sd)
+    # energy: deposited + escaped + killed scattered photons = incident
+    tot = acc.sum() + st["e_escaped"] + st["e_killed"]
+    assert tot == pytest.approx(n * E, rel=1e-5)
+
+
+def test_electron_pencil_depth_staircase_no_scattering():
+    """A 2 MeV electron pencil beam without scattering deposits the
+    deterministic CSDA staircase of the oracle."""
+    n = 1000
+    T0 = 2.0
+    ps = phase_space_arrays(np.ones(n), np.full(n, T0), np.full(n, 1e-4),
+                            np.full(n, 1e-4), np.zeros(n), np.zeros(n),
+                            np.ones(n), 100.0)
+    dz = 0.05
+    ph = S.water_phantom((3, 3, 400), dz, (-0.075, -0.075, 100.0))
+    wl = _wl(ps, _single_bin_grid(ps, 1.0), ph,
+             [S.Field(-1, 1, -1, 1, jaws=False)], n * 2, 2, fixed=False)
+    import paper_1302_1861_amd as P
+    import torch
+    eng = _engine(wl, n, phys_flags=P.PSL_FLAG_NO_MSC)
+    eng.step(0)
+    torch.cuda.synchronize()
+    dep = eng.s1.cpu().numpy().reshape(400, 3, 3)[:, 1, 1] / n
+    st = np.zeros((1, 8))
+    st[0] = [T0, 1e-4, 1e-4, 100.0, 0, 0, 1, 1]
+    acc, _, _, _ = oracle.transport(np.ones(1, np.uint8), st,
+                                    np.zeros(1, np.uint64), 1, ph,
+                                    oracle.ophys(flags=oracle.FLAG_NO_MSC))
+    want = acc.reshape(400, 3, 3)[:, 1, 1]
+    last = int(np.nonzero(want)[0].max())
+    assert int(np.nonzero(dep > 1e-9)[0].max()) in (last - 1, last, last + 1)
+    np.testing.assert_allclose(dep[:last - 1], want[:last - 1], rtol=5e-3)
+    assert dep.sum() == pytest.approx(T0, rel=1e-5)
+
+
+# ---------------------------------------- conservation / reproducibility --
+def test_energy_conservation_heterogeneous():
+    wl = S.workload_heterogeneous(n_particles=500_000, shape=(64, 64, 40),
+                                  voxel=0.8)
+    import torch
+    eng = _engine(wl, 400_000)
+    eng.sample(0)
+    eng.transport(0)
+    torch.cuda.synchronize()
+    st = eng.stats_dict()
+    dep = eng.acc_t.cpu().numpy().astype(np.float64).sum() * 2.0 ** -32
+    _say("conservation", st, dep)
+    assert st["lost"] == 0 and st["runaway"] == 0
+    assert dep + st["e_escaped"] == pytest.approx(st["e_in"], rel=1e-5)
+    assert st["interactions"] > 0 and st["segments"] > 0
+
+
+def test_fixed_point_dose_independent_of_launch_shape():
+    import torch
+    import paper_1302_1861_amd as P
+    wl = S.workload_clinical(side=10.0, n_particles=500_000)
+    wl.phantom = S.water_phantom((64, 64, 64), 0.5, (-16.0, -16.0, 100.0))
+    out = []
+    for bpc in (1, 8, 3):
+        L = P.psl_launch()
+        L.block, L.blocks_per_cu, L.n_cu = 256, bpc, 0
+        eng = _engine(wl, 300_000, launch=L)
+        eng.sample(4)
+        eng.transport(4)
+        torch.cuda.synchronize()
+        out.append(eng.acc_t.cpu().numpy().copy())
+    assert out[0].any()
+    for o in out[1:]:
+        assert np.array_equal(o, out[0])
+
+
+# ------------------------------------------------ statistical parity -----
+def _parity(wl, hist, batches, threads=0, check_gamma=False):
+    import torch
+    eng = _engine(wl, hist // batches)
+    for b in range(batches):
+        eng.step(b)
+    d_g, s_g = eng.finalize()
+    torch.cuda.synchronize()
+    d_g = d_g.cpu().numpy().astype(np.float64)
+    s_g = s_g.cpu().numpy().astype(np.float64)
+    d_o, s_o, info = oracle.run_dose(wl, n_threads=threads, histories=hist,
+                                     batches=batches)
+    z = analysis.zscore_stats(d_g, s_g, d_o, s_o, ref_for_threshold=d_o)
+    _say(wl.name, "z", z)
+    assert z["frac_le3"] >= 0.99
+    assert abs(z["mean"]) < 0.1
+    assert 0.85 < z["sd"] < 1.15
+    return d_g, s_g, d_o, s_o
+
+
+def test_dose_parity_tiny_water():
+    wl = S.workload_tiny()
+    d_g, s_g, d_o, s_o = _parity(wl, 2_000_000, 10)
+    # depth dose on the central 4x4 voxel columns, low noise
+    shp = wl.phantom.density.shape
+    g = d_g.reshape(shp)[:, 28:32, 28:32].sum((1, 2))
+    o = d_o.reshape(shp)[:, 28:32, 28:32].sum((1, 2))
+    sg = np.sqrt((s_g.reshape(shp)[:, 28:32, 28:32] ** 2).sum((1, 2)))
+    so = np.sqrt((s_o.reshape(shp)[:, 28:32, 28:32] ** 2).sum((1, 2)))
+    zz = (g - o) / np.sqrt(sg ** 2 + so ** 2)
+    _say("pdd z", np.round(zz, 2))
+    assert np.all(np.abs(zz) < 4)
+
+
+def test_dose_parity_heterogeneous_jaws_fluence():
+    wl = S.workload_heterogeneous(n_particles=1_000_000, shape=(40, 40, 40),
+                                  voxel=0.8)
+    _parity(wl, 2_000_000, 10)
+
+
+def test_dose_parity_imrt_rotated_segments():
+    wl = S.workload_imrt(n_particles=1_000_000)
+    wl.phantom = S.water_phantom((40, 40, 40), 0.8, (-16.0, -16.0, 84.0))
+    _parity(wl, 2_000_000, 10)
+
+
+@pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN,
+                                                    "oracle_dose_tiny.npz")),
+                    reason="high-statistics oracle reference not generated")
+def test_dose_gamma_against_high_statistics_oracle():
+    """Gamma 2%/2mm >= 99% above the 10% isodose and per-voxel agreement
+    within 3 sigma against the oracle's high-statistics dose."""
+    import torch
+    ref = np.load(os.path.join(GOLDEN, "oracle_dose_tiny.npz"))
+    hist = int(ref["histories"])
+    wl = S.workload_tiny()
+    eng = _engine(wl, hist // 10)
+    for b in range(10):
+        eng.step(b)
+    d_g, s_g = eng.finalize()
+    torch.cuda.synchronize()
+    shp = wl.phantom.density.shape
+    d_g = d_g.cpu().numpy().astype(np.float64).reshape(shp)
+    s_g = s_g.cpu().numpy().astype(np.float64).reshape(shp)
+    d_o = ref["dose"].astype(np.float64).reshape(shp)
+    s_o = ref["sigma"].astype(np.float64).reshape(shp)
+    z = analysis.zscore_stats(d_g, s_g, d_o, s_o, ref_for_threshold=d_o)
+    _say("golden z", z)
+    assert z["frac_le3"] >= 0.99 and abs(z["mean"]) < 0.1
+    rate = analysis.gamma_pass_rate(d_o, d_g, 0.5, dose_crit=0.02, dta=0.2,
+                                    threshold=0.1)
+    _say("gamma 2%/2mm", rate)
+    assert rate >= 0.99
