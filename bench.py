@@ -1,0 +1,200 @@
+#!/usr/bin/env python
+"""Throughput of the PSL Monte Carlo dose path on one MI355X.
+
+Workload: the PSL method at clinical scale -- a seeded synthetic 1e7-particle
+linac-like phase space (97% photons, triangular 0.1-6 MeV spectrum, 1 mm
+Gaussian source, aimed over 40x40 cm at the SAD plane) pre-sorted into
+2 x 32 log energy bins x 22 x 22 position bins of 5 mm at the PSL plane; a
+square open field (10x10 cm by default) with ROI culling and the jaw model;
+a 128^3 water phantom of 2.5 mm voxels at SSD 100 cm; 1e8 histories per
+field in 10 batches of 1e7; FP32 transport, 64-bit fixed-point dose atomics.
+
+One step = one batch of 1e7 histories through the whole hot path: ROI
+selection and allocation, sampling, photon and electron transport, and the
+fold of the batch tally (psl_sample -> transport_batch -> dose_tally).  The
+PSL build is a commissioning step done once, before timing.  Inputs are
+resident in HBM before the timed region starts.
+
+Prints one JSON line.  `value` is histories/s of the timed steps.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _algorithmic_bytes(group, st, nvox):
+    """Algorithmic HBM bytes of one launch of a kernel group, from the
+    batch statistics (definitions in the design notes)."""
+    q = 44  # queue entry: E x y z u v w wt (32) + uid (8) + ctr (4)
+    if group == "electrons":
+        n_el = st["electrons"] + st["secondaries"]
+        return q * n_el + 16 * st["deposits"] + 4 * st["segments"]
+    if group == "photons":
+        return (q * st["photons"] + 4 * st["flights"] + q * st["secondaries"]
+                + 16 * st["photon_deposits"])
+    if group == "sample":
+        acc = st["photons"] + st["electrons"]
+        return 29 * st["histories"] + q * acc
+    if group == "fold":
+        return 48 * nvox
+    return None
+
+
+def cpu_baseline(wl, hist_target_s, threads):
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    PSL build (untimed), then batches of sampling + transport + fold."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    perm, off, nd = oracle.build_psl(wl.phsp, wl.grid)
+    sps = wl.phsp.subset(perm)
+    geom = oracle.geometry(wl.phantom, z_psl=wl.grid.z_plane)
+    mask = oracle.cull(wl.fields, wl.grid, wl.cull, geom)
+    nvox = wl.phantom.density.size
+    s1 = np.zeros(nvox)
+    s2 = np.zeros(nvox)
+
+    def batch(b, H):
+        N, g, _ = oracle.alloc(wl.fields, wl.alloc_mode, H, off, mask,
+                               wl.grid)
+        S_ = oracle.sample(wl.fields, geom, off, N, g, b, wl.seed, sps)
+        ok = S_["status"] == 1
+        acc, _, _, _ = oracle.transport(S_["type"][ok], S_["state"][ok],
+                                        S_["uid"][ok], wl.seed, wl.phantom,
+                                        n_threads=threads)
+        oracle.fold(acc, s1, s2)
+
+    t0 = time.perf_counter()
+    batch(0, 20_000)
+    dt = time.perf_counter() - t0
+    rate0 = 20_000 / max(dt, 1e-6)
+    H = int(min(max(rate0 * hist_target_s, 20_000), 5_000_000))
+    t0 = time.perf_counter()
+    batch(1, H)
+    dt = time.perf_counter() - t0
+    return {"value": H / dt, "unit": "histories/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d histories of the same workload in one batch "
+                      "(sampling + transport + fold, %.1f s, PSL build "
+                      "excluded)" % (H, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--field", type=float, default=10.0)
+    ap.add_argument("--histories-per-step", type=int, default=10_000_000)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU "
+              "path (histories would shard across GPUs with one all-reduce "
+              "of the fixed-point dose; not implemented). Use --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import psl_synth as S
+    import paper_1302_1861_amd as P
+
+    wl = S.workload_clinical(side=args.field)
+    H = args.histories_per_step
+    eng = P.Engine(wl, histories_per_batch=H)
+    torch.cuda.synchronize()
+    for b in range(args.warmup):
+        eng.step(b)
+    torch.cuda.synchronize()
+    eng.reset_tally()
+    P.profile_read(reset=True)
+    P.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        eng.step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.profile_enable(False)
+    prof = P.profile_read(reset=True)
+    st = eng.stats_dict()
+    counts = eng.queue_counts()
+    if st["lost"]:
+        raise SystemExit("queue overflow: batch invalid")
+
+    value = args.steps * H / elapsed
+    ms = 1000.0 * elapsed / args.steps
+    # dominant kernel and its HBM roofline
+    groups = {g: v for g, v in prof.items() if v[1] > 0}
+    dom = max(groups, key=lambda g: groups[g][0])
+    avg_ms = groups[dom][0] / groups[dom][1]
+    nbytes = _algorithmic_bytes(dom, st, eng.nvox)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    kernel_ms = {g: round(v[0] / v[1], 4) for g, v in groups.items()}
+
+    # time to 1% uncertainty from the timed steps (batches)
+    d, s = eng.finalize()
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    s = s.cpu().numpy()
+    sel = d >= 0.5 * d.max()
+    sbar = float((s[sel] / d[sel]).mean())
+    t1 = elapsed * (sbar / 0.01) ** 2
+
+    out = {
+        "metric": "MC histories/sec on 1 GPU",
+        "value": value,
+        "unit": "histories/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "PSL clinical scale: 1e7-particle phase space,"
+                               " %gx%g cm open field, 128^3 water at 2.5 mm, "
+                               "1e7 histories per step" % (args.field,
+                                                           args.field),
+                   "histories_per_step": H, "phase_space": wl.phsp.n,
+                   "psl_grid": "2x32x22x22", "phantom": "128^3 x 2.5 mm",
+                   "tally": "u64 fixed point 2^-32 MeV",
+                   "parallelism": "single GPU"},
+        "roofline": {"kernel": dom, "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None,
+                     "algorithmic_bytes_per_launch": nbytes,
+                     "avg_launch_ms": avg_ms},
+        "kernel_ms": kernel_ms,
+        "batch_stats": {k: st[k] for k in (
+            "histories", "photons", "electrons", "jaw_rejected",
+            "interactions", "secondaries", "segments", "deposits",
+            "photon_deposits", "flights")},
+        "time_to_1pct_s": t1,
+        "mean_rel_sigma_50pct": sbar,
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or \
+            min(16, os.cpu_count() or 1)
+        wl_cpu = S.workload_clinical(side=args.field)
+        out["cpu_baseline"] = cpu_baseline(wl_cpu, args.cpu_seconds, threads)
+        out["cpu_baseline"]["gpu_over_cpu"] = value / \
+            out["cpu_baseline"]["value"]
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

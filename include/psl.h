@@ -164,9 +164,12 @@ typedef struct psl_stats {
     uint64_t segments;          /* electron voxel segments                   */
     uint64_t flights;           /* photon free flights (real + virtual)      */
     uint64_t runaway;           /* particles stopped by the loop guard       */
+    uint64_t deposits;          /* dose atomics issued by electrons          */
+    uint64_t photon_deposits;   /* dose atomics issued by photons            */
     double e_in;                /* sum E*wt of queued source particles       */
     double e_escaped;           /* sum E*wt leaving the phantom              */
-    double reserved[2];
+    double e_killed;            /* sum E*wt of photons ended by              */
+                                /* PSL_FLAG_FIRST_COLLISION                  */
 } psl_stats;
 
 /*
@@ -195,11 +198,16 @@ typedef struct psl_stats {
  *   d_mask (optional, device uint8 [n_fields][n_y*n_x]) receives the ROI
  *   selection; d_alloc (optional, device int64 [n_fields][n_keys])
  *   receives N_ik.  d_stats (device) is zeroed and filled.
+ * Accepted particles are first written to per-history slots and then
+ * compacted into the queues in history order (no contended atomics), so
+ * queue contents and order are deterministic.
  * Errors: PSL_EINVAL (sizes, jaws X1 > X2, MU <= 0, z_jaw >= sad, ...),
- * PSL_ENOSPC if the workspace is too small or the photon queue cannot hold
- * n_histories entries.
+ * PSL_ENOSPC if the workspace is too small (psl_sample_workspace_bytes for
+ * the same grid, field count and n_histories) or the photon queue cannot
+ * hold n_histories entries.
  */
-size_t psl_sample_workspace_bytes(const psl_grid *g, int32_t n_fields);
+size_t psl_sample_workspace_bytes(const psl_grid *g, int32_t n_fields,
+                                  int64_t n_histories);
 psl_status psl_sample(const psl_phsp *sorted, const int64_t *d_offsets,
                       const psl_grid *g, const psl_field *fields,
                       int32_t n_fields, const psl_sample_cfg *cfg,
@@ -313,6 +321,30 @@ psl_status dose_tally(psl_dose_acc *acc, double *d_s1, double *d_s2,
                       int32_t op, int32_t n_batches, const psl_phantom *ph,
                       double norm, float *d_dose, float *d_sigma,
                       void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Kernel timing for benchmarks.                                             */
+/* ------------------------------------------------------------------------ */
+#define PSL_PROF_BUILD 0        /* psl_build: all kernels                    */
+#define PSL_PROF_SAMPLE 1       /* psl_sample: the per-history kernel        */
+#define PSL_PROF_ALLOC 2        /* psl_sample: cull, allocation, scans       */
+#define PSL_PROF_PHOTONS 3      /* transport_batch: photon kernel            */
+#define PSL_PROF_ELECTRONS 4    /* transport_batch: electron kernel          */
+#define PSL_PROF_FOLD 5         /* dose_tally: fold                          */
+#define PSL_PROF_FINALIZE 6     /* dose_tally: finalize                      */
+#define PSL_PROF_REBUCKET 7     /* transport_batch: secondary re-bucketing   */
+#define PSL_PROF_N 8
+
+/*
+ * psl_profile_enable - while on, the calls above bracket the kernels of each
+ * PSL_PROF_* group with hipEvents recorded on the call's own stream.
+ * psl_profile_read waits for the recorded events, returns the accumulated
+ * milliseconds and launch counts per group (arrays of PSL_PROF_N, either may
+ * be NULL) and, if reset != 0, clears them.  Host-side state shared by all
+ * threads; not meant for concurrent use.
+ */
+psl_status psl_profile_enable(int32_t on);
+psl_status psl_profile_read(double *ms, int64_t *launches, int32_t reset);
 
 #ifdef __cplusplus
 }

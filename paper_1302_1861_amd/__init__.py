@@ -34,7 +34,8 @@ PSL_FLAG_FIRST_COLLISION, PSL_FLAG_NO_MSC = 1, 2
 EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_build", "psl_sample_workspace_bytes", "psl_sample",
            "psl_physics_init", "transport_batch_workspace_bytes",
-           "transport_batch", "dose_tally"]
+           "transport_batch", "dose_tally", "psl_profile_enable",
+           "psl_profile_read"]
 
 
 class PslError(RuntimeError):
@@ -91,13 +92,14 @@ class psl_queue(C.Structure):
 
 STATS_FIELDS = ["histories", "jaw_rejected", "fluence_zero", "missed",
                 "photons", "electrons", "lost", "interactions", "secondaries",
-                "segments", "flights", "runaway"]
+                "segments", "flights", "runaway", "deposits",
+                "photon_deposits"]
 
 
 class psl_stats(C.Structure):
     _fields_ = [(k, C.c_uint64) for k in STATS_FIELDS] + \
         [("e_in", C.c_double), ("e_escaped", C.c_double),
-         ("reserved", C.c_double * 2)]
+         ("e_killed", C.c_double)]
 
 
 class psl_phantom(C.Structure):
@@ -148,7 +150,7 @@ def lib():
         L.psl_build_workspace_bytes.restype = sz
         L.psl_build.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
         L.psl_build.restype = i32
-        L.psl_sample_workspace_bytes.argtypes = [vp, i32]
+        L.psl_sample_workspace_bytes.argtypes = [vp, i32, i64]
         L.psl_sample_workspace_bytes.restype = sz
         L.psl_sample.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
                                  sz, vp]
@@ -162,6 +164,10 @@ def lib():
         L.transport_batch.restype = i32
         L.dose_tally.argtypes = [vp, vp, vp, i32, i32, vp, d, vp, vp, vp]
         L.dose_tally.restype = i32
+        L.psl_profile_enable.argtypes = [i32]
+        L.psl_profile_enable.restype = i32
+        L.psl_profile_read.argtypes = [vp, vp, i32]
+        L.psl_profile_read.restype = i32
         _lib = L
     return _lib
 
@@ -305,9 +311,25 @@ def stats_to_dict(stats_t) -> Dict:
     raw = stats_t.cpu().numpy().tobytes()
     s = psl_stats.from_buffer_copy(raw[:C.sizeof(psl_stats)])
     d = {k: int(getattr(s, k)) for k in STATS_FIELDS}
-    d["e_in"], d["e_escaped"] = s.e_in, s.e_escaped
-    d["e_killed"] = s.reserved[0]
+    d["e_in"], d["e_escaped"], d["e_killed"] = s.e_in, s.e_escaped, \
+        s.e_killed
     return d
+
+
+PROF_GROUPS = ["build", "sample", "alloc", "photons", "electrons", "fold",
+               "finalize", "rebucket"]
+
+
+def profile_enable(on=True):
+    _check(lib().psl_profile_enable(1 if on else 0))
+
+
+def profile_read(reset=True):
+    """{group: (milliseconds, launches)} accumulated while profiling."""
+    ms = (C.c_double * 8)()
+    n = (C.c_int64 * 8)()
+    _check(lib().psl_profile_read(ms, n, 1 if reset else 0))
+    return {g: (ms[i], n[i]) for i, g in enumerate(PROF_GROUPS)}
 
 
 from .engine import Engine, Buffers  # noqa: E402,F401

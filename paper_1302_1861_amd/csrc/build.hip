@@ -240,6 +240,7 @@ extern "C" psl_status psl_build(const psl_phsp *in, const psl_grid *g,
     hipStream_t st = (hipStream_t)stream;
     BuildWs w = carve_build(d_ws, n, n_keys);
     const int cu = device_cu_count();
+    ProfScope prof(PSL_PROF_BUILD, st);
 
     hipLaunchKernelGGL(k_fill_u32, dim3(64), dim3(256), 0, st, w.hist,
                        n_keys + 1, 0u);

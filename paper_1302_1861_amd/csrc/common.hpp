@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstddef>
 #include <cstdint>
 #include <cstdio>
 #include <string>
@@ -16,6 +17,21 @@ namespace psl {
 void set_error(const char *fmt, ...);
 psl_status check_device();          // PSL_EUNSUPPORTED unless gfx950
 int device_cu_count();
+
+// Brackets the launches in its scope with hipEvents when profiling is on.
+class ProfScope {
+  public:
+    ProfScope(int group, hipStream_t st);
+    ~ProfScope();
+    ProfScope(const ProfScope &) = delete;
+    ProfScope &operator=(const ProfScope &) = delete;
+
+  private:
+    int group_;
+    hipStream_t st_;
+    hipEvent_t a_{}, b_{};
+    bool active_ = false;
+};
 
 #define PSL_REQUIRE(cond, ...)                                                \
     do {                                                                      \
@@ -178,5 +194,87 @@ constexpr int kTabRange = 2048;
 constexpr int kTabInv = 4096;
 constexpr size_t kTabHeaderBytes = 256;
 // floats after the header: mu[kTabMu], range[kTabRange], inv[kTabInv]
+
+}  // namespace psl
+
+namespace psl {
+
+// --------------------------------------------------------- block stats ----
+// psl_stats as words: counters first, then doubles.
+constexpr int kStatWords = (int)(sizeof(psl_stats) / 8);
+constexpr int kStatFirstDouble = (int)(offsetof(psl_stats, e_in) / 8);
+
+// Per-thread statistics, reduced per block into a partial record (plain
+// stores) and summed by k_stats_reduce: no contended atomics.
+struct StatAcc {
+    uint64_t w[kStatWords];
+    __device__ void zero() {
+#pragma unroll
+        for (int i = 0; i < kStatWords; ++i) w[i] = 0;
+    }
+    __device__ void add(int word, uint64_t v) { w[word] += v; }
+    __device__ void addf(int word, double v) {
+        w[word] = __double_as_longlong(__longlong_as_double(w[word]) + v);
+    }
+};
+
+#define PSL_STAT(field) ((int)(offsetof(psl_stats, field) / 8))
+
+// Block reduction of StatAcc into part[blockIdx.x * kStatWords + i].  All
+// threads of the block must call it; s_red: LDS of (blockDim/64) *
+// kStatWords words.
+__device__ __forceinline__ void block_stats_write(StatAcc &a, uint64_t *s_red,
+                                                  uint64_t *part) {
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int i = 0; i < kStatWords; ++i) {
+        uint64_t v = a.w[i];
+        if (i < kStatFirstDouble) {
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        } else {
+            double d = __longlong_as_double(v);
+            for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o);
+            v = __double_as_longlong(d);
+        }
+        if (lane == 0) s_red[wid * kStatWords + i] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kStatWords) {
+        const int i = threadIdx.x;
+        uint64_t v = 0;
+        double d = 0.0;
+        for (int w = 0; w < nw; ++w) {
+            if (i < kStatFirstDouble) v += s_red[w * kStatWords + i];
+            else d += __longlong_as_double(s_red[w * kStatWords + i]);
+        }
+        part[(int64_t)blockIdx.x * kStatWords + i] =
+            i < kStatFirstDouble ? v : (uint64_t)__double_as_longlong(d);
+    }
+}
+
+// Adds the per-block partial records part[n_blocks][kStatWords] to *out.
+psl_status stats_reduce(const uint64_t *part, int n_blocks, psl_stats *out,
+                        hipStream_t st);
+
+// --------------------------------------------------- work distribution ----
+// Chunks of 64 items are claimed from kParts counters on separate cache
+// lines; a wave starts at its own partition and moves on when it is empty.
+constexpr int kParts = 64;
+constexpr int kPartStride = 32;   // uint32 per counter (128 bytes)
+
+__device__ __forceinline__ int64_t claim_chunk(uint32_t *ctr, int64_t n_chunks,
+                                               int &part, int &tried) {
+    while (tried < kParts) {
+        uint32_t k = 0;
+        if (__lane_id() == 0) k = atomicAdd(&ctr[part * kPartStride], 1u);
+        k = __shfl(k, 0);
+        int64_t chunk = part + (int64_t)k * kParts;
+        if (chunk < n_chunks) return chunk;
+        part = (part + 1) % kParts;
+        ++tried;
+    }
+    return -1;
+}
 
 }  // namespace psl

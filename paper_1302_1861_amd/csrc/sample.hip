@@ -13,9 +13,11 @@
 // phantom) are taken in double precision with floating-point contraction
 // disabled, so they are reproducible operation by operation.
 #include "common.hpp"
+#include "compact.hpp"
 #include "scan.hpp"
 
 #include <cmath>
+#include <memory>
 #include <vector>
 
 namespace psl {
@@ -191,55 +193,35 @@ __global__ void k_cursor(const int64_t *__restrict__ N, int n_fields,
     T[k] = run;
 }
 
-struct QueueDev {
-    psl_particles ph, el;
-    int32_t n_b;
-    int64_t cap_b;
-    uint32_t *counts;
-};
-
-__device__ __forceinline__ void push(const psl_particles &P, int64_t slot,
-                                     float E, float x, float y, float z,
-                                     float u, float v, float w, float wt,
-                                     uint64_t uid, uint32_t ctr) {
-    P.E[slot] = E;
-    P.x[slot] = x;
-    P.y[slot] = y;
-    P.z[slot] = z;
-    P.u[slot] = u;
-    P.v[slot] = v;
-    P.w[slot] = w;
-    P.wt[slot] = wt;
-    P.uid[slot] = uid;
-    P.ctr[slot] = ctr;
-}
-
 constexpr uint32_t kSourceElectronCtr = 0xFFFFFFFFu;
+constexpr int kSampleBlock = 256;
 
-__global__ void __launch_bounds__(256)
+// One thread per history: read the particle from its PSL, apply the jaw
+// model, the fluence weight and g_ik, rotate by the gantry and move it to
+// the phantom; write the result into slot h with its queue code.
+__global__ void __launch_bounds__(kSampleBlock)
 k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
          const FieldDev *__restrict__ fields, Geo geo,
          const int64_t *__restrict__ H, int64_t n_ranges,
          const uint64_t *__restrict__ h_total_p,
          const int64_t *__restrict__ before, const int64_t *__restrict__ T,
          const double *__restrict__ g, uint64_t seed, int64_t batch,
-         QueueDev q, psl_queue qcfg, psl_stats *__restrict__ stats) {
+         Slots slots, int64_t n_slots, psl_queue qcfg, uint64_t *part) {
 #pragma clang fp contract(off)
     __shared__ float s_edges[PSL_MAX_QBUCKETS + 1];
+    __shared__ uint64_t s_red[(kSampleBlock / 64) * kStatWords];
     if (threadIdx.x <= PSL_MAX_QBUCKETS)
         s_edges[threadIdx.x] = qcfg.e_bucket_edges[threadIdx.x];
     __syncthreads();
+    StatAcc st;
+    st.zero();
     const int64_t h_total = (int64_t)*h_total_p;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // loop bound uniform per wave so that wave-level pushes see all lanes
-    const int64_t h_end = ((h_total + 63) / 64) * 64;
-    for (int64_t h0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-         h0 < h_end; h0 += stride) {
-        const bool live = h0 < h_total;
-        int status = -1;  // 0 jaw, 2 fluence, 3 miss, 1 accepted
-        float oE = 0, ox = 0, oy = 0, oz = 0, ou = 0, ov = 0, ow = 0, owt = 0;
-        uint8_t type = 0;
-        if (live) {
+    const int64_t stride = (int64_t)gridDim.x * kSampleBlock;
+    for (int64_t h0 = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
+         h0 < n_slots; h0 += stride) {
+        uint8_t code = kEmpty;
+        if (h0 < h_total) {
+            st.add(PSL_STAT(histories), 1);
             // range containing h: last idx with H[idx] <= h
             int64_t lo = 0, hi = n_ranges;  // H[lo] <= h < H[hi]
             while (hi - lo > 1) {
@@ -256,10 +238,10 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
                                (uint64_t)before[idx];
             const int64_t p = off[k] + (int64_t)((sk + c + (uint64_t)r) % nk);
             const FieldDev F = fields[f];
-            type = ps.type[p];
+            const uint8_t type = ps.type[p];
             const double px = ps.x[p], py = ps.y[p], pz = geo.z_psl;
             const double du = ps.u[p], dv = ps.v[p], dw = ps.w[p];
-            status = 1;
+            int status = 1;  // 0 jaw, 2 fluence, 3 miss, 1 accepted
             if (F.jaws_on) {
                 if (!(dw > 0.0)) {
                     status = 0;
@@ -321,51 +303,40 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
                 if (miss || tn > tf || tf <= 0.0) {
                     status = 3;
                 } else {
-                    double t = tn > 0.0 ? tn : 0.0;
-                    oE = ps.E[p];
-                    ox = (float)(pos[0] + t * dir[0]);
-                    oy = (float)(pos[1] + t * dir[1]);
-                    oz = (float)(pos[2] + t * dir[2]);
-                    ou = (float)eu;
-                    ov = (float)ev;
-                    ow = (float)ew;
-                    owt = (float)wgt;
+                    const double t = tn > 0.0 ? tn : 0.0;
+                    const float oE = ps.E[p];
+                    const float owt = (float)wgt;
+                    int which = 0;
+                    if (type != 0) {
+                        int b = 0;
+                        for (int j = 1; j < qcfg.n_ebuckets; ++j)
+                            if (oE >= s_edges[j]) b = j;
+                        which = 1 + b;
+                    }
+                    const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
+                                         (uint64_t)h0;
+                    slots.p.E[h0] = oE;
+                    slots.p.x[h0] = (float)(pos[0] + t * dir[0]);
+                    slots.p.y[h0] = (float)(pos[1] + t * dir[1]);
+                    slots.p.z[h0] = (float)(pos[2] + t * dir[2]);
+                    slots.p.u[h0] = (float)eu;
+                    slots.p.v[h0] = (float)ev;
+                    slots.p.w[h0] = (float)ew;
+                    slots.p.wt[h0] = owt;
+                    slots.p.uid[h0] = uid;
+                    slots.p.ctr[h0] = which ? kSourceElectronCtr : 0u;
+                    code = (uint8_t)which;
+                    st.add(which ? PSL_STAT(electrons) : PSL_STAT(photons), 1);
+                    st.addf(PSL_STAT(e_in), (double)oE * owt);
                 }
             }
+            if (status == 0) st.add(PSL_STAT(jaw_rejected), 1);
+            if (status == 2) st.add(PSL_STAT(fluence_zero), 1);
+            if (status == 3) st.add(PSL_STAT(missed), 1);
         }
-        // queue selection: 0 photons, 1 + b electron bucket b
-        const bool acc = status == 1;
-        int which = 0;
-        if (acc && type != 0) {
-            int b = 0;
-            for (int j = 1; j < q.n_b; ++j)
-                if (oE >= s_edges[j]) b = j;
-            which = 1 + b;
-        }
-        uint32_t slot = wave_reserve(q.counts, which, acc);
-        bool lost = false;
-        if (acc) {
-            const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
-                                 (uint64_t)h0;
-            if (which == 0) {
-                push(q.ph, slot, oE, ox, oy, oz, ou, ov, ow, owt, uid, 0u);
-            } else if ((int64_t)slot < q.cap_b) {
-                push(q.el, (int64_t)(which - 1) * q.cap_b + slot, oE, ox, oy,
-                     oz, ou, ov, ow, owt, uid, kSourceElectronCtr);
-            } else {
-                lost = true;
-            }
-        }
-        wave_add_u64(&stats->histories, live ? 1 : 0);
-        wave_add_u64(&stats->jaw_rejected, status == 0 ? 1 : 0);
-        wave_add_u64(&stats->fluence_zero, status == 2 ? 1 : 0);
-        wave_add_u64(&stats->missed, status == 3 ? 1 : 0);
-        wave_add_u64(&stats->photons, acc && which == 0 ? 1 : 0);
-        wave_add_u64(&stats->electrons, acc && which != 0 && !lost ? 1 : 0);
-        wave_add_u64(&stats->lost, lost ? 1 : 0);
-        wave_add_f64(&stats->e_in, acc && !lost ? (double)oE * owt : 0.0);
-        if (lost) atomicAdd(&q.counts[PSL_QCOUNTS - 1], 1u);
+        slots.code[h0] = code;
     }
+    block_stats_write(st, s_red, part);
 }
 
 struct SampleWs {
@@ -373,13 +344,19 @@ struct SampleWs {
     uint8_t *mask;
     int64_t *C, *NF, *N, *H, *before, *T;
     double *g, *mu_tot;
-    uint64_t *chunks, *h_total;
+    uint64_t *chunks, *h_total, *part;
+    Slots slots;
+    uint32_t *tiles;
     size_t bytes;
 };
 
-SampleWs carve_sample(void *base, int64_t n_keys, int P, int F) {
+constexpr int kSampleMaxBlocks = 16384;
+
+SampleWs carve_sample(void *base, int64_t n_keys, int P, int F,
+                      int64_t n_hist) {
     Carver c(base);
     SampleWs w;
+    const int64_t ns = std::max<int64_t>(n_hist, 1);
     w.fields = c.take<FieldDev>(F);
     w.mask = c.take<uint8_t>((int64_t)F * P);
     w.C = c.take<int64_t>(F);
@@ -392,6 +369,20 @@ SampleWs carve_sample(void *base, int64_t n_keys, int P, int F) {
     w.T = c.take<int64_t>(n_keys);
     w.chunks = c.take<uint64_t>(scan_chunks((int64_t)F * n_keys + 1) + 1);
     w.h_total = c.take<uint64_t>(1);
+    w.part = c.take<uint64_t>((int64_t)kSampleMaxBlocks * kStatWords);
+    w.slots.p.capacity = ns;
+    w.slots.p.E = c.take<float>(ns);
+    w.slots.p.x = c.take<float>(ns);
+    w.slots.p.y = c.take<float>(ns);
+    w.slots.p.z = c.take<float>(ns);
+    w.slots.p.u = c.take<float>(ns);
+    w.slots.p.v = c.take<float>(ns);
+    w.slots.p.w = c.take<float>(ns);
+    w.slots.p.wt = c.take<float>(ns);
+    w.slots.p.uid = c.take<uint64_t>(ns);
+    w.slots.p.ctr = c.take<uint32_t>(ns);
+    w.slots.code = c.take<uint8_t>(ns);
+    w.tiles = c.take<uint32_t>((int64_t)kMaxQ * compact_tiles(ns));
     w.bytes = c.used;
     return w;
 }
@@ -429,10 +420,12 @@ psl_status validate_queue(const psl_queue *q) {
 using namespace psl;
 
 extern "C" size_t psl_sample_workspace_bytes(const psl_grid *g,
-                                             int32_t n_fields) {
-    if (!g || n_fields < 1) return 0;
+                                             int32_t n_fields,
+                                             int64_t n_histories) {
+    if (!g || n_fields < 1 || n_histories < 0) return 0;
     int64_t n_keys = 2LL * g->n_e * g->n_x * g->n_y;
-    return carve_sample(nullptr, n_keys, g->n_x * g->n_y, n_fields).bytes;
+    return carve_sample(nullptr, n_keys, g->n_x * g->n_y, n_fields,
+                        n_histories).bytes;
 }
 
 extern "C" psl_status psl_sample(const psl_phsp *sorted,
@@ -494,14 +487,15 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
     }
     const int64_t n_keys = 2LL * g->n_e * g->n_x * g->n_y;
     const int P = g->n_x * g->n_y;
-    SampleWs need = carve_sample(nullptr, n_keys, P, n_fields);
+    SampleWs need = carve_sample(nullptr, n_keys, P, n_fields,
+                                 cfg->n_histories);
     if (!d_ws || ws_bytes < need.bytes) {
         set_error("workspace %zu bytes < %zu required", ws_bytes, need.bytes);
         return PSL_ENOSPC;
     }
     if ((s = check_device())) return s;
     hipStream_t st = (hipStream_t)stream;
-    SampleWs w = carve_sample(d_ws, n_keys, P, n_fields);
+    SampleWs w = carve_sample(d_ws, n_keys, P, n_fields, cfg->n_histories);
     uint8_t *mask = d_mask ? d_mask : w.mask;
     int64_t *N = d_alloc ? d_alloc : w.N;
     PSL_HIP(hipMemcpyAsync(w.fields, fd.data(), sizeof(FieldDev) * n_fields,
@@ -512,6 +506,7 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
             {cfg->box_hi[0], cfg->box_hi[1], cfg->box_hi[2]}};
     hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, d_stats,
                        q->d_counts);
+    std::unique_ptr<ProfScope> prof_alloc(new ProfScope(PSL_PROF_ALLOC, st));
     int64_t nm = (int64_t)n_fields * P;
     hipLaunchKernelGGL(k_cull, dim3((unsigned)((nm + 255) / 256)), dim3(256),
                        0, st, w.fields, n_fields, geo, *g, cfg->cull, mask);
@@ -529,16 +524,24 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
     if ((s = exclusive_scan<int64_t, int64_t>(N, w.H, n_ranges, w.chunks,
                                               w.h_total, st)))
         return s;
-    QueueDev qd{q->ph, q->el, q->n_ebuckets, q->el.capacity / q->n_ebuckets,
-                q->d_counts};
+    prof_alloc.reset();
     if (cfg->n_histories > 0) {
+        ProfScope prof(PSL_PROF_SAMPLE, st);
         int cu = device_cu_count();
-        int64_t blocks = std::min<int64_t>((cfg->n_histories + 255) / 256,
-                                           (int64_t)cu * 16);
-        hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks), dim3(256), 0, st,
-                           *sorted, d_offsets, n_keys, w.fields, geo, w.H,
-                           n_ranges, w.h_total, w.before, w.T, w.g, cfg->seed,
-                           cfg->batch, qd, *q, d_stats);
+        int64_t blocks = std::min<int64_t>(
+            (cfg->n_histories + kSampleBlock - 1) / kSampleBlock,
+            std::min<int64_t>((int64_t)cu * 16, kSampleMaxBlocks));
+        hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks),
+                           dim3(kSampleBlock), 0, st, *sorted, d_offsets,
+                           n_keys, w.fields, geo, w.H, n_ranges, w.h_total,
+                           w.before, w.T, w.g, cfg->seed, cfg->batch, w.slots,
+                           cfg->n_histories, *q, w.part);
+        QueueRegions qr{q->ph, q->el, 1 + q->n_ebuckets,
+                        q->el.capacity / q->n_ebuckets, q->d_counts};
+        if ((s = compact_slots(w.slots, cfg->n_histories, nullptr, 0, 0, qr,
+                               w.tiles, st)))
+            return s;
+        if ((s = stats_reduce(w.part, (int)blocks, d_stats, st))) return s;
     }
     PSL_LAUNCHED();
     return PSL_OK;

@@ -73,6 +73,7 @@ extern "C" psl_status dose_tally(psl_dose_acc *acc, double *d_s1,
                          acc->frac_bits >= 16 && acc->frac_bits <= 40),
                     "bad accumulator mode");
         if (psl_status s = check_device()) return s;
+        ProfScope prof(PSL_PROF_FOLD, st);
         if (acc->mode == PSL_ACC_FIXED64)
             hipLaunchKernelGGL(k_fold<PSL_ACC_FIXED64>, dim3((unsigned)blocks),
                                dim3(kBlock), 0, st, acc->data,
@@ -87,6 +88,7 @@ extern "C" psl_status dose_tally(psl_dose_acc *acc, double *d_s1,
         PSL_REQUIRE(ph->dx > 0 && ph->dy > 0 && ph->dz > 0, "bad voxel size");
         if (psl_status s = check_device()) return s;
         double inv_vol = 1.0 / (ph->dx * ph->dy * ph->dz);
+        ProfScope prof(PSL_PROF_FINALIZE, st);
         hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(kBlock), 0,
                            st, d_s1, d_s2, ph->density, inv_vol, norm,
                            n_batches, d_dose, d_sigma, n);

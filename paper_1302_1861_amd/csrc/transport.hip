@@ -13,6 +13,7 @@
 //                LDS; consecutive deposits into one voxel are merged before
 //                the atomic; Highland deflection after each step.
 #include "common.hpp"
+#include "compact.hpp"
 
 #include <cmath>
 #include <vector>
@@ -87,7 +88,8 @@ __device__ __forceinline__ float lerp_tab(const float *t, int n, float x) {
 
 template <int MODE>
 __device__ __forceinline__ void tally(void *acc, int64_t v, float e, float wt,
-                                      double scale) {
+                                      double scale, uint64_t &n_dep) {
+    ++n_dep;
     if (MODE == PSL_ACC_FIXED64) {
         double q = (double)e * (double)wt * scale + 0.5;
         atomicAdd(reinterpret_cast<unsigned long long *>(acc) + v,
@@ -134,20 +136,36 @@ struct Items {
     uint32_t *counts;   // [0] photons, [1 + b] electron buckets
 };
 
-// Wave-granular work distribution over a fixed item count.
-__device__ __forceinline__ int64_t grab64(uint32_t *ctr) {
-    uint32_t base = 0;
-    if (__lane_id() == 0) base = atomicAdd(ctr, 64u);
-    return (int64_t)__shfl(base, 0);
+// Secondary-electron slots of the photon kernel: photon i owns slots
+// spill_cap + i * kSecPerPhoton + j; further secondaries go to the spill
+// slots [0, spill_cap) through one counter.
+constexpr int kSecPerPhoton = 6;
+
+struct SecSlots {
+    Slots s;
+    int64_t spill_cap;
+    uint32_t *spill_n;
+};
+
+__device__ __forceinline__ void put_slot(const Slots &S, int64_t k, float E,
+                                         float x, float y, float z, float u,
+                                         float v, float w, float wt,
+                                         uint64_t uid, uint32_t ctr,
+                                         uint8_t code) {
+    S.p.E[k] = E; S.p.x[k] = x; S.p.y[k] = y; S.p.z[k] = z;
+    S.p.u[k] = u; S.p.v[k] = v; S.p.w[k] = w; S.p.wt[k] = wt;
+    S.p.uid[k] = uid; S.p.ctr[k] = ctr;
+    S.code[k] = code;
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock)
-k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
+k_photons(Items ph, SecSlots sec, psl_queue qcfg, PhDev P, PhysDev Y,
           const float *__restrict__ tables, uint64_t seed, void *acc,
-          double scale, uint32_t *work, psl_stats *stats) {
+          double scale, uint32_t *work, uint64_t *part) {
     __shared__ float s_mu[kTabMu];
     __shared__ float s_bk[PSL_MAX_QBUCKETS + 1];
+    __shared__ uint64_t s_red[(kBlock / 64) * kStatWords];
     const TableHeader H = *reinterpret_cast<const TableHeader *>(tables);
     const float *gmu = tables + kTabHeaderBytes / 4;
     for (int i = threadIdx.x; i < kTabMu; i += kBlock) s_mu[i] = gmu[i];
@@ -155,12 +173,17 @@ k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
         s_bk[threadIdx.x] = qcfg.e_bucket_edges[threadIdx.x];
     __syncthreads();
     const int64_t n = (int64_t)ph.counts[0];
-    uint64_t n_int = 0, n_sec = 0, n_fl = 0, n_run = 0, n_lost = 0;
-    double e_esc = 0.0, e_killed = 0.0;
+    const int64_t n_chunks = (n + 63) / 64;
+    StatAcc st;
+    st.zero();
+    uint64_t n_dep = 0;
+    int part_i = (int)((blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) %
+                       kParts),
+        tried = 0;
     for (;;) {
-        const int64_t base = grab64(&work[0]);
-        if (base >= n) break;
-        const int64_t i = base + __lane_id();
+        const int64_t chunk = claim_chunk(work, n_chunks, part_i, tried);
+        if (chunk < 0) break;
+        const int64_t i = chunk * 64 + __lane_id();
         bool alive = i < n;
         float E = 0, x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, wt = 0;
         uint64_t uid = 0;
@@ -174,42 +197,36 @@ k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
         float mu1 = alive ? lerp_tab(s_mu, kTabMu,
                                      (__logf(E) - H.mu_lnE0) * H.mu_inv_dlnE)
                           : 0.0f;
-        int flights = 0;
-        bool first = true;
+        int flights = 0, n_sec = 0;
         while (__ballot(alive)) {
             bool push_e = false;
             float Te = 0, eu = 0, ev = 0, ew = 0;
             uint32_t birth = 0;
-            int64_t vox = 0;
-            if (alive) {
-                if (E < Y.p_cut) {
-                    int ix, iy, iz;
-                    if (voxel_of(P, x, y, z, ix, iy, iz))
-                        tally<MODE>(acc, ((int64_t)iz * P.ny + iy) * P.nx + ix,
-                                    E, wt, scale);
-                    else
-                        e_esc += (double)E * wt;
-                    alive = false;
-                }
+            if (alive && E < Y.p_cut) {
+                int ix, iy, iz;
+                if (voxel_of(P, x, y, z, ix, iy, iz))
+                    tally<MODE>(acc, ((int64_t)iz * P.ny + iy) * P.nx + ix, E,
+                                wt, scale, n_dep);
+                else
+                    st.addf(PSL_STAT(e_escaped), (double)E * wt);
+                alive = false;
             }
             if (alive) {
                 // one free flight against the majorant
                 float s = -__logf(rng.next()) / (mu1 * P.rho_max);
                 x += s * u; y += s * v; z += s * w;
-                ++n_fl;
+                st.add(PSL_STAT(flights), 1);
                 int ix, iy, iz;
                 if (!voxel_of(P, x, y, z, ix, iy, iz)) {
-                    e_esc += (double)E * wt;
-                    alive = false;
-                } else if (++flights > kMaxFlights) {
-                    ++n_run;
-                    vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
-                    tally<MODE>(acc, vox, E, wt, scale);
+                    st.addf(PSL_STAT(e_escaped), (double)E * wt);
                     alive = false;
                 } else {
-                    vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
-                    float rho = P.rho[vox];
-                    if (rng.next() * P.rho_max <= rho) {
+                    const int64_t vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
+                    if (++flights > kMaxFlights) {
+                        st.add(PSL_STAT(runaway), 1);
+                        tally<MODE>(acc, vox, E, wt, scale, n_dep);
+                        alive = false;
+                    } else if (rng.next() * P.rho_max <= P.rho[vox]) {
                         // Compton: Butcher-Messel sampling of eps = E'/E
                         float k = E / kME;
                         float e0 = 1.0f / (1.0f + 2.0f * k);
@@ -233,7 +250,7 @@ k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
                             float gr = 1.0f - eps * sint2 / (1.0f + epssq);
                             if (gr >= r3 || tries > 1000) break;
                         }
-                        ++n_int;
+                        st.add(PSL_STAT(interactions), 1);
                         float cost = 1.0f - onecost;
                         float sint = sqrtf(fmaxf(sint2, 0.0f));
                         float sp, cp;
@@ -242,7 +259,8 @@ k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
                         float T = E - Es;
                         float pu = u, pv = v, pw = w;
                         rotate(u, v, w, cost, sint, cp, sp);
-                        if (T > Y.t_cut && !(Y.flags & PSL_FLAG_FIRST_COLLISION)) {
+                        if (T > Y.t_cut &&
+                            !(Y.flags & PSL_FLAG_FIRST_COLLISION)) {
                             float qx = E * pu - Es * u, qy = E * pv - Es * v,
                                   qz = E * pw - Es * w;
                             float rq = rsqrtf(qx * qx + qy * qy + qz * qz);
@@ -251,10 +269,10 @@ k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
                             eu = qx * rq; ev = qy * rq; ew = qz * rq;
                             birth = rng.n;
                         } else {
-                            tally<MODE>(acc, vox, T, wt, scale);
+                            tally<MODE>(acc, vox, T, wt, scale, n_dep);
                         }
                         if (Y.flags & PSL_FLAG_FIRST_COLLISION) {
-                            e_killed += (double)Es * wt;
+                            st.addf(PSL_STAT(e_killed), (double)Es * wt);
                             alive = false;
                         } else {
                             E = Es;
@@ -265,50 +283,50 @@ k_photons(Items ph, Items el, psl_queue qcfg, PhDev P, PhysDev Y,
                     }
                 }
             }
-            (void)first;
-            // recoil electrons into their energy bucket, one atomic per
-            // wave and bucket
-            int b = 0;
-            for (int j = 1; j < el.n_b; ++j)
-                if (Te >= s_bk[j]) b = j;
-            uint32_t slot = wave_reserve(el.counts, 1 + b, push_e);
+            // recoil electron: own slot, or a spill slot past kSecPerPhoton
+            const bool spill = push_e && n_sec >= kSecPerPhoton;
+            uint32_t sslot = wave_reserve(sec.spill_n, 0, spill);
             if (push_e) {
-                if ((int64_t)slot < el.cap_b) {
-                    int64_t d = (int64_t)b * el.cap_b + slot;
-                    el.p.E[d] = Te; el.p.x[d] = x; el.p.y[d] = y;
-                    el.p.z[d] = z; el.p.u[d] = eu; el.p.v[d] = ev;
-                    el.p.w[d] = ew; el.p.wt[d] = wt; el.p.uid[d] = uid;
-                    el.p.ctr[d] = birth;
-                    ++n_sec;
+                int b = 0;
+                for (int j = 1; j < qcfg.n_ebuckets; ++j)
+                    if (Te >= s_bk[j]) b = j;
+                int64_t k = -1;
+                if (!spill)
+                    k = sec.spill_cap + i * kSecPerPhoton + n_sec;
+                else if ((int64_t)sslot < sec.spill_cap)
+                    k = sslot;
+                if (k >= 0) {
+                    put_slot(sec.s, k, Te, x, y, z, eu, ev, ew, wt, uid, birth,
+                             (uint8_t)(1 + b));
+                    st.add(PSL_STAT(secondaries), 1);
                 } else {
-                    ++n_lost;
-                    atomicAdd(&el.counts[PSL_QCOUNTS - 1], 1u);
+                    st.add(PSL_STAT(lost), 1);
                 }
+                ++n_sec;
             }
         }
+        // mark this photon's unused secondary slots empty
+        if (i < n)
+            for (int j = n_sec; j < kSecPerPhoton; ++j)
+                sec.s.code[sec.spill_cap + i * kSecPerPhoton + j] = kEmpty;
     }
-    wave_add_u64(&stats->interactions, n_int);
-    wave_add_u64(&stats->secondaries, n_sec);
-    wave_add_u64(&stats->flights, n_fl);
-    wave_add_u64(&stats->runaway, n_run);
-    wave_add_u64(&stats->lost, n_lost);
-    wave_add_f64(&stats->e_escaped, e_esc);
-    wave_add_f64(&stats->reserved[0], e_killed);
+    st.add(PSL_STAT(photon_deposits), n_dep);
+    block_stats_write(st, s_red, part);
 }
 
 template <int MODE>
 __global__ void __launch_bounds__(kBlock)
 k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
             uint64_t seed, void *acc, double scale, uint32_t *work,
-            psl_stats *stats) {
+            uint64_t *part) {
     __shared__ float s_rng[kTabRange];
     __shared__ float s_inv[kTabInv];
+    __shared__ uint64_t s_red[(kBlock / 64) * kStatWords];
     const TableHeader H = *reinterpret_cast<const TableHeader *>(tables);
     const float *g = tables + kTabHeaderBytes / 4 + kTabMu;
     for (int i = threadIdx.x; i < kTabRange; i += kBlock) s_rng[i] = g[i];
     for (int i = threadIdx.x; i < kTabInv; i += kBlock)
         s_inv[i] = g[kTabRange + i];
-    __syncthreads();
     // bucket sizes (clamped to the region capacity), highest energy first
     __shared__ int64_t s_cnt[PSL_MAX_QBUCKETS];
     if (threadIdx.x < PSL_MAX_QBUCKETS) {
@@ -319,12 +337,17 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
     __syncthreads();
     int64_t total = 0;
     for (int b = 0; b < el.n_b; ++b) total += s_cnt[b];
-    uint64_t n_seg = 0, n_run = 0;
-    double e_esc = 0.0;
+    const int64_t n_chunks = (total + 63) / 64;
+    StatAcc st;
+    st.zero();
+    uint64_t n_dep = 0;
+    int part_i = (int)((blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) %
+                       kParts),
+        tried = 0;
     for (;;) {
-        const int64_t base = grab64(&work[1]);
-        if (base >= total) break;
-        int64_t t = base + __lane_id();
+        const int64_t chunk = claim_chunk(work, n_chunks, part_i, tried);
+        if (chunk < 0) break;
+        int64_t t = chunk * 64 + __lane_id();
         if (t >= total) continue;
         int b = el.n_b - 1;
         while (t >= s_cnt[b]) { t -= s_cnt[b]; --b; }
@@ -339,7 +362,7 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
         int iz = (int)floorf((z - P.z0) * P.iz_);
         if (ix < -1 || iy < -1 || iz < -1 || ix > P.nx || iy > P.ny ||
             iz > P.nz) {
-            e_esc += (double)T * wt;
+            st.addf(PSL_STAT(e_escaped), (double)T * wt);
             continue;
         }
         ix = min(max(ix, 0), P.nx - 1);
@@ -347,7 +370,7 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
         iz = min(max(iz, 0), P.nz - 1);
         int64_t vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
         if (T <= Y.t_cut) {
-            tally<MODE>(acc, vox, T, wt, scale);
+            tally<MODE>(acc, vox, T, wt, scale, n_dep);
             continue;
         }
         Rng rng;
@@ -374,11 +397,11 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 sb = fmaxf(sb, 0.0f);
                 float seg = fminf(rem, sb);
                 float dm = P.rho[vox] * seg;
-                ++n_seg;
+                st.add(PSL_STAT(segments), 1);
                 if (dm >= r || ++segs > kMaxSegments) {
-                    if (segs > kMaxSegments) ++n_run;
+                    if (segs > kMaxSegments) st.add(PSL_STAT(runaway), 1);
                     if (vox != pv) {
-                        tally<MODE>(acc, pv, pe, wt, scale);
+                        tally<MODE>(acc, pv, pe, wt, scale, n_dep);
                         pv = vox;
                         pe = 0.0f;
                     }
@@ -390,7 +413,7 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 r -= dm;
                 float Tn = fminf(lerp_tab(s_inv, kTabInv, r * H.inv_inv_dr), T);
                 if (vox != pv) {
-                    tally<MODE>(acc, pv, pe, wt, scale);
+                    tally<MODE>(acc, pv, pe, wt, scale, n_dep);
                     pv = vox;
                     pe = 0.0f;
                 }
@@ -408,7 +431,7 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                     else { iz += w > 0.0f ? 1 : -1;
                            in = (unsigned)iz < (unsigned)P.nz; }
                     if (!in) {
-                        e_esc += (double)T * wt;
+                        st.addf(PSL_STAT(e_escaped), (double)T * wt);
                         T = 0.0f;
                         done = true;
                         break;
@@ -422,8 +445,9 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 // mass thickness; space angle Rayleigh-distributed with
                 // scale theta0, truncated at pi
                 float pbc = T0 * (T0 + 2.0f * kME) / (T0 + kME);
-                float q = tm / Y.X0;
-                float th0 = 13.6f / pbc * sqrtf(q) * (1.0f + 0.038f * __logf(q));
+                float qq = tm / Y.X0;
+                float th0 = 13.6f / pbc * sqrtf(qq) *
+                            (1.0f + 0.038f * __logf(qq));
                 th0 = fmaxf(th0, 0.0f);
                 float th;
                 int tries = 0;
@@ -431,26 +455,66 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                     th = th0 * sqrtf(-2.0f * __logf(rng.next()));
                 } while (th > kPI && ++tries < 64);
                 if (th > kPI) th = kPI * rng.next();
-                float st, ct, sp, cp;
-                __sincosf(th, &st, &ct);
+                float sth, cth, sp, cp;
+                __sincosf(th, &sth, &cth);
                 __sincosf(2.0f * kPI * rng.next(), &sp, &cp);
-                rotate(u, v, w, ct, st, cp, sp);
+                rotate(u, v, w, cth, sth, cp, sp);
             }
         }
-        if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale);
+        if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale, n_dep);
     }
-    wave_add_u64(&stats->segments, n_seg);
-    wave_add_u64(&stats->runaway, n_run);
-    wave_add_f64(&stats->e_escaped, e_esc);
+    st.add(PSL_STAT(deposits), n_dep);
+    block_stats_write(st, s_red, part);
 }
 
-__global__ void k_transport_init(uint32_t *work) {
-    if (threadIdx.x < 2) work[threadIdx.x] = 0;
+__global__ void k_transport_init(uint32_t *work, int n_words,
+                                 uint8_t *spill_code, int64_t spill_cap) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_words;
+         i += gridDim.x * blockDim.x)
+        work[i] = 0;
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
+         i < spill_cap; i += (int64_t)gridDim.x * blockDim.x)
+        spill_code[i] = kEmpty;
 }
 
 __global__ void k_consume(uint32_t *counts) {
     if (threadIdx.x < PSL_QCOUNTS - 1) counts[threadIdx.x] = 0;
 }
+
+struct TransportWs {
+    uint32_t *work;        // 2 work-claim arrays + spill counter
+    Slots sec;
+    uint32_t *tiles;
+    uint64_t *part;
+    int64_t spill_cap, n_slots;
+    size_t bytes;
+};
+
+TransportWs carve_transport(void *base, int64_t ph_cap, int grid_blocks) {
+    Carver c(base);
+    TransportWs w;
+    w.work = c.take<uint32_t>(2 * kParts * kPartStride + 64);
+    w.spill_cap = std::max<int64_t>(65536, ph_cap / 8);
+    w.n_slots = w.spill_cap + std::max<int64_t>(ph_cap, 1) * kSecPerPhoton;
+    w.sec.p.capacity = w.n_slots;
+    w.sec.p.E = c.take<float>(w.n_slots);
+    w.sec.p.x = c.take<float>(w.n_slots);
+    w.sec.p.y = c.take<float>(w.n_slots);
+    w.sec.p.z = c.take<float>(w.n_slots);
+    w.sec.p.u = c.take<float>(w.n_slots);
+    w.sec.p.v = c.take<float>(w.n_slots);
+    w.sec.p.w = c.take<float>(w.n_slots);
+    w.sec.p.wt = c.take<float>(w.n_slots);
+    w.sec.p.uid = c.take<uint64_t>(w.n_slots);
+    w.sec.p.ctr = c.take<uint32_t>(w.n_slots);
+    w.sec.code = c.take<uint8_t>(w.n_slots);
+    w.tiles = c.take<uint32_t>((int64_t)kMaxQ * compact_tiles(w.n_slots));
+    w.part = c.take<uint64_t>((int64_t)2 * grid_blocks * kStatWords);
+    w.bytes = c.used;
+    return w;
+}
+
+constexpr int kMaxGridBlocks = 64 * 1024;
 
 }  // namespace
 }  // namespace psl
@@ -528,8 +592,8 @@ extern "C" psl_status psl_physics_init(const psl_physics *phys,
 }
 
 extern "C" size_t transport_batch_workspace_bytes(const psl_queue *q) {
-    (void)q;
-    return 256;
+    if (!q) return 0;
+    return carve_transport(nullptr, q->ph.capacity, kMaxGridBlocks).bytes;
 }
 
 extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
@@ -558,22 +622,26 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     PSL_REQUIRE(phys->t_cut > 0 && phys->p_cut > 0 && phys->step > 0 &&
                     phys->X0 > 0,
                 "bad physics constants");
-    if (!d_ws || ws_bytes < transport_batch_workspace_bytes(q)) {
-        set_error("workspace too small");
-        return PSL_ENOSPC;
-    }
     psl_launch L{kBlock, 8, 0, 0};
     if (launch) {
         PSL_REQUIRE(launch->block == kBlock,
                     "block must be %d in this build", kBlock);
         PSL_REQUIRE(launch->blocks_per_cu >= 1 && launch->blocks_per_cu <= 64,
                     "blocks_per_cu outside 1..64");
+        PSL_REQUIRE(launch->n_cu >= 0 && launch->n_cu <= 1024,
+                    "n_cu outside 0..1024");
         L = *launch;
+    }
+    if (!d_ws || ws_bytes < transport_batch_workspace_bytes(q)) {
+        set_error("workspace %zu bytes < %zu required", ws_bytes,
+                  transport_batch_workspace_bytes(q));
+        return PSL_ENOSPC;
     }
     if ((s = check_device())) return s;
     const int cu = L.n_cu > 0 ? L.n_cu : device_cu_count();
+    const int blocks = std::min(cu * L.blocks_per_cu, kMaxGridBlocks);
     hipStream_t st = (hipStream_t)stream;
-    uint32_t *work = static_cast<uint32_t *>(d_ws);
+    TransportWs w = carve_transport(d_ws, q->ph.capacity, kMaxGridBlocks);
     PhDev P{ph->nx, ph->ny, ph->nz, (float)ph->x0, (float)ph->y0,
             (float)ph->z0, (float)ph->dx, (float)ph->dy, (float)ph->dz,
             (float)(1.0 / ph->dx), (float)(1.0 / ph->dy),
@@ -583,25 +651,49 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     Items iph{q->ph, 1, q->ph.capacity, q->d_counts};
     Items iel{q->el, q->n_ebuckets, q->el.capacity / q->n_ebuckets,
               q->d_counts};
+    uint32_t *work_ph = w.work;
+    uint32_t *work_el = w.work + kParts * kPartStride;
+    uint32_t *spill_n = w.work + 2 * kParts * kPartStride;
+    SecSlots sec{w.sec, w.spill_cap, spill_n};
+    QueueRegions qr{q->ph, q->el, 1 + q->n_ebuckets,
+                    q->el.capacity / q->n_ebuckets, q->d_counts};
     const float *tab = static_cast<const float *>(d_tables);
-    double scale = acc->mode == PSL_ACC_FIXED64 ? std::ldexp(1.0, acc->frac_bits)
-                                                : 1.0;
-    dim3 grid((unsigned)(cu * L.blocks_per_cu)), block(kBlock);
-    hipLaunchKernelGGL(k_transport_init, dim3(1), dim3(64), 0, st, work);
-    if (acc->mode == PSL_ACC_FIXED64) {
-        hipLaunchKernelGGL(k_photons<PSL_ACC_FIXED64>, grid, block, 0, st,
-                           iph, iel, *q, P, Y, tab, seed, acc->data, scale,
-                           work, d_stats);
-        hipLaunchKernelGGL(k_electrons<PSL_ACC_FIXED64>, grid, block, 0, st,
-                           iel, P, Y, tab, seed, acc->data, scale, work,
-                           d_stats);
-    } else {
-        hipLaunchKernelGGL(k_photons<PSL_ACC_F64>, grid, block, 0, st, iph,
-                           iel, *q, P, Y, tab, seed, acc->data, scale, work,
-                           d_stats);
-        hipLaunchKernelGGL(k_electrons<PSL_ACC_F64>, grid, block, 0, st, iel,
-                           P, Y, tab, seed, acc->data, scale, work, d_stats);
+    const double scale =
+        acc->mode == PSL_ACC_FIXED64 ? std::ldexp(1.0, acc->frac_bits) : 1.0;
+    const bool fixed = acc->mode == PSL_ACC_FIXED64;
+    dim3 grid((unsigned)blocks), block(kBlock);
+    hipLaunchKernelGGL(k_transport_init, dim3(256), dim3(256), 0, st, w.work,
+                       2 * kParts * kPartStride + 64, w.sec.code,
+                       w.spill_cap);
+    {
+        ProfScope prof(PSL_PROF_PHOTONS, st);
+        if (fixed)
+            hipLaunchKernelGGL(k_photons<PSL_ACC_FIXED64>, grid, block, 0, st,
+                               iph, sec, *q, P, Y, tab, seed, acc->data,
+                               scale, work_ph, w.part);
+        else
+            hipLaunchKernelGGL(k_photons<PSL_ACC_F64>, grid, block, 0, st,
+                               iph, sec, *q, P, Y, tab, seed, acc->data,
+                               scale, work_ph, w.part);
     }
+    {
+        ProfScope prof(PSL_PROF_REBUCKET, st);
+        if ((s = compact_slots(w.sec, w.n_slots, q->d_counts, kSecPerPhoton,
+                               w.spill_cap, qr, w.tiles, st)))
+            return s;
+    }
+    {
+        ProfScope prof(PSL_PROF_ELECTRONS, st);
+        if (fixed)
+            hipLaunchKernelGGL(k_electrons<PSL_ACC_FIXED64>, grid, block, 0,
+                               st, iel, P, Y, tab, seed, acc->data, scale,
+                               work_el, w.part + (int64_t)blocks * kStatWords);
+        else
+            hipLaunchKernelGGL(k_electrons<PSL_ACC_F64>, grid, block, 0, st,
+                               iel, P, Y, tab, seed, acc->data, scale,
+                               work_el, w.part + (int64_t)blocks * kStatWords);
+    }
+    if ((s = stats_reduce(w.part, 2 * blocks, d_stats, st))) return s;
     hipLaunchKernelGGL(k_consume, dim3(1), dim3(64), 0, st, q->d_counts);
     PSL_LAUNCHED();
     return PSL_OK;

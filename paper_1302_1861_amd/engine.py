@@ -160,7 +160,7 @@ class Engine:
         self.stats = torch.zeros(C.sizeof(psl_stats), dtype=torch.uint8,
                                  device=device)
         self.ws_sample = _ws(lib().psl_sample_workspace_bytes(
-            C.byref(self.grid), len(wl.fields)), device)
+            C.byref(self.grid), len(wl.fields), self.hpb), device)
         self.ws_transport = _ws(lib().transport_batch_workspace_bytes(
             C.byref(self.queue)), device)
         self.n_kept = None
@@ -212,7 +212,11 @@ class Engine:
         return self.finalize()
 
     def stats_dict(self):
-        return stats_to_dict(self.stats)
+        """Batch statistics; `lost` includes entries a full queue region
+        could not take."""
+        d = stats_to_dict(self.stats)
+        d["lost"] += int(self.queue_counts()[-1])
+        return d
 
     def queue_counts(self):
         return self.counts.cpu().numpy().view(np.uint32).copy()

@@ -201,7 +201,11 @@ def _parity(wl, hist, batches, threads=0, check_gamma=False):
     s_g = s_g.cpu().numpy().astype(np.float64)
     d_o, s_o, info = oracle.run_dose(wl, n_threads=threads, histories=hist,
                                      batches=batches)
-    z = analysis.zscore_stats(d_g, s_g, d_o, s_o, ref_for_threshold=d_o)
+    # the 10% isodose region is taken on the mean of the two doses: taking
+    # it on either noisy dose alone keeps that side's upward fluctuations
+    # near the threshold and biases the mean z
+    z = analysis.zscore_stats(d_g, s_g, d_o, s_o,
+                              ref_for_threshold=0.5 * (d_g + d_o))
     _say(wl.name, "z", z)
     assert z["frac_le3"] >= 0.99
     assert abs(z["mean"]) < 0.1
@@ -211,7 +215,7 @@ def _parity(wl, hist, batches, threads=0, check_gamma=False):
 
 def test_dose_parity_tiny_water():
     wl = S.workload_tiny()
-    d_g, s_g, d_o, s_o = _parity(wl, 2_000_000, 10)
+    d_g, s_g, d_o, s_o = _parity(wl, 2_000_000, 40)
     # depth dose on the central 4x4 voxel columns, low noise
     shp = wl.phantom.density.shape
     g = d_g.reshape(shp)[:, 28:32, 28:32].sum((1, 2))
@@ -226,13 +230,13 @@ def test_dose_parity_tiny_water():
 def test_dose_parity_heterogeneous_jaws_fluence():
     wl = S.workload_heterogeneous(n_particles=1_000_000, shape=(40, 40, 40),
                                   voxel=0.8)
-    _parity(wl, 2_000_000, 10)
+    _parity(wl, 2_000_000, 40)
 
 
 def test_dose_parity_imrt_rotated_segments():
     wl = S.workload_imrt(n_particles=1_000_000)
     wl.phantom = S.water_phantom((40, 40, 40), 0.8, (-16.0, -16.0, 84.0))
-    _parity(wl, 2_000_000, 10)
+    _parity(wl, 2_000_000, 40)
 
 
 @pytest.mark.skipif(not os.path.exists(os.path.join(GOLDEN,
@@ -243,10 +247,11 @@ def test_dose_gamma_against_high_statistics_oracle():
     within 3 sigma against the oracle's high-statistics dose."""
     import torch
     ref = np.load(os.path.join(GOLDEN, "oracle_dose_tiny.npz"))
+    B = int(ref["batches"])
     hist = int(ref["histories"])
     wl = S.workload_tiny()
-    eng = _engine(wl, hist // 10)
-    for b in range(10):
+    eng = _engine(wl, hist // B)
+    for b in range(B):
         eng.step(b)
     d_g, s_g = eng.finalize()
     torch.cuda.synchronize()
@@ -255,7 +260,8 @@ def test_dose_gamma_against_high_statistics_oracle():
     s_g = s_g.cpu().numpy().astype(np.float64).reshape(shp)
     d_o = ref["dose"].astype(np.float64).reshape(shp)
     s_o = ref["sigma"].astype(np.float64).reshape(shp)
-    z = analysis.zscore_stats(d_g, s_g, d_o, s_o, ref_for_threshold=d_o)
+    z = analysis.zscore_stats(d_g, s_g, d_o, s_o,
+                              ref_for_threshold=0.5 * (d_g + d_o))
     _say("golden z", z)
     assert z["frac_le3"] >= 0.99 and abs(z["mean"]) < 0.1
     rate = analysis.gamma_pass_rate(d_o, d_g, 0.5, dose_crit=0.02, dta=0.2,
