@@ -266,12 +266,15 @@ typedef struct psl_dose_acc {
     void *data;                 /* device [nz*ny*nx]                         */
 } psl_dose_acc;
 
-/* Launch shape.  NULL selects defaults; the autotuner chooses values. */
+/* Launch shape.  NULL selects defaults (256, 8, 0, 1); the autotuner
+ * chooses values. */
 typedef struct psl_launch {
-    int32_t block;              /* threads per block: 64..1024, multiple 64 */
-    int32_t blocks_per_cu;      /* resident blocks per CU to launch         */
-    int32_t n_cu;               /* CUs to assume (0 = query the device)     */
-    int32_t pad;
+    int32_t block;              /* threads per block (256 in this build)     */
+    int32_t blocks_per_cu;      /* transport blocks launched per CU, 1..64   */
+    int32_t n_cu;               /* CUs to assume (0 = query the device)      */
+    int32_t rebucket;           /* 1: compact secondary electrons into the   */
+                                /* energy buckets before electron transport; */
+                                /* 0: transport them from the raw stream     */
 } psl_launch;
 
 /*

@@ -125,7 +125,14 @@ class psl_dose_acc(C.Structure):
 
 class psl_launch(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("n_cu", C.c_int32), ("pad", C.c_int32)]
+                ("n_cu", C.c_int32), ("rebucket", C.c_int32)]
+
+
+def make_launch(blocks_per_cu=8, rebucket=1, n_cu=0, block=256):
+    L = psl_launch()
+    L.block, L.blocks_per_cu, L.n_cu, L.rebucket = block, blocks_per_cu, \
+        n_cu, rebucket
+    return L
 
 
 # ------------------------------------------------------------------ load --

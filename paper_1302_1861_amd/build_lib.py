@@ -15,7 +15,8 @@ OBJ = os.path.join(HERE, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
+         "-munsafe-fp-atomics", "-fno-hip-fp32-correctly-rounded-divide-sqrt",
+         "-Wall", "-Wno-unused-function",
          "-I" + os.path.join(HERE, "..", "include")]
 
 

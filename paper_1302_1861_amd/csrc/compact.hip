@@ -13,28 +13,29 @@ __device__ __forceinline__ int64_t slot_count(int64_t n_host,
     return n < n_host ? n : n_host;
 }
 
+// one wave per 1024-slot tile
 __global__ void __launch_bounds__(kCompactBlock)
 k_compact_count(const uint8_t *__restrict__ code, int64_t n_host,
                 const uint32_t *n_dev, int64_t mult, int64_t add, int nq,
                 uint32_t *__restrict__ tile_counts, int64_t n_tiles) {
-    __shared__ uint32_t cnt[kMaxQ];
-    if (threadIdx.x < kMaxQ) cnt[threadIdx.x] = 0;
-    __syncthreads();
+    const int lane = __lane_id();
+    const int64_t tile = (int64_t)blockIdx.x * (kCompactBlock / 64) +
+                         (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
     const int64_t n = slot_count(n_host, n_dev, mult, add);
-    const int64_t base = (int64_t)blockIdx.x * kCompactTile;
+    const int64_t base = tile * kCompactTile;
+    uint32_t mine = 0;   // lane c counts code c
     if (base < n) {
-        for (int r = 0; r < kCompactItems; ++r) {
-            int64_t i = base + r * kCompactBlock + threadIdx.x;
-            if (i < n) {
-                uint32_t c = code[i];
-                if (c < (uint32_t)nq) atomicAdd(&cnt[c], 1u);
+        for (int r = 0; r < kCompactRounds; ++r) {
+            const int64_t i = base + r * 64 + lane;
+            const uint32_t c = i < n ? (uint32_t)code[i] : (uint32_t)kEmpty;
+            for (int q = 0; q < nq; ++q) {
+                uint64_t m = __ballot(c == (uint32_t)q);
+                if (lane == q) mine += (uint32_t)__popcll(m);
             }
         }
     }
-    __syncthreads();
-    if (threadIdx.x < nq)
-        tile_counts[(int64_t)threadIdx.x * n_tiles + blockIdx.x] =
-            cnt[threadIdx.x];
+    if (lane < nq) tile_counts[(int64_t)lane * n_tiles + tile] = mine;
 }
 
 constexpr int kOffBlock = 1024;
@@ -61,43 +62,30 @@ __global__ void __launch_bounds__(kCompactBlock)
 k_compact_scatter(Slots s, int64_t n_host, const uint32_t *n_dev,
                   int64_t mult, int64_t add, QueueRegions q,
                   const uint32_t *__restrict__ tile_off, int64_t n_tiles) {
-    constexpr int NW = kCompactBlock / 64;
-    __shared__ uint32_t s_base[kMaxQ];
-    __shared__ uint32_t s_w[NW][kMaxQ];
-    const int tid = threadIdx.x, wid = tid >> 6;
+    const int lane = __lane_id();
+    const int64_t tile = (int64_t)blockIdx.x * (kCompactBlock / 64) +
+                         (threadIdx.x >> 6);
+    if (tile >= n_tiles) return;
     const int64_t n = slot_count(n_host, n_dev, mult, add);
-    const int64_t base = (int64_t)blockIdx.x * kCompactTile;
-    if (base >= n) return;   // uniform per block
-    if (tid < q.nq) s_base[tid] = tile_off[(int64_t)tid * n_tiles + blockIdx.x];
+    const int64_t base = tile * kCompactTile;
+    if (base >= n) return;
+    uint32_t run = lane < q.nq ? tile_off[(int64_t)lane * n_tiles + tile] : 0;
     uint32_t lost = 0;
-    for (int r = 0; r < kCompactItems; ++r) {
-        if (tid < NW * kMaxQ) (&s_w[0][0])[tid] = 0;
-        __syncthreads();
-        const int64_t i = base + r * kCompactBlock + tid;
+    for (int r = 0; r < kCompactRounds; ++r) {
+        const int64_t i = base + r * 64 + lane;
         const uint32_t c = i < n ? (uint32_t)s.code[i] : (uint32_t)kEmpty;
+        uint64_t my = 0;
+        uint32_t add_c = 0;
+        for (int qq = 0; qq < q.nq; ++qq) {
+            uint64_t m = __ballot(c == (uint32_t)qq);
+            if (c == (uint32_t)qq) my = m;
+            if (lane == qq) add_c = (uint32_t)__popcll(m);
+        }
         const bool valid = c < (uint32_t)q.nq;
-        uint64_t peers = __ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            uint64_t bb = __ballot((c >> b) & 1u);
-            peers &= ((c >> b) & 1u) ? bb : ~bb;
-        }
-        const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
-        if (valid && rank == 0) s_w[wid][c] = (uint32_t)__popcll(peers);
-        __syncthreads();
-        if (tid < q.nq) {
-            uint32_t run = s_base[tid];
-#pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                uint32_t t = s_w[w][tid];
-                s_w[w][tid] = run;
-                run += t;
-            }
-            s_base[tid] = run;
-        }
-        __syncthreads();
+        const uint32_t cb = __shfl(run, valid ? (int)c : 0);
+        run += add_c;
         if (valid) {
-            const uint32_t dst = s_w[wid][c] + rank;
+            const uint32_t dst = cb + (uint32_t)__popcll(my & lanemask_lt());
             const psl_particles &P = c == 0 ? q.ph : q.el;
             const int64_t cap = c == 0 ? q.ph.capacity : q.cap_b;
             if ((int64_t)dst < cap) {
@@ -117,9 +105,9 @@ k_compact_scatter(Slots s, int64_t n_host, const uint32_t *n_dev,
                 ++lost;
             }
         }
-        __syncthreads();
     }
-    if (lost) atomicAdd(&q.counts[PSL_QCOUNTS - 1], lost);
+    for (int o = 32; o > 0; o >>= 1) lost += __shfl_xor(lost, o);
+    if (lane == 0 && lost) atomicAdd(&q.counts[PSL_QCOUNTS - 1], lost);
 }
 
 }  // namespace
@@ -129,13 +117,15 @@ psl_status compact_slots(const Slots &s, int64_t n_host, const uint32_t *n_dev,
                          uint32_t *tile_counts, hipStream_t st) {
     const int64_t n_tiles = compact_tiles(n_host);
     if (n_tiles == 0) return PSL_OK;
-    hipLaunchKernelGGL(k_compact_count, dim3((unsigned)n_tiles),
+    const int64_t wpb = kCompactBlock / 64;
+    const unsigned blocks = (unsigned)((n_tiles + wpb - 1) / wpb);
+    hipLaunchKernelGGL(k_compact_count, dim3(blocks),
                        dim3(kCompactBlock), 0, st, s.code, n_host, n_dev,
                        mult, add, q.nq, tile_counts, n_tiles);
     hipLaunchKernelGGL(k_compact_offsets, dim3((unsigned)q.nq),
                        dim3(kOffBlock), 0, st, tile_counts, n_tiles,
                        q.counts);
-    hipLaunchKernelGGL(k_compact_scatter, dim3((unsigned)n_tiles),
+    hipLaunchKernelGGL(k_compact_scatter, dim3(blocks),
                        dim3(kCompactBlock), 0, st, s, n_host, n_dev, mult,
                        add, q, tile_counts, n_tiles);
     PSL_LAUNCHED();

@@ -6,13 +6,14 @@
 // secondary), with a one-byte queue code (0 photons, 1 + b electron bucket
 // b, kEmpty nothing).  Three kernels then move the occupied slots into the
 // queue regions:
-//   k_compact_count    per 4096-slot tile, LDS counts per queue code
+//   k_compact_count    per 1024-slot wave tile, counts per queue code from
+//                      ballots (no LDS, no barriers)
 //   k_compact_offsets  per queue, exclusive scan of the tile counts on top of
 //                      the queue's current count; the count is advanced
-//   k_compact_scatter  stable scatter: each round of 256 slots is ranked
-//                      with wave ballots over the code bits, per-wave counts
-//                      in LDS order the waves, a per-code running base
-//                      carries the rounds
+//   k_compact_scatter  stable scatter: one wave per tile takes 16 rounds of
+//                      64 slots; a slot's rank among equal codes is a
+//                      popcount of the ballot for its code, the base of
+//                      code c is held by lane c and advanced each round
 // Queue order is the slot order, so the result is deterministic.
 #pragma once
 
@@ -22,8 +23,8 @@ namespace psl {
 
 constexpr uint8_t kEmpty = 0xFF;
 constexpr int kCompactBlock = 256;
-constexpr int kCompactItems = 16;
-constexpr int kCompactTile = kCompactBlock * kCompactItems;
+constexpr int kCompactRounds = 16;
+constexpr int kCompactTile = 64 * kCompactRounds;   // slots per wave
 constexpr int kMaxQ = 1 + PSL_MAX_QBUCKETS;
 
 struct Slots {
@@ -45,6 +46,7 @@ inline int64_t compact_tiles(int64_t n_max) {
 // Enqueues the three kernels over slots [0, n) where n = n_host, or, if
 // n_dev is given, n = min(n_host, n_dev[0] * mult + add).
 // tile_counts: workspace of kMaxQ * compact_tiles(n_host) uint32.
+// Codes >= nq (kEmpty) are skipped; nq <= kMaxQ.
 psl_status compact_slots(const Slots &s, int64_t n_host,
                          const uint32_t *n_dev, int64_t mult, int64_t add,
                          const QueueRegions &q, uint32_t *tile_counts,

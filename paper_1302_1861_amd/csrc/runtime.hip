@@ -52,41 +52,40 @@ k_stats_reduce(const uint64_t *__restrict__ part, int n_blocks,
                psl_stats *out) {
     __shared__ uint64_t s[kRedBlock];
     uint64_t *o = reinterpret_cast<uint64_t *>(out);
-    for (int i = 0; i < kStatWords; ++i) {
-        uint64_t v = 0;
-        double d = 0.0;
-        for (int b = threadIdx.x; b < n_blocks; b += kRedBlock) {
-            uint64_t x = part[(int64_t)b * kStatWords + i];
-            if (i < kStatFirstDouble) v += x;
-            else d += __longlong_as_double(x);
-        }
-        s[threadIdx.x] = i < kStatFirstDouble ? v : __double_as_longlong(d);
-        __syncthreads();
-        for (int h = kRedBlock / 2; h > 0; h >>= 1) {
-            if (threadIdx.x < h) {
-                if (i < kStatFirstDouble)
-                    s[threadIdx.x] += s[threadIdx.x + h];
-                else
-                    s[threadIdx.x] = __double_as_longlong(
-                        __longlong_as_double(s[threadIdx.x]) +
-                        __longlong_as_double(s[threadIdx.x + h]));
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (i < kStatFirstDouble) o[i] += s[0];
-            else o[i] = __double_as_longlong(__longlong_as_double(o[i]) +
-                                             __longlong_as_double(s[0]));
+    const int i = blockIdx.x;   // one statistics word per block
+    const bool is_int = i < kStatFirstDouble;
+    uint64_t v = 0;
+    double d = 0.0;
+    for (int b = threadIdx.x; b < n_blocks; b += kRedBlock) {
+        uint64_t x = part[(int64_t)b * kStatWords + i];
+        if (is_int) v += x;
+        else d += __longlong_as_double(x);
+    }
+    s[threadIdx.x] = is_int ? v : (uint64_t)__double_as_longlong(d);
+    __syncthreads();
+    for (int h = kRedBlock / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            if (is_int)
+                s[threadIdx.x] += s[threadIdx.x + h];
+            else
+                s[threadIdx.x] = __double_as_longlong(
+                    __longlong_as_double(s[threadIdx.x]) +
+                    __longlong_as_double(s[threadIdx.x + h]));
         }
         __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (is_int) o[i] += s[0];
+        else o[i] = __double_as_longlong(__longlong_as_double(o[i]) +
+                                         __longlong_as_double(s[0]));
     }
 }
 }  // namespace
 
 psl_status stats_reduce(const uint64_t *part, int n_blocks, psl_stats *out,
                         hipStream_t st) {
-    hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(kRedBlock), 0, st, part,
-                       n_blocks, out);
+    hipLaunchKernelGGL(k_stats_reduce, dim3(kStatWords), dim3(kRedBlock), 0,
+                       st, part, n_blocks, out);
     PSL_LAUNCHED();
     return PSL_OK;
 }

@@ -136,47 +136,46 @@ __global__ void k_field_totals(const FieldDev *__restrict__ fields,
     }
 }
 
-// N_ik = floor(N_i S_k / C_i) - floor(N_i S_k-1 / C_i); one block per field,
-// a block scan over the keys in chunks.
-__global__ void __launch_bounds__(kAllocBlock)
-k_key_alloc(const FieldDev *__restrict__ fields, const int64_t *__restrict__ off,
-            int64_t n_keys, int P, const uint8_t *__restrict__ mask,
-            const int64_t *__restrict__ C, const int64_t *__restrict__ NF,
-            const double *__restrict__ mu_tot, int64_t *__restrict__ N,
-            double *__restrict__ g) {
+// Selected population per (field, key): sel_ik * n_k.
+__global__ void k_masked_counts(const int64_t *__restrict__ off,
+                                int64_t n_keys, int P, int n_fields,
+                                const uint8_t *__restrict__ mask,
+                                int64_t *__restrict__ v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_fields * n_keys) return;
+    const int64_t f = i / n_keys, k = i % n_keys;
+    v[i] = mask[f * P + k % P] ? off[k + 1] - off[k] : 0;
+}
+
+// N_ik = floor(N_i S_k / C_i) - floor(N_i S_k-1 / C_i), S the running
+// selected population of field i in key order (from a device-wide exclusive
+// scan Pm of the masked counts v); g_ik = (MU_i / MU_tot) n_k / N_ik.
+__global__ void k_key_alloc(const FieldDev *__restrict__ fields,
+                            const int64_t *__restrict__ off, int64_t n_keys,
+                            int n_fields, const int64_t *__restrict__ v,
+                            const int64_t *__restrict__ Pm,
+                            const int64_t *__restrict__ C,
+                            const int64_t *__restrict__ NF,
+                            const double *__restrict__ mu_tot,
+                            int64_t *__restrict__ N, double *__restrict__ g) {
 #pragma clang fp contract(off)
-    __shared__ uint64_t s_wave[kAllocBlock / 64];
-    const int f = blockIdx.x;
-    const uint8_t *m = mask + (int64_t)f * P;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n_fields * n_keys) return;
+    const int64_t f = i / n_keys, k = i % n_keys;
     const uint64_t Cf = (uint64_t)C[f];
     const uint64_t Ni = (uint64_t)NF[f];
-    const double wmu = fields[f].MU / *mu_tot;
-    uint64_t carry = 0;
-    for (int64_t k0 = 0; k0 < n_keys; k0 += kAllocBlock) {
-        int64_t k = k0 + threadIdx.x;
-        uint64_t nk = 0;
-        bool sel = false;
-        if (k < n_keys) {
-            nk = (uint64_t)(off[k + 1] - off[k]);
-            sel = m[k % P] != 0;
-        }
-        uint64_t v = sel ? nk : 0;
-        uint64_t tot;
-        uint64_t ex = block_exclusive_scan<kAllocBlock>(v, &tot, s_wave);
-        if (k < n_keys) {
-            int64_t idx = (int64_t)f * n_keys + k;
-            int64_t Nik = 0;
-            if (sel && Cf > 0) {
-                uint64_t Sk = carry + ex + v, Sp = carry + ex;
-                uint64_t a = (uint64_t)(((unsigned __int128)Ni * Sk) / Cf);
-                uint64_t b = (uint64_t)(((unsigned __int128)Ni * Sp) / Cf);
-                Nik = (int64_t)(a - b);
-            }
-            N[idx] = Nik;
-            g[idx] = Nik > 0 ? wmu * ((double)nk / (double)Nik) : 0.0;
-        }
-        carry += tot;
+    const uint64_t vi = (uint64_t)v[i];
+    int64_t Nik = 0;
+    if (vi > 0 && Cf > 0) {
+        const uint64_t Sp = (uint64_t)(Pm[i] - Pm[f * n_keys]);
+        const uint64_t Sk = Sp + vi;
+        const uint64_t a = (uint64_t)(((unsigned __int128)Ni * Sk) / Cf);
+        const uint64_t b = (uint64_t)(((unsigned __int128)Ni * Sp) / Cf);
+        Nik = (int64_t)(a - b);
     }
+    N[i] = Nik;
+    const double nk = (double)(off[k + 1] - off[k]);
+    g[i] = Nik > 0 ? (fields[f].MU / *mu_tot) * (nk / (double)Nik) : 0.0;
 }
 
 // Per PSL: particles read by earlier fields of a batch, and per batch.
@@ -515,9 +514,19 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
     hipLaunchKernelGGL(k_field_totals, dim3(1), dim3(1), 0, st, w.fields,
                        n_fields, w.C, cfg->alloc_mode, cfg->n_histories, w.NF,
                        w.mu_tot);
-    hipLaunchKernelGGL(k_key_alloc, dim3(n_fields), dim3(kAllocBlock), 0, st,
-                       w.fields, d_offsets, n_keys, P, mask, w.C, w.NF,
-                       w.mu_tot, N, w.g);
+    {
+        // masked counts in H, their scan in `before` (both rewritten below)
+        const int64_t nr = (int64_t)n_fields * n_keys;
+        const unsigned nb = (unsigned)((nr + 255) / 256);
+        hipLaunchKernelGGL(k_masked_counts, dim3(nb), dim3(256), 0, st,
+                           d_offsets, n_keys, P, n_fields, mask, w.H);
+        if ((s = exclusive_scan<int64_t, int64_t>(w.H, w.before, nr, w.chunks,
+                                                  nullptr, st)))
+            return s;
+        hipLaunchKernelGGL(k_key_alloc, dim3(nb), dim3(256), 0, st, w.fields,
+                           d_offsets, n_keys, n_fields, w.H, w.before, w.C,
+                           w.NF, w.mu_tot, N, w.g);
+    }
     hipLaunchKernelGGL(k_cursor, dim3((unsigned)((n_keys + 255) / 256)),
                        dim3(256), 0, st, N, n_fields, n_keys, w.before, w.T);
     const int64_t n_ranges = (int64_t)n_fields * n_keys;

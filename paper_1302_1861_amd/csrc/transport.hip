@@ -1,17 +1,26 @@
 // transport_batch and psl_physics_init: photon and electron transport with
 // per-voxel energy tallies.
 //
-//   k_photons    persistent grid; each wave takes 64 queued photons at a
-//                time.  Woodcock free flights against rho_max, Compton
-//                scattering (Butcher-Messel sampling of Klein-Nishina),
-//                recoil electrons pushed with one atomic per wave and
-//                energy bucket; the attenuation table lives in LDS.
-//   k_electrons  persistent grid over the electron buckets from the highest
-//                energy down, so a wave holds electrons of similar range.
-//                CSDA steps split at voxel faces; the energy after a piece
-//                comes from the residual-range table and its inverse in
-//                LDS; consecutive deposits into one voxel are merged before
-//                the atomic; Highland deflection after each step.
+// Both transport kernels run a persistent grid in which every lane owns one
+// particle at a time and refills itself as soon as its particle is done:
+// the lanes that need work claim a contiguous run of queue items with one
+// atomic per wave on one of 64 counters that split the queue, so waves stay
+// full however unequal particle lifetimes are.
+//
+//   k_photons    Woodcock free flights against rho_max; Compton scattering
+//                sampled by Butcher and Messel's mixture-rejection method;
+//                recoil electrons above the cut-off go into a dense stream
+//                of 64-slot chunks that each wave claims from partitioned
+//                counters (holes only at the end of a wave's last chunk);
+//                the attenuation table is staged in LDS.
+//   rebucket     (optional) ballot-ranked compaction of that stream into the
+//                electron energy buckets, after the source electrons.
+//   k_electrons  CSDA steps split at voxel faces; the energy after each
+//                piece comes from the residual-range table and its inverse
+//                in LDS; deposits into one voxel are merged before the
+//                atomic; Highland deflection after each step.  Work is the
+//                electron buckets from the highest energy down, then (when
+//                not re-bucketed) the secondary stream.
 #include "common.hpp"
 #include "compact.hpp"
 
@@ -75,7 +84,7 @@ struct PhDev {
 };
 
 struct PhysDev {
-    float step, p_cut, t_cut, X0, pbc_me;
+    float step, p_cut, t_cut, X0;
     int flags;
 };
 
@@ -88,7 +97,7 @@ __device__ __forceinline__ float lerp_tab(const float *t, int n, float x) {
 
 template <int MODE>
 __device__ __forceinline__ void tally(void *acc, int64_t v, float e, float wt,
-                                      double scale, uint64_t &n_dep) {
+                                      double scale, uint32_t &n_dep) {
     ++n_dep;
     if (MODE == PSL_ACC_FIXED64) {
         double q = (double)e * (double)wt * scale + 0.5;
@@ -105,9 +114,9 @@ __device__ __forceinline__ void rotate(float &u, float &v, float &w, float ct,
     float s2 = 1.0f - w * w;
     float nu, nv, nw;
     if (s2 > 1e-10f) {
-        float s = sqrtf(s2);
-        nu = u * ct + st * (u * w * cp - v * sp) / s;
-        nv = v * ct + st * (v * w * cp + u * sp) / s;
+        float s = sqrtf(s2), is = 1.0f / s;
+        nu = u * ct + st * (u * w * cp - v * sp) * is;
+        nv = v * ct + st * (v * w * cp + u * sp) * is;
         nw = w * ct - st * cp * s;
     } else {
         nu = st * cp;
@@ -129,38 +138,106 @@ __device__ __forceinline__ bool voxel_of(const PhDev &P, float x, float y,
            (unsigned)iz < (unsigned)P.nz;
 }
 
-struct Items {
-    psl_particles p;
-    int32_t n_b;
-    int64_t cap_b;
-    uint32_t *counts;   // [0] photons, [1 + b] electron buckets
-};
-
-// Secondary-electron slots of the photon kernel: photon i owns slots
-// spill_cap + i * kSecPerPhoton + j; further secondaries go to the spill
-// slots [0, spill_cap) through one counter.
-constexpr int kSecPerPhoton = 6;
-
-struct SecSlots {
-    Slots s;
-    int64_t spill_cap;
-    uint32_t *spill_n;
-};
-
-__device__ __forceinline__ void put_slot(const Slots &S, int64_t k, float E,
-                                         float x, float y, float z, float u,
-                                         float v, float w, float wt,
-                                         uint64_t uid, uint32_t ctr,
-                                         uint8_t code) {
-    S.p.E[k] = E; S.p.x[k] = x; S.p.y[k] = y; S.p.z[k] = z;
-    S.p.u[k] = u; S.p.v[k] = v; S.p.w[k] = w; S.p.wt[k] = wt;
-    S.p.uid[k] = uid; S.p.ctr[k] = ctr;
-    S.code[k] = code;
+// ---------------------------------------------------------- work claims ---
+// Items [0, n) are split into kParts contiguous partitions with one
+// counter each (kPartStride apart).  A wave asks for `want` items from its
+// current partition; it gets a contiguous run [*base, *base + got) of at
+// most `want`, or moves to the next partition when the current one is
+// drained.  Returns false once all partitions are drained.  Wave-uniform.
+__device__ __forceinline__ bool claim_items(uint32_t *ctr, int64_t n,
+                                            int want, int &part, int &tried,
+                                            int64_t &base, int &got) {
+    const int64_t len = (n + kParts - 1) / kParts;
+    while (tried < kParts) {
+        const int64_t p0 = (int64_t)part * len;
+        const int64_t p1 = p0 + len < n ? p0 + len : n;
+        uint32_t old = 0;
+        if (__lane_id() == 0 && p0 < p1)
+            old = atomicAdd(&ctr[part * kPartStride], (uint32_t)want);
+        old = __shfl(old, 0);
+        const int64_t b = p0 + old;
+        if (p0 < p1 && b < p1) {
+            base = b;
+            got = (int)((p1 - b) < want ? (p1 - b) : want);
+            return true;
+        }
+        part = (part + 1) % kParts;
+        ++tried;
+    }
+    return false;
 }
 
+// Dense output stream of secondary electrons: 64-slot chunks claimed per
+// wave from kParts partitions of the chunk space.
+struct SecStream {
+    Slots s;
+    int64_t n_chunks;
+    uint32_t *chunk_ctr;     // kParts counters, kPartStride apart
+    uint32_t *chunks_used;   // number of chunks claimed (max index + 1)
+};
+
+// Wave-uniform cursor into the wave's current chunk.
+struct SecCursor {
+    int64_t base = -1;   // first slot of the current chunk (-1: none)
+    int fill = 64;       // slots used in it
+    int part, tried = 0;
+};
+
+__device__ __forceinline__ int64_t new_chunk(const SecStream &S,
+                                             SecCursor &c) {
+    const int64_t len = (S.n_chunks + kParts - 1) / kParts;
+    while (c.tried < kParts) {
+        const int64_t p0 = (int64_t)c.part * len;
+        const int64_t p1 = p0 + len < S.n_chunks ? p0 + len : S.n_chunks;
+        uint32_t old = 0;
+        if (__lane_id() == 0 && p0 < p1)
+            old = atomicAdd(&S.chunk_ctr[c.part * kPartStride], 1u);
+        old = __shfl(old, 0);
+        if (p0 + (int64_t)old < p1) {
+            const int64_t ch = p0 + old;
+            if (__lane_id() == 0) atomicMax(S.chunks_used, (uint32_t)(ch + 1));
+            return ch * 64;
+        }
+        c.part = (c.part + 1) % kParts;
+        ++c.tried;
+    }
+    return -1;
+}
+
+// Reserve one slot for each lane with `want`; -1 if the stream is full.
+__device__ __forceinline__ int64_t sec_reserve(const SecStream &S,
+                                               SecCursor &c, bool want) {
+    const uint64_t m = __ballot(want);
+    if (!m) return -1;
+    const int cnt = __popcll(m);
+    const int rank = __popcll(m & lanemask_lt());
+    const int left = 64 - c.fill;
+    int64_t slot = -1;
+    if (cnt <= left) {
+        if (want && c.base >= 0) slot = c.base + c.fill + rank;
+        c.fill += cnt;
+    } else {
+        if (want && rank < left && c.base >= 0) slot = c.base + c.fill + rank;
+        const int64_t nb = new_chunk(S, c);
+        if (want && rank >= left && nb >= 0) slot = nb + (rank - left);
+        c.base = nb;
+        c.fill = cnt - left;
+    }
+    return slot;
+}
+
+// Marks the unused tail of the wave's last chunk empty.
+__device__ __forceinline__ void sec_close(const SecStream &S,
+                                          const SecCursor &c) {
+    if (c.base >= 0 && (int)__lane_id() >= c.fill)
+        S.s.code[c.base + __lane_id()] = kEmpty;
+}
+
+// ---------------------------------------------------------------- photons -
 template <int MODE>
-__global__ void __launch_bounds__(kBlock)
-k_photons(Items ph, SecSlots sec, psl_queue qcfg, PhDev P, PhysDev Y,
+__global__ void __launch_bounds__(kBlock, 5)
+k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
+          SecStream sec, psl_queue qcfg, PhDev P, PhysDev Y,
           const float *__restrict__ tables, uint64_t seed, void *acc,
           double scale, uint32_t *work, uint64_t *part) {
     __shared__ float s_mu[kTabMu];
@@ -172,189 +249,228 @@ k_photons(Items ph, SecSlots sec, psl_queue qcfg, PhDev P, PhysDev Y,
     if (threadIdx.x <= PSL_MAX_QBUCKETS)
         s_bk[threadIdx.x] = qcfg.e_bucket_edges[threadIdx.x];
     __syncthreads();
-    const int64_t n = (int64_t)ph.counts[0];
-    const int64_t n_chunks = (n + 63) / 64;
-    StatAcc st;
-    st.zero();
-    uint64_t n_dep = 0;
-    int part_i = (int)((blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) %
-                       kParts),
-        tried = 0;
+    const int64_t n = (int64_t)counts[0];
+    const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    uint32_t c_int = 0, c_sec = 0, c_fl = 0, c_run = 0, c_lost = 0, c_dep = 0;
+    double e_esc = 0.0, e_killed = 0.0;
+    int part_i = wave % kParts, tried = 0;
+    bool more = true;
+    SecCursor cur;
+    cur.part = wave % kParts;
+    bool alive = false;
+    float E = 0, x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, wt = 0, mu1 = 0;
+    uint64_t uid = 0;
+    int flights = 0;
+    Rng rng;
+    rng.init(seed, 0, 0u, 0u, 0u);
     for (;;) {
-        const int64_t chunk = claim_chunk(work, n_chunks, part_i, tried);
-        if (chunk < 0) break;
-        const int64_t i = chunk * 64 + __lane_id();
-        bool alive = i < n;
-        float E = 0, x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, wt = 0;
-        uint64_t uid = 0;
-        Rng rng;
-        if (alive) {
-            E = ph.p.E[i]; x = ph.p.x[i]; y = ph.p.y[i]; z = ph.p.z[i];
-            u = ph.p.u[i]; v = ph.p.v[i]; w = ph.p.w[i]; wt = ph.p.wt[i];
-            uid = ph.p.uid[i];
-            rng.init(seed, uid, 0u, 0u, ph.p.ctr[i]);
-        }
-        float mu1 = alive ? lerp_tab(s_mu, kTabMu,
-                                     (__logf(E) - H.mu_lnE0) * H.mu_inv_dlnE)
-                          : 0.0f;
-        int flights = 0, n_sec = 0;
-        while (__ballot(alive)) {
-            bool push_e = false;
-            float Te = 0, eu = 0, ev = 0, ew = 0;
-            uint32_t birth = 0;
-            if (alive && E < Y.p_cut) {
-                int ix, iy, iz;
-                if (voxel_of(P, x, y, z, ix, iy, iz))
-                    tally<MODE>(acc, ((int64_t)iz * P.ny + iy) * P.nx + ix, E,
-                                wt, scale, n_dep);
-                else
-                    st.addf(PSL_STAT(e_escaped), (double)E * wt);
-                alive = false;
+        // refill the lanes whose photon is done
+        const uint64_t need = __ballot(!alive);
+        if (need && more) {
+            int64_t base = 0;
+            int got = 0;
+            more = claim_items(work, n, __popcll(need), part_i, tried, base,
+                               got);
+            const int rank = __popcll(need & lanemask_lt());
+            if (more && !alive && rank < got) {
+                const int64_t i = base + rank;
+                E = ph.E[i]; x = ph.x[i]; y = ph.y[i]; z = ph.z[i];
+                u = ph.u[i]; v = ph.v[i]; w = ph.w[i]; wt = ph.wt[i];
+                uid = ph.uid[i];
+                rng.init(seed, uid, 0u, 0u, ph.ctr[i]);
+                mu1 = lerp_tab(s_mu, kTabMu,
+                               (__logf(E) - H.mu_lnE0) * H.mu_inv_dlnE);
+                flights = 0;
+                alive = true;
             }
-            if (alive) {
-                // one free flight against the majorant
-                float s = -__logf(rng.next()) / (mu1 * P.rho_max);
-                x += s * u; y += s * v; z += s * w;
-                st.add(PSL_STAT(flights), 1);
-                int ix, iy, iz;
-                if (!voxel_of(P, x, y, z, ix, iy, iz)) {
-                    st.addf(PSL_STAT(e_escaped), (double)E * wt);
+        }
+        if (!__ballot(alive)) {
+            if (!more) break;
+            continue;
+        }
+        bool push_e = false;
+        float Te = 0, eu = 0, ev = 0, ew = 0;
+        uint32_t birth = 0;
+        if (alive && E < Y.p_cut) {
+            int ix, iy, iz;
+            if (voxel_of(P, x, y, z, ix, iy, iz))
+                tally<MODE>(acc, ((int64_t)iz * P.ny + iy) * P.nx + ix, E, wt,
+                            scale, c_dep);
+            else
+                e_esc += (double)E * wt;
+            alive = false;
+        }
+        if (alive) {
+            // one free flight against the majorant
+            const float s = -__logf(rng.next()) / (mu1 * P.rho_max);
+            x += s * u; y += s * v; z += s * w;
+            ++c_fl;
+            int ix, iy, iz;
+            if (!voxel_of(P, x, y, z, ix, iy, iz)) {
+                e_esc += (double)E * wt;
+                alive = false;
+            } else {
+                const int64_t vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
+                if (++flights > kMaxFlights) {
+                    ++c_run;
+                    tally<MODE>(acc, vox, E, wt, scale, c_dep);
                     alive = false;
-                } else {
-                    const int64_t vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
-                    if (++flights > kMaxFlights) {
-                        st.add(PSL_STAT(runaway), 1);
-                        tally<MODE>(acc, vox, E, wt, scale, n_dep);
+                } else if (rng.next() * P.rho_max <= P.rho[vox]) {
+                    // Compton: Butcher-Messel sampling of eps = E'/E
+                    const float k = E / kME;
+                    const float e0 = 1.0f / (1.0f + 2.0f * k);
+                    const float e0sq = e0 * e0;
+                    const float a1 = -__logf(e0), a2 = 0.5f * (1.0f - e0sq);
+                    float eps, onecost, sint2, phi_u;
+                    for (int tries = 0;; ++tries) {
+                        const float r1 = rng.next(), r2 = rng.next(),
+                                    r3 = rng.next();
+                        phi_u = rng.next();
+                        float epssq;
+                        if (r1 * (a1 + a2) < a1) {
+                            eps = __expf(-a1 * r2);
+                            epssq = eps * eps;
+                        } else {
+                            epssq = e0sq + (1.0f - e0sq) * r2;
+                            eps = sqrtf(epssq);
+                        }
+                        onecost = (1.0f - eps) / (eps * k);
+                        sint2 = onecost * (2.0f - onecost);
+                        const float gr = 1.0f - eps * sint2 / (1.0f + epssq);
+                        if (gr >= r3 || tries > 1000) break;
+                    }
+                    ++c_int;
+                    const float cost = 1.0f - onecost;
+                    const float sint = sqrtf(fmaxf(sint2, 0.0f));
+                    float sp, cp;
+                    __sincosf(2.0f * kPI * phi_u, &sp, &cp);
+                    const float Es = eps * E;
+                    const float T = E - Es;
+                    const float pu = u, pv = v, pw = w;
+                    rotate(u, v, w, cost, sint, cp, sp);
+                    if (T > Y.t_cut && !(Y.flags & PSL_FLAG_FIRST_COLLISION)) {
+                        const float qx = E * pu - Es * u, qy = E * pv - Es * v,
+                                    qz = E * pw - Es * w;
+                        const float rq = rsqrtf(qx * qx + qy * qy + qz * qz);
+                        push_e = true;
+                        Te = T;
+                        eu = qx * rq; ev = qy * rq; ew = qz * rq;
+                        birth = rng.n;
+                    } else {
+                        tally<MODE>(acc, vox, T, wt, scale, c_dep);
+                    }
+                    if (Y.flags & PSL_FLAG_FIRST_COLLISION) {
+                        e_killed += (double)Es * wt;
                         alive = false;
-                    } else if (rng.next() * P.rho_max <= P.rho[vox]) {
-                        // Compton: Butcher-Messel sampling of eps = E'/E
-                        float k = E / kME;
-                        float e0 = 1.0f / (1.0f + 2.0f * k);
-                        float e0sq = e0 * e0;
-                        float a1 = -__logf(e0), a2 = 0.5f * (1.0f - e0sq);
-                        float eps, onecost, sint2, phi_u;
-                        for (int tries = 0;; ++tries) {
-                            float r1 = rng.next(), r2 = rng.next(),
-                                  r3 = rng.next();
-                            phi_u = rng.next();
-                            float epssq;
-                            if (r1 * (a1 + a2) < a1) {
-                                eps = __expf(-a1 * r2);
-                                epssq = eps * eps;
-                            } else {
-                                epssq = e0sq + (1.0f - e0sq) * r2;
-                                eps = sqrtf(epssq);
-                            }
-                            onecost = (1.0f - eps) / (eps * k);
-                            sint2 = onecost * (2.0f - onecost);
-                            float gr = 1.0f - eps * sint2 / (1.0f + epssq);
-                            if (gr >= r3 || tries > 1000) break;
-                        }
-                        st.add(PSL_STAT(interactions), 1);
-                        float cost = 1.0f - onecost;
-                        float sint = sqrtf(fmaxf(sint2, 0.0f));
-                        float sp, cp;
-                        __sincosf(2.0f * kPI * phi_u, &sp, &cp);
-                        float Es = eps * E;
-                        float T = E - Es;
-                        float pu = u, pv = v, pw = w;
-                        rotate(u, v, w, cost, sint, cp, sp);
-                        if (T > Y.t_cut &&
-                            !(Y.flags & PSL_FLAG_FIRST_COLLISION)) {
-                            float qx = E * pu - Es * u, qy = E * pv - Es * v,
-                                  qz = E * pw - Es * w;
-                            float rq = rsqrtf(qx * qx + qy * qy + qz * qz);
-                            push_e = true;
-                            Te = T;
-                            eu = qx * rq; ev = qy * rq; ew = qz * rq;
-                            birth = rng.n;
-                        } else {
-                            tally<MODE>(acc, vox, T, wt, scale, n_dep);
-                        }
-                        if (Y.flags & PSL_FLAG_FIRST_COLLISION) {
-                            st.addf(PSL_STAT(e_killed), (double)Es * wt);
-                            alive = false;
-                        } else {
-                            E = Es;
-                            mu1 = lerp_tab(s_mu, kTabMu,
-                                           (__logf(E) - H.mu_lnE0) *
-                                               H.mu_inv_dlnE);
-                        }
+                    } else {
+                        E = Es;
+                        mu1 = lerp_tab(s_mu, kTabMu,
+                                       (__logf(E) - H.mu_lnE0) * H.mu_inv_dlnE);
                     }
                 }
             }
-            // recoil electron: own slot, or a spill slot past kSecPerPhoton
-            const bool spill = push_e && n_sec >= kSecPerPhoton;
-            uint32_t sslot = wave_reserve(sec.spill_n, 0, spill);
-            if (push_e) {
+        }
+        // recoil electrons into the dense secondary stream
+        const int64_t slot = sec_reserve(sec, cur, push_e);
+        if (push_e) {
+            if (slot >= 0) {
                 int b = 0;
                 for (int j = 1; j < qcfg.n_ebuckets; ++j)
                     if (Te >= s_bk[j]) b = j;
-                int64_t k = -1;
-                if (!spill)
-                    k = sec.spill_cap + i * kSecPerPhoton + n_sec;
-                else if ((int64_t)sslot < sec.spill_cap)
-                    k = sslot;
-                if (k >= 0) {
-                    put_slot(sec.s, k, Te, x, y, z, eu, ev, ew, wt, uid, birth,
-                             (uint8_t)(1 + b));
-                    st.add(PSL_STAT(secondaries), 1);
-                } else {
-                    st.add(PSL_STAT(lost), 1);
-                }
-                ++n_sec;
+                const Slots &S = sec.s;
+                S.p.E[slot] = Te; S.p.x[slot] = x; S.p.y[slot] = y;
+                S.p.z[slot] = z; S.p.u[slot] = eu; S.p.v[slot] = ev;
+                S.p.w[slot] = ew; S.p.wt[slot] = wt; S.p.uid[slot] = uid;
+                S.p.ctr[slot] = birth;
+                S.code[slot] = (uint8_t)(1 + b);
+                ++c_sec;
+            } else {
+                ++c_lost;
             }
         }
-        // mark this photon's unused secondary slots empty
-        if (i < n)
-            for (int j = n_sec; j < kSecPerPhoton; ++j)
-                sec.s.code[sec.spill_cap + i * kSecPerPhoton + j] = kEmpty;
     }
-    st.add(PSL_STAT(photon_deposits), n_dep);
+    sec_close(sec, cur);
+    StatAcc st;
+    st.zero();
+    st.add(PSL_STAT(interactions), c_int);
+    st.add(PSL_STAT(secondaries), c_sec);
+    st.add(PSL_STAT(flights), c_fl);
+    st.add(PSL_STAT(runaway), c_run);
+    st.add(PSL_STAT(lost), c_lost);
+    st.add(PSL_STAT(photon_deposits), c_dep);
+    st.addf(PSL_STAT(e_escaped), e_esc);
+    st.addf(PSL_STAT(e_killed), e_killed);
     block_stats_write(st, s_red, part);
 }
 
+// -------------------------------------------------------------- electrons -
+// Work list: the electron bucket regions from the highest bucket down, then
+// (optionally) a raw stream of slots whose empty entries are skipped.
+struct ElWork {
+    psl_particles el;
+    int32_t n_b;
+    int64_t cap_b;
+    const uint32_t *counts;
+    Slots raw;                  // raw.code == nullptr: no raw stream
+    const uint32_t *raw_chunks; // chunks used in the raw stream
+};
+
 template <int MODE>
-__global__ void __launch_bounds__(kBlock)
-k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
+__global__ void __launch_bounds__(kBlock, 6)
+k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
             uint64_t seed, void *acc, double scale, uint32_t *work,
             uint64_t *part) {
     __shared__ float s_rng[kTabRange];
     __shared__ float s_inv[kTabInv];
     __shared__ uint64_t s_red[(kBlock / 64) * kStatWords];
+    __shared__ int64_t s_cnt[PSL_MAX_QBUCKETS + 1];
     const TableHeader H = *reinterpret_cast<const TableHeader *>(tables);
     const float *g = tables + kTabHeaderBytes / 4 + kTabMu;
     for (int i = threadIdx.x; i < kTabRange; i += kBlock) s_rng[i] = g[i];
     for (int i = threadIdx.x; i < kTabInv; i += kBlock)
         s_inv[i] = g[kTabRange + i];
-    // bucket sizes (clamped to the region capacity), highest energy first
-    __shared__ int64_t s_cnt[PSL_MAX_QBUCKETS];
-    if (threadIdx.x < PSL_MAX_QBUCKETS) {
-        int64_t c = threadIdx.x < el.n_b
-                        ? (int64_t)el.counts[1 + threadIdx.x] : 0;
-        s_cnt[threadIdx.x] = c < el.cap_b ? c : el.cap_b;
+    // segment sizes in processing order: buckets high to low, then raw
+    if (threadIdx.x <= PSL_MAX_QBUCKETS) {
+        int64_t c = 0;
+        if (threadIdx.x < W.n_b) {
+            const int b = W.n_b - 1 - threadIdx.x;
+            c = (int64_t)W.counts[1 + b];
+            c = c < W.cap_b ? c : W.cap_b;
+        } else if (threadIdx.x == W.n_b && W.raw.code) {
+            c = (int64_t)(*W.raw_chunks) * 64;
+        }
+        s_cnt[threadIdx.x] = c;
     }
     __syncthreads();
     int64_t total = 0;
-    for (int b = 0; b < el.n_b; ++b) total += s_cnt[b];
-    const int64_t n_chunks = (total + 63) / 64;
-    StatAcc st;
-    st.zero();
-    uint64_t n_dep = 0;
-    int part_i = (int)((blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) %
-                       kParts),
-        tried = 0;
+    for (int b = 0; b <= W.n_b; ++b) total += s_cnt[b];
+    const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    uint32_t c_seg = 0, c_run = 0, c_dep = 0;
+    double e_esc = 0.0;
+    int part_i = wave % kParts, tried = 0;
+    // one electron per lane, followed to its end: the buckets keep the
+    // electrons of a wave at similar ranges
     for (;;) {
-        const int64_t chunk = claim_chunk(work, n_chunks, part_i, tried);
-        if (chunk < 0) break;
-        int64_t t = chunk * 64 + __lane_id();
-        if (t >= total) continue;
-        int b = el.n_b - 1;
-        while (t >= s_cnt[b]) { t -= s_cnt[b]; --b; }
-        const int64_t i = (int64_t)b * el.cap_b + t;
-        float T = el.p.E[i];
-        float x = el.p.x[i], y = el.p.y[i], z = el.p.z[i];
-        float u = el.p.u[i], v = el.p.v[i], w = el.p.w[i], wt = el.p.wt[i];
+        int64_t base = 0;
+        int got = 0;
+        if (!claim_items(work, total, 64, part_i, tried, base, got)) break;
+        if ((int)__lane_id() >= got) continue;
+        int64_t t = base + __lane_id();
+        int sgi = 0;
+        while (t >= s_cnt[sgi]) { t -= s_cnt[sgi]; ++sgi; }
+        const psl_particles *src;
+        int64_t i;
+        if (sgi < W.n_b) {
+            src = &W.el;
+            i = (int64_t)(W.n_b - 1 - sgi) * W.cap_b + t;
+        } else {
+            src = &W.raw.p;
+            i = t;
+            if (W.raw.code[i] == kEmpty) continue;
+        }
+        float T = src->E[i];
+        float x = src->x[i], y = src->y[i], z = src->z[i];
+        float u = src->u[i], v = src->v[i], w = src->w[i], wt = src->wt[i];
         // entry voxel; a point on the box surface belongs to the voxel
         // inside
         int ix = (int)floorf((x - P.x0) * P.ix_);
@@ -362,7 +478,7 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
         int iz = (int)floorf((z - P.z0) * P.iz_);
         if (ix < -1 || iy < -1 || iz < -1 || ix > P.nx || iy > P.ny ||
             iz > P.nz) {
-            st.addf(PSL_STAT(e_escaped), (double)T * wt);
+            e_esc += (double)T * wt;
             continue;
         }
         ix = min(max(ix, 0), P.nx - 1);
@@ -370,11 +486,11 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
         iz = min(max(iz, 0), P.nz - 1);
         int64_t vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
         if (T <= Y.t_cut) {
-            tally<MODE>(acc, vox, T, wt, scale, n_dep);
+            tally<MODE>(acc, vox, T, wt, scale, c_dep);
             continue;
         }
         Rng rng;
-        rng.init(seed, el.p.uid[i], el.p.ctr[i], kElectronTag, 0u);
+        rng.init(seed, src->uid[i], src->ctr[i], kElectronTag, 0u);
         float r = lerp_tab(s_rng, kTabRange,
                            (__logf(T) - H.rng_lnT0) * H.rng_inv_dlnT);
         int64_t pv = vox;
@@ -382,41 +498,42 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
         int segs = 0;
         bool done = false;
         while (!done) {
-            float rem = Y.step, tm = 0.0f, T0 = T;
+            // one step of Y.step cm, split at voxel faces
+            float rem = Y.step, tm = 0.0f;
+            const float T0 = T;
             while (rem > 0.0f) {
-                float sx = u > 0.0f ? (P.x0 + (ix + 1) * P.dx - x) / u
-                         : u < 0.0f ? (P.x0 + ix * P.dx - x) / u : INFINITY;
-                float sy = v > 0.0f ? (P.y0 + (iy + 1) * P.dy - y) / v
-                         : v < 0.0f ? (P.y0 + iy * P.dy - y) / v : INFINITY;
-                float sz = w > 0.0f ? (P.z0 + (iz + 1) * P.dz - z) / w
-                         : w < 0.0f ? (P.z0 + iz * P.dz - z) / w : INFINITY;
+                const float sx = u > 0.0f ? (P.x0 + (ix + 1) * P.dx - x) / u
+                               : u < 0.0f ? (P.x0 + ix * P.dx - x) / u
+                                          : INFINITY;
+                const float sy = v > 0.0f ? (P.y0 + (iy + 1) * P.dy - y) / v
+                               : v < 0.0f ? (P.y0 + iy * P.dy - y) / v
+                                          : INFINITY;
+                const float sz = w > 0.0f ? (P.z0 + (iz + 1) * P.dz - z) / w
+                               : w < 0.0f ? (P.z0 + iz * P.dz - z) / w
+                                          : INFINITY;
                 int axis = 0;
                 float sb = sx;
                 if (sy < sb) { sb = sy; axis = 1; }
                 if (sz < sb) { sb = sz; axis = 2; }
                 sb = fmaxf(sb, 0.0f);
-                float seg = fminf(rem, sb);
-                float dm = P.rho[vox] * seg;
-                st.add(PSL_STAT(segments), 1);
+                const float seg = fminf(rem, sb);
+                const float dm = P.rho[vox] * seg;
+                ++c_seg;
+                if (vox != pv) {
+                    tally<MODE>(acc, pv, pe, wt, scale, c_dep);
+                    pv = vox;
+                    pe = 0.0f;
+                }
                 if (dm >= r || ++segs > kMaxSegments) {
-                    if (segs > kMaxSegments) st.add(PSL_STAT(runaway), 1);
-                    if (vox != pv) {
-                        tally<MODE>(acc, pv, pe, wt, scale, n_dep);
-                        pv = vox;
-                        pe = 0.0f;
-                    }
+                    if (segs > kMaxSegments) ++c_run;
                     pe += T;
                     T = 0.0f;
                     done = true;
                     break;
                 }
                 r -= dm;
-                float Tn = fminf(lerp_tab(s_inv, kTabInv, r * H.inv_inv_dr), T);
-                if (vox != pv) {
-                    tally<MODE>(acc, pv, pe, wt, scale, n_dep);
-                    pv = vox;
-                    pe = 0.0f;
-                }
+                const float Tn =
+                    fminf(lerp_tab(s_inv, kTabInv, r * H.inv_inv_dr), T);
                 pe += T - Tn;
                 T = Tn;
                 tm += dm;
@@ -424,14 +541,18 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 rem -= seg;
                 if (seg == sb) {
                     bool in;
-                    if (axis == 0) { ix += u > 0.0f ? 1 : -1;
-                                     in = (unsigned)ix < (unsigned)P.nx; }
-                    else if (axis == 1) { iy += v > 0.0f ? 1 : -1;
-                                          in = (unsigned)iy < (unsigned)P.ny; }
-                    else { iz += w > 0.0f ? 1 : -1;
-                           in = (unsigned)iz < (unsigned)P.nz; }
+                    if (axis == 0) {
+                        ix += u > 0.0f ? 1 : -1;
+                        in = (unsigned)ix < (unsigned)P.nx;
+                    } else if (axis == 1) {
+                        iy += v > 0.0f ? 1 : -1;
+                        in = (unsigned)iy < (unsigned)P.ny;
+                    } else {
+                        iz += w > 0.0f ? 1 : -1;
+                        in = (unsigned)iz < (unsigned)P.nz;
+                    }
                     if (!in) {
-                        st.addf(PSL_STAT(e_escaped), (double)T * wt);
+                        e_esc += (double)T * wt;
                         T = 0.0f;
                         done = true;
                         break;
@@ -439,13 +560,12 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                     vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
                 }
             }
-            if (done) break;
-            if (!(Y.flags & PSL_FLAG_NO_MSC) && tm > 0.0f) {
+            if (!done && !(Y.flags & PSL_FLAG_NO_MSC) && tm > 0.0f) {
                 // Highland angle from the pre-step energy and the step's
                 // mass thickness; space angle Rayleigh-distributed with
                 // scale theta0, truncated at pi
-                float pbc = T0 * (T0 + 2.0f * kME) / (T0 + kME);
-                float qq = tm / Y.X0;
+                const float pbc = T0 * (T0 + 2.0f * kME) / (T0 + kME);
+                const float qq = tm / Y.X0;
                 float th0 = 13.6f / pbc * sqrtf(qq) *
                             (1.0f + 0.038f * __logf(qq));
                 th0 = fmaxf(th0, 0.0f);
@@ -461,20 +581,28 @@ k_electrons(Items el, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 rotate(u, v, w, cth, sth, cp, sp);
             }
         }
-        if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale, n_dep);
+        if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale, c_dep);
     }
-    st.add(PSL_STAT(deposits), n_dep);
+    StatAcc st;
+    st.zero();
+    st.add(PSL_STAT(segments), c_seg);
+    st.add(PSL_STAT(runaway), c_run);
+    st.add(PSL_STAT(deposits), c_dep);
+    st.addf(PSL_STAT(e_escaped), e_esc);
     block_stats_write(st, s_red, part);
 }
 
-__global__ void k_transport_init(uint32_t *work, int n_words,
-                                 uint8_t *spill_code, int64_t spill_cap) {
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n_words;
-         i += gridDim.x * blockDim.x)
-        work[i] = 0;
+__global__ void k_transport_init(uint32_t *words, int n_words,
+                                 uint32_t *codes, int64_t n_code_words) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
-         i < spill_cap; i += (int64_t)gridDim.x * blockDim.x)
-        spill_code[i] = kEmpty;
+         i < n_words; i += stride)
+        words[i] = 0;
+    // every slot of the secondary stream starts empty
+    const uint32_t e4 = 0x01010101u * kEmpty;
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
+         i < n_code_words; i += stride)
+        codes[i] = e4;
 }
 
 __global__ void k_consume(uint32_t *counts) {
@@ -482,39 +610,46 @@ __global__ void k_consume(uint32_t *counts) {
 }
 
 struct TransportWs {
-    uint32_t *work;        // 2 work-claim arrays + spill counter
-    Slots sec;
+    uint32_t *words;     // photon claims, electron claims, chunk claims,
+                         // chunks used
+    int n_words;
+    SecStream sec;
     uint32_t *tiles;
     uint64_t *part;
-    int64_t spill_cap, n_slots;
     size_t bytes;
 };
 
-TransportWs carve_transport(void *base, int64_t ph_cap, int grid_blocks) {
+constexpr int kMaxGridBlocks = 16 * 1024;
+
+TransportWs carve_transport(void *base, int64_t el_cap) {
+    // el_cap: capacity of one electron bucket region
     Carver c(base);
     TransportWs w;
-    w.work = c.take<uint32_t>(2 * kParts * kPartStride + 64);
-    w.spill_cap = std::max<int64_t>(65536, ph_cap / 8);
-    w.n_slots = w.spill_cap + std::max<int64_t>(ph_cap, 1) * kSecPerPhoton;
-    w.sec.p.capacity = w.n_slots;
-    w.sec.p.E = c.take<float>(w.n_slots);
-    w.sec.p.x = c.take<float>(w.n_slots);
-    w.sec.p.y = c.take<float>(w.n_slots);
-    w.sec.p.z = c.take<float>(w.n_slots);
-    w.sec.p.u = c.take<float>(w.n_slots);
-    w.sec.p.v = c.take<float>(w.n_slots);
-    w.sec.p.w = c.take<float>(w.n_slots);
-    w.sec.p.wt = c.take<float>(w.n_slots);
-    w.sec.p.uid = c.take<uint64_t>(w.n_slots);
-    w.sec.p.ctr = c.take<uint32_t>(w.n_slots);
-    w.sec.code = c.take<uint8_t>(w.n_slots);
-    w.tiles = c.take<uint32_t>((int64_t)kMaxQ * compact_tiles(w.n_slots));
-    w.part = c.take<uint64_t>((int64_t)2 * grid_blocks * kStatWords);
+    w.n_words = 3 * kParts * kPartStride + 64;
+    w.words = c.take<uint32_t>(w.n_words);
+    // secondary stream: one slot per electron-queue entry plus one chunk per
+    // wave of the largest grid for partly filled chunks
+    const int64_t chunks = (std::max<int64_t>(el_cap, 64) + 63) / 64 +
+                           (int64_t)kMaxGridBlocks * (kBlock / 64);
+    const int64_t n = chunks * 64;
+    w.sec.n_chunks = chunks;
+    w.sec.s.p.capacity = n;
+    w.sec.s.p.E = c.take<float>(n);
+    w.sec.s.p.x = c.take<float>(n);
+    w.sec.s.p.y = c.take<float>(n);
+    w.sec.s.p.z = c.take<float>(n);
+    w.sec.s.p.u = c.take<float>(n);
+    w.sec.s.p.v = c.take<float>(n);
+    w.sec.s.p.w = c.take<float>(n);
+    w.sec.s.p.wt = c.take<float>(n);
+    w.sec.s.p.uid = c.take<uint64_t>(n);
+    w.sec.s.p.ctr = c.take<uint32_t>(n);
+    w.sec.s.code = c.take<uint8_t>(n);   // n is a multiple of 64
+    w.tiles = c.take<uint32_t>((int64_t)kMaxQ * compact_tiles(n));
+    w.part = c.take<uint64_t>((int64_t)2 * kMaxGridBlocks * kStatWords);
     w.bytes = c.used;
     return w;
 }
-
-constexpr int kMaxGridBlocks = 64 * 1024;
 
 }  // namespace
 }  // namespace psl
@@ -592,8 +727,8 @@ extern "C" psl_status psl_physics_init(const psl_physics *phys,
 }
 
 extern "C" size_t transport_batch_workspace_bytes(const psl_queue *q) {
-    if (!q) return 0;
-    return carve_transport(nullptr, q->ph.capacity, kMaxGridBlocks).bytes;
+    if (!q || q->n_ebuckets < 1) return 0;
+    return carve_transport(nullptr, q->el.capacity / q->n_ebuckets).bytes;
 }
 
 extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
@@ -622,7 +757,7 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     PSL_REQUIRE(phys->t_cut > 0 && phys->p_cut > 0 && phys->step > 0 &&
                     phys->X0 > 0,
                 "bad physics constants");
-    psl_launch L{kBlock, 8, 0, 0};
+    psl_launch L{kBlock, 8, 0, 1};
     if (launch) {
         PSL_REQUIRE(launch->block == kBlock,
                     "block must be %d in this build", kBlock);
@@ -630,6 +765,8 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
                     "blocks_per_cu outside 1..64");
         PSL_REQUIRE(launch->n_cu >= 0 && launch->n_cu <= 1024,
                     "n_cu outside 0..1024");
+        PSL_REQUIRE(launch->rebucket == 0 || launch->rebucket == 1,
+                    "rebucket must be 0 or 1");
         L = *launch;
     }
     if (!d_ws || ws_bytes < transport_batch_workspace_bytes(q)) {
@@ -641,57 +778,60 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     const int cu = L.n_cu > 0 ? L.n_cu : device_cu_count();
     const int blocks = std::min(cu * L.blocks_per_cu, kMaxGridBlocks);
     hipStream_t st = (hipStream_t)stream;
-    TransportWs w = carve_transport(d_ws, q->ph.capacity, kMaxGridBlocks);
+    TransportWs w = carve_transport(d_ws, q->el.capacity / q->n_ebuckets);
     PhDev P{ph->nx, ph->ny, ph->nz, (float)ph->x0, (float)ph->y0,
             (float)ph->z0, (float)ph->dx, (float)ph->dy, (float)ph->dz,
             (float)(1.0 / ph->dx), (float)(1.0 / ph->dy),
             (float)(1.0 / ph->dz), ph->rho_max, ph->density};
     PhysDev Y{(float)phys->step, (float)phys->p_cut, (float)phys->t_cut,
-              (float)phys->X0, 0.0f, phys->flags};
-    Items iph{q->ph, 1, q->ph.capacity, q->d_counts};
-    Items iel{q->el, q->n_ebuckets, q->el.capacity / q->n_ebuckets,
-              q->d_counts};
-    uint32_t *work_ph = w.work;
-    uint32_t *work_el = w.work + kParts * kPartStride;
-    uint32_t *spill_n = w.work + 2 * kParts * kPartStride;
-    SecSlots sec{w.sec, w.spill_cap, spill_n};
-    QueueRegions qr{q->ph, q->el, 1 + q->n_ebuckets,
-                    q->el.capacity / q->n_ebuckets, q->d_counts};
+              (float)phys->X0, phys->flags};
+    uint32_t *work_ph = w.words;
+    uint32_t *work_el = w.words + kParts * kPartStride;
+    w.sec.chunk_ctr = w.words + 2 * kParts * kPartStride;
+    w.sec.chunks_used = w.words + 3 * kParts * kPartStride;
+    const int64_t cap_b = q->el.capacity / q->n_ebuckets;
+    QueueRegions qr{q->ph, q->el, 1 + q->n_ebuckets, cap_b, q->d_counts};
     const float *tab = static_cast<const float *>(d_tables);
     const double scale =
         acc->mode == PSL_ACC_FIXED64 ? std::ldexp(1.0, acc->frac_bits) : 1.0;
     const bool fixed = acc->mode == PSL_ACC_FIXED64;
     dim3 grid((unsigned)blocks), block(kBlock);
-    hipLaunchKernelGGL(k_transport_init, dim3(256), dim3(256), 0, st, w.work,
-                       2 * kParts * kPartStride + 64, w.sec.code,
-                       w.spill_cap);
+    hipLaunchKernelGGL(k_transport_init, dim3(1024), dim3(256), 0, st,
+                       w.words, w.n_words,
+                       reinterpret_cast<uint32_t *>(w.sec.s.code),
+                       w.sec.s.p.capacity / 4);
     {
         ProfScope prof(PSL_PROF_PHOTONS, st);
         if (fixed)
             hipLaunchKernelGGL(k_photons<PSL_ACC_FIXED64>, grid, block, 0, st,
-                               iph, sec, *q, P, Y, tab, seed, acc->data,
-                               scale, work_ph, w.part);
+                               q->ph, q->d_counts, w.sec, *q, P, Y, tab, seed,
+                               acc->data, scale, work_ph, w.part);
         else
             hipLaunchKernelGGL(k_photons<PSL_ACC_F64>, grid, block, 0, st,
-                               iph, sec, *q, P, Y, tab, seed, acc->data,
-                               scale, work_ph, w.part);
+                               q->ph, q->d_counts, w.sec, *q, P, Y, tab, seed,
+                               acc->data, scale, work_ph, w.part);
     }
-    {
+    ElWork ew{q->el, q->n_ebuckets, cap_b, q->d_counts, Slots{}, nullptr};
+    if (L.rebucket) {
         ProfScope prof(PSL_PROF_REBUCKET, st);
-        if ((s = compact_slots(w.sec, w.n_slots, q->d_counts, kSecPerPhoton,
-                               w.spill_cap, qr, w.tiles, st)))
+        if ((s = compact_slots(w.sec.s, w.sec.s.p.capacity, w.sec.chunks_used,
+                               64, 0, qr, w.tiles, st)))
             return s;
+    } else {
+        ew.raw = w.sec.s;
+        ew.raw_chunks = w.sec.chunks_used;
     }
     {
         ProfScope prof(PSL_PROF_ELECTRONS, st);
+        uint64_t *part_el = w.part + (int64_t)blocks * kStatWords;
         if (fixed)
             hipLaunchKernelGGL(k_electrons<PSL_ACC_FIXED64>, grid, block, 0,
-                               st, iel, P, Y, tab, seed, acc->data, scale,
-                               work_el, w.part + (int64_t)blocks * kStatWords);
+                               st, ew, P, Y, tab, seed, acc->data, scale,
+                               work_el, part_el);
         else
             hipLaunchKernelGGL(k_electrons<PSL_ACC_F64>, grid, block, 0, st,
-                               iel, P, Y, tab, seed, acc->data, scale,
-                               work_el, w.part + (int64_t)blocks * kStatWords);
+                               ew, P, Y, tab, seed, acc->data, scale, work_el,
+                               part_el);
     }
     if ((s = stats_reduce(w.part, 2 * blocks, d_stats, st))) return s;
     hipLaunchKernelGGL(k_consume, dim3(1), dim3(64), 0, st, q->d_counts);

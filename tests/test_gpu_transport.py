@@ -176,9 +176,8 @@ def test_fixed_point_dose_independent_of_launch_shape():
     wl = S.workload_clinical(side=10.0, n_particles=500_000)
     wl.phantom = S.water_phantom((64, 64, 64), 0.5, (-16.0, -16.0, 100.0))
     out = []
-    for bpc in (1, 8, 3):
-        L = P.psl_launch()
-        L.block, L.blocks_per_cu, L.n_cu = 256, bpc, 0
+    for bpc, rb in ((1, 1), (8, 0), (3, 1), (5, 0)):
+        L = P.make_launch(blocks_per_cu=bpc, rebucket=rb)
         eng = _engine(wl, 300_000, launch=L)
         eng.sample(4)
         eng.transport(4)
