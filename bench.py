@@ -28,6 +28,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical_10x10.json")
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1302_1861_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel, launches_per_step):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE scaled by a plain copy of known size), or None
+    when the kernels changed since the counters were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != _source_hash() or kernel not in t["kernels"]:
+        return None
+    return t["kernels"][kernel]["bytes_per_launch"]
 
 
 def _algorithmic_bytes(group, st, nvox):
@@ -96,6 +120,9 @@ def main():
     ap.add_argument("--histories-per-step", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="device-to-device copy of this size before the "
+                         "timed region (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU "
@@ -113,6 +140,14 @@ def main():
     H = args.histories_per_step
     eng = P.Engine(wl, histories_per_batch=H)
     torch.cuda.synchronize()
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    atom_scatter, atom_same = P.bench_atomics(eng.nvox)
     for b in range(args.warmup):
         eng.step(b)
     torch.cuda.synchronize()
@@ -141,6 +176,12 @@ def main():
     nbytes = _algorithmic_bytes(dom, st, eng.nvox)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     kernel_ms = {g: round(v[0] / v[1], 4) for g, v in groups.items()}
+    # dose atomics of the transport kernels against the measured roof
+    t_tr = (groups.get("photons", (0, 1))[0] / groups.get("photons", (0, 1))[1]
+            + groups.get("electrons", (0, 1))[0]
+            / groups.get("electrons", (0, 1))[1]) * 1e-3
+    n_atom = st["deposits"] + st["photon_deposits"]
+    atomic_rate = n_atom / t_tr if t_tr > 0 else 0.0
 
     # time to 1% uncertainty from the timed steps (batches)
     d, s = eng.finalize()
@@ -175,10 +216,16 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm",
                      "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None,
+                     "traffic": _traffic(dom, 1),
                      "algorithmic_bytes_per_launch": nbytes,
                      "avg_launch_ms": avg_ms},
         "kernel_ms": kernel_ms,
+        "atomic_roofline": {"kernels": "photons+electrons",
+                            "achieved": atomic_rate, "peak": atom_scatter,
+                            "unit": "u64 atomic adds/s",
+                            "frac": atomic_rate / atom_scatter,
+                            "same_address_peak": atom_same,
+                            "atomics_per_step": n_atom},
         "batch_stats": {k: st[k] for k in (
             "histories", "photons", "electrons", "jaw_rejected",
             "interactions", "secondaries", "segments", "deposits",

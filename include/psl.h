@@ -166,6 +166,7 @@ typedef struct psl_stats {
     uint64_t runaway;           /* particles stopped by the loop guard       */
     uint64_t deposits;          /* dose atomics issued by electrons          */
     uint64_t photon_deposits;   /* dose atomics issued by photons            */
+    uint64_t bucket_peak;       /* largest electron bucket fill of the batch */
     double e_in;                /* sum E*wt of queued source particles       */
     double e_escaped;           /* sum E*wt leaving the phantom              */
     double e_killed;            /* sum E*wt of photons ended by              */
@@ -294,6 +295,8 @@ typedef struct psl_launch {
  * results do not depend on scheduling.  Photons are processed first, then
  * electron buckets from the highest energy down.  Queues are consumed
  * (counts zeroed).
+ * Secondary electrons are first written to a stream of at most
+ * 2 x ph.capacity entries (beyond that they are counted in stats.lost).
  * Errors: PSL_EINVAL (sizes, null pointers, bad acc mode), PSL_ENOSPC
  * (workspace too small).
  */
@@ -348,6 +351,135 @@ psl_status dose_tally(psl_dose_acc *acc, double *d_s1, double *d_s2,
  */
 psl_status psl_profile_enable(int32_t on);
 psl_status psl_profile_read(double *ms, int64_t *launches, int32_t reset);
+
+/* ------------------------------------------------------------------------ */
+/* Batched plans (many fields or segments, batch after batch).              */
+/* ------------------------------------------------------------------------ */
+typedef struct psl_plan psl_plan;   /* opaque, host-side */
+
+typedef struct psl_tune_result {
+    psl_launch launch;              /* chosen transport launch shape         */
+    int32_t n_ebuckets;             /* chosen electron bucket count          */
+    int32_t configs_tried;
+    float e_bucket_edges[PSL_MAX_QBUCKETS + 1];
+    double ms_per_batch;            /* sample + transport time of the choice */
+    int64_t el_capacity_suggested;  /* electron queue capacity that holds    */
+                                    /* the observed peak bucket with 25%     */
+                                    /* margin, for n_ebuckets buckets        */
+    int64_t bucket_peak;            /* observed peak bucket fill             */
+} psl_tune_result;
+
+/*
+ * psl_plan_create - a plan over n_fields fields or segments (for an IMRT
+ * plan: the segments of all beams, Sec. 2.3.3 and 2.4 treat each as a field
+ * with its jaws, MU and fluence map).  ROI selection and the allocation of
+ * Eq. (1)-(4) are computed once here, on `stream`; each batch of
+ * psl_plan_run is then psl_sample's per-history step, transport_batch and
+ * dose_tally(FOLD) into d_s1/d_s2, all in one persistent launch per kernel
+ * whatever the number of segments.  Buffers are as for the individual
+ * calls; d_ws holds psl_plan_workspace_bytes() and is owned by the plan
+ * until psl_plan_destroy.  *out receives a host handle.
+ */
+size_t psl_plan_workspace_bytes(const psl_grid *g, int32_t n_fields,
+                                int64_t n_histories, const psl_queue *q);
+psl_status psl_plan_create(psl_plan **out, const psl_phsp *sorted,
+                           const int64_t *d_offsets, const psl_grid *g,
+                           const psl_field *fields, int32_t n_fields,
+                           const psl_sample_cfg *cfg, const psl_queue *q,
+                           const psl_phantom *ph, const psl_physics *phys,
+                           const void *d_tables, uint64_t seed,
+                           const psl_dose_acc *acc, double *d_s1,
+                           double *d_s2, psl_stats *d_stats,
+                           const psl_launch *launch, void *d_ws,
+                           size_t ws_bytes, void *stream);
+/*
+ * psl_plan_run - enqueues batches first_batch .. first_batch + n_batches - 1.
+ * With use_graph != 0 the batch is captured once into a hipGraph (on this
+ * stream, which must not be the null stream) and replayed per batch; the
+ * batch index lives in device memory and each replay advances it, so the
+ * result is identical to the eager path.
+ */
+psl_status psl_plan_run(psl_plan *p, int64_t first_batch, int32_t n_batches,
+                        int32_t use_graph, void *stream);
+/*
+ * psl_autotune - times `trials` batches (after one warm-up) of sampling and
+ * transport for electron bucket counts {1, 4, 8, 16} (edges log-spaced from
+ * t_cut to e_max), with and without re-bucketing, at 2, 4, 8 and 16 blocks
+ * per CU; configurations that overflow a queue region are rejected.  The
+ * fastest is applied to the plan and returned with the queue capacity it
+ * needs.  The tallies d_s1/d_s2 are not touched; the batch accumulator is
+ * left zero.  Synchronises the stream.
+ */
+psl_status psl_autotune(psl_plan *p, int32_t trials, psl_tune_result *out,
+                        void *stream);
+/* Current queue layout and launch shape of a plan (after tuning). */
+psl_status psl_plan_get(const psl_plan *p, psl_queue *q, psl_launch *launch);
+psl_status psl_plan_destroy(psl_plan *p);
+
+/* ------------------------------------------------------------------------ */
+/* Learned dose denoiser (not part of the paper's method).                   */
+/* ------------------------------------------------------------------------ */
+/* A 3D U-Net: 4 levels of 16/32/64/128 channels, two 3x3x3 convolutions
+ * (zero padding, ReLU) per level and side, 2x2x2 average pooling, nearest
+ * up-sampling with concatenated skips, and a 1x1 head added to the input
+ * dose (residual).  Inputs per sample are the noisy dose and the density,
+ * both [nz][ny][nx]; the dose is normalised by its maximum.  BF16 weights
+ * and activations on MFMA with FP32 accumulation; FP32 master weights.
+ * Parameter blob layout (floats): for each of the 14 convolutions in the
+ * order enc0a enc0b enc1a enc1b enc2a enc2b enc3a enc3b dec2a dec2b dec1a
+ * dec1b dec0a dec0b: W[Cout][Kp] with K = offset * Cin + ci (offset =
+ * (dz+1)*9 + (dy+1)*3 + (dx+1)) zero-padded to Kp = roundup(27 Cin, 32),
+ * then b[Cout]; then the head w[16] and b[1] (plus 7 padding floats).
+ * enc0a reads 16 input channels: dose, density and 14 zeros. */
+typedef struct psl_unet {
+    int32_t levels, base;       /* 4 and 16 in this build                  */
+    int64_t n_params;           /* unet_param_count(4, 16)                 */
+    float *params;              /* device fp32 master weights              */
+    uint16_t *params_bf16;      /* device bf16 copy used by the kernels    */
+} psl_unet;
+
+int64_t unet_param_count(int32_t levels, int32_t base);
+size_t unet_workspace_bytes(const psl_unet *u, int32_t n, int32_t nz,
+                            int32_t ny, int32_t nx, int32_t training);
+/* He-normal weights (counter-based, from seed), zero biases, zero head. */
+psl_status unet_init(psl_unet *u, uint64_t seed, void *stream);
+/* d_out [n][nz][ny][nx] = denoised dose (same units as d_dose).  Each axis
+ * must be a multiple of 8. */
+psl_status unet_forward(const psl_unet *u, const float *d_dose,
+                        const float *d_density, int32_t n, int32_t nz,
+                        int32_t ny, int32_t nx, float *d_out, void *d_ws,
+                        size_t ws_bytes, void *stream);
+/* Forward with saved activations, then the mean squared error against
+ * d_target (in normalised units) added into *d_loss (device double) and
+ * its gradient added into d_grads (n_params floats, same layout). */
+psl_status unet_backward(const psl_unet *u, const float *d_dose,
+                         const float *d_density, const float *d_target,
+                         int32_t n, int32_t nz, int32_t ny, int32_t nx,
+                         float *d_grads, double *d_loss, void *d_ws,
+                         size_t ws_bytes, void *stream);
+/* Adam on the fp32 weights (step counts from 1), refreshes the bf16 copy
+ * and zeroes d_grads. */
+psl_status unet_adam_step(psl_unet *u, float *d_grads, float *d_m, float *d_v,
+                          float lr, float beta1, float beta2, float eps,
+                          int32_t step, void *stream);
+/* dose_denoise - one volume through the trained network (unet_forward with
+ * n = 1); plain Monte Carlo stays the reference the result is judged by. */
+psl_status dose_denoise(const float *d_dose, const float *d_density,
+                        int32_t nx, int32_t ny, int32_t nz,
+                        const psl_unet *net, float *d_out, void *d_ws,
+                        size_t ws_bytes, void *stream);
+
+/*
+ * psl_bench_atomics - measures the atomic roofs the dose tally works
+ * against, on the current device: rates[0] = 64-bit atomic adds per second
+ * scattered over n_addresses (>= 1024) 8-byte counters, the access pattern
+ * of the tally; rates[1] = atomic adds per second that all target one
+ * address.  Needs psl_bench_atomics_workspace_bytes(n_addresses) of device
+ * workspace (contents destroyed).  Synchronises the stream.
+ */
+size_t psl_bench_atomics_workspace_bytes(int64_t n_addresses);
+psl_status psl_bench_atomics(int64_t n_addresses, double *rates, void *d_ws,
+                             size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -35,7 +35,11 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_build", "psl_sample_workspace_bytes", "psl_sample",
            "psl_physics_init", "transport_batch_workspace_bytes",
            "transport_batch", "dose_tally", "psl_profile_enable",
-           "psl_profile_read"]
+           "psl_profile_read", "psl_bench_atomics_workspace_bytes",
+           "psl_bench_atomics", "psl_plan_workspace_bytes", "psl_plan_create",
+           "psl_plan_run", "psl_autotune", "psl_plan_get", "psl_plan_destroy",
+           "unet_param_count", "unet_workspace_bytes", "unet_init",
+           "unet_forward", "unet_backward", "unet_adam_step", "dose_denoise"]
 
 
 class PslError(RuntimeError):
@@ -93,7 +97,7 @@ class psl_queue(C.Structure):
 STATS_FIELDS = ["histories", "jaw_rejected", "fluence_zero", "missed",
                 "photons", "electrons", "lost", "interactions", "secondaries",
                 "segments", "flights", "runaway", "deposits",
-                "photon_deposits"]
+                "photon_deposits", "bucket_peak"]
 
 
 class psl_stats(C.Structure):
@@ -126,6 +130,21 @@ class psl_dose_acc(C.Structure):
 class psl_launch(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32),
                 ("n_cu", C.c_int32), ("rebucket", C.c_int32)]
+
+
+class psl_tune_result(C.Structure):
+    _fields_ = [("launch", psl_launch), ("n_ebuckets", C.c_int32),
+                ("configs_tried", C.c_int32),
+                ("e_bucket_edges", C.c_float * (PSL_MAX_QBUCKETS + 1)),
+                ("ms_per_batch", C.c_double),
+                ("el_capacity_suggested", C.c_int64),
+                ("bucket_peak", C.c_int64)]
+
+
+class psl_unet(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("base", C.c_int32),
+                ("n_params", C.c_int64), ("params", C.c_void_p),
+                ("params_bf16", C.c_void_p)]
 
 
 def make_launch(blocks_per_cu=8, rebucket=1, n_cu=0, block=256):
@@ -175,6 +194,40 @@ def lib():
         L.psl_profile_enable.restype = i32
         L.psl_profile_read.argtypes = [vp, vp, i32]
         L.psl_profile_read.restype = i32
+        L.psl_bench_atomics_workspace_bytes.argtypes = [i64]
+        L.psl_bench_atomics_workspace_bytes.restype = sz
+        L.psl_bench_atomics.argtypes = [i64, vp, vp, sz, vp]
+        L.psl_bench_atomics.restype = i32
+        L.psl_plan_workspace_bytes.argtypes = [vp, i32, i64, vp]
+        L.psl_plan_workspace_bytes.restype = sz
+        L.psl_plan_create.argtypes = [vp, vp, vp, vp, vp, i32, vp, vp, vp, vp,
+                                      vp, u64, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.psl_plan_create.restype = i32
+        L.psl_plan_run.argtypes = [vp, i64, i32, i32, vp]
+        L.psl_plan_run.restype = i32
+        L.psl_autotune.argtypes = [vp, i32, vp, vp]
+        L.psl_autotune.restype = i32
+        L.psl_plan_get.argtypes = [vp, vp, vp]
+        L.psl_plan_get.restype = i32
+        L.psl_plan_destroy.argtypes = [vp]
+        L.psl_plan_destroy.restype = i32
+        L.unet_param_count.argtypes = [i32, i32]
+        L.unet_param_count.restype = i64
+        L.unet_workspace_bytes.argtypes = [vp, i32, i32, i32, i32, i32]
+        L.unet_workspace_bytes.restype = sz
+        L.unet_init.argtypes = [vp, u64, vp]
+        L.unet_init.restype = i32
+        L.unet_forward.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, sz,
+                                   vp]
+        L.unet_forward.restype = i32
+        L.unet_backward.argtypes = [vp, vp, vp, vp, i32, i32, i32, i32, vp,
+                                    vp, vp, sz, vp]
+        L.unet_backward.restype = i32
+        L.unet_adam_step.argtypes = [vp, vp, vp, vp, C.c_float, C.c_float,
+                                     C.c_float, C.c_float, i32, vp]
+        L.unet_adam_step.restype = i32
+        L.dose_denoise.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
+        L.dose_denoise.restype = i32
         _lib = L
     return _lib
 
@@ -314,6 +367,133 @@ def dose_tally(acc: Optional[psl_dose_acc], s1, s2, op, n_batches,
                             _ptr(sigma), _stream(stream)))
 
 
+class Plan:
+    """A psl_plan handle: allocation once, then batches eagerly or under a
+    hipGraph (psl_plan_run), optionally autotuned (psl_autotune)."""
+
+    def __init__(self, handle, ws, stream):
+        self.handle = handle
+        self.ws = ws          # the plan owns its workspace until destroyed
+        self.stream = stream
+
+    def run(self, first_batch, n_batches, use_graph=True, stream=None):
+        _check(lib().psl_plan_run(self.handle, int(first_batch),
+                                  int(n_batches), 1 if use_graph else 0,
+                                  _stream(stream or self.stream)))
+
+    def autotune(self, trials=2, stream=None):
+        r = psl_tune_result()
+        _check(lib().psl_autotune(self.handle, int(trials), C.byref(r),
+                                  _stream(stream or self.stream)))
+        return r
+
+    def layout(self):
+        q, L = psl_queue(), psl_launch()
+        _check(lib().psl_plan_get(self.handle, C.byref(q), C.byref(L)))
+        return q, L
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().psl_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Denoiser:
+    """Device state of the dose denoiser (fp32 master weights, bf16 copy,
+    gradients and Adam moments) and the calls on it."""
+
+    def __init__(self, device="cuda", seed=None):
+        import torch
+        self.torch = torch
+        n = lib().unet_param_count(4, 16)
+        self.n = n
+        self.params = torch.zeros(n, dtype=torch.float32, device=device)
+        self.params_bf16 = torch.zeros(n, dtype=torch.int16, device=device)
+        self.grads = torch.zeros(n, dtype=torch.float32, device=device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.step_no = 0
+        self.net = psl_unet()
+        self.net.levels, self.net.base, self.net.n_params = 4, 16, n
+        self.net.params = self.params.data_ptr()
+        self.net.params_bf16 = self.params_bf16.data_ptr()
+        self._ws = {}
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+        if seed is not None:
+            self.init(seed)
+
+    def init(self, seed):
+        _check(lib().unet_init(C.byref(self.net), C.c_uint64(seed),
+                               _stream()))
+
+    def set_params(self, blob):
+        """Load fp32 master weights (the documented blob layout); the bf16
+        copy is their round-to-nearest-even rounding."""
+        torch = self.torch
+        t = torch.as_tensor(np.asarray(blob, np.float32)).to(
+            self.params.device)
+        self.params.copy_(t)
+        self.params_bf16.copy_(t.to(torch.bfloat16).view(torch.int16))
+
+    def _workspace(self, shape, training):
+        key = (tuple(shape), training)
+        if key not in self._ws:
+            n, d, h, w = shape
+            nb = lib().unet_workspace_bytes(C.byref(self.net), n, d, h, w,
+                                            1 if training else 0)
+            self._ws[key] = self.torch.empty(nb, dtype=torch_uint8(),
+                                             device=self.params.device)
+        return self._ws[key]
+
+    def forward(self, dose, rho):
+        """dose, rho: float32 [n, nz, ny, nx] device tensors."""
+        out = self.torch.empty_like(dose)
+        ws = self._workspace(dose.shape, False)
+        n, d, h, w = dose.shape
+        _check(lib().unet_forward(C.byref(self.net), _ptr(dose), _ptr(rho),
+                                  n, d, h, w, _ptr(out), _ptr(ws), ws.numel(),
+                                  _stream()))
+        return out
+
+    def backward(self, dose, rho, target):
+        """Adds the loss gradient into self.grads; returns the device loss
+        tensor (accumulated since the last zeroing)."""
+        ws = self._workspace(dose.shape, True)
+        n, d, h, w = dose.shape
+        _check(lib().unet_backward(C.byref(self.net), _ptr(dose), _ptr(rho),
+                                   _ptr(target), n, d, h, w,
+                                   _ptr(self.grads), _ptr(self.loss),
+                                   _ptr(ws), ws.numel(), _stream()))
+        return self.loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        self.step_no += 1
+        _check(lib().unet_adam_step(C.byref(self.net), _ptr(self.grads),
+                                    _ptr(self.m), _ptr(self.v), lr, beta1,
+                                    beta2, eps, self.step_no, _stream()))
+
+    def denoise(self, dose, rho):
+        """dose, rho: float32 [nz, ny, nx]; returns the denoised dose."""
+        out = self.torch.empty_like(dose)
+        ws = self._workspace((1,) + tuple(dose.shape), False)
+        nz, ny, nx = dose.shape
+        _check(lib().dose_denoise(_ptr(dose), _ptr(rho), nx, ny, nz,
+                                  C.byref(self.net), _ptr(out), _ptr(ws),
+                                  ws.numel(), _stream()))
+        return out
+
+
+def torch_uint8():
+    import torch
+    return torch.uint8
+
+
 def stats_to_dict(stats_t) -> Dict:
     raw = stats_t.cpu().numpy().tobytes()
     s = psl_stats.from_buffer_copy(raw[:C.sizeof(psl_stats)])
@@ -325,6 +505,18 @@ def stats_to_dict(stats_t) -> Dict:
 
 PROF_GROUPS = ["build", "sample", "alloc", "photons", "electrons", "fold",
                "finalize", "rebucket"]
+
+
+def bench_atomics(n_addresses, device="cuda"):
+    """Measured atomic roofs: (scattered u64 adds/s over n_addresses,
+    same-address adds/s)."""
+    import torch
+    nb = lib().psl_bench_atomics_workspace_bytes(int(n_addresses))
+    ws = torch.zeros(nb, dtype=torch.uint8, device=device)
+    rates = (C.c_double * 2)()
+    _check(lib().psl_bench_atomics(int(n_addresses), rates, _ptr(ws), nb,
+                                   _stream()))
+    return rates[0], rates[1]
 
 
 def profile_enable(on=True):

@@ -1,0 +1,310 @@
+// psl_plan: a treatment plan of many fields or segments (an IMRT plan) run
+// batch after batch.  ROI selection and history allocation are computed once
+// at creation; each batch is sampling -> transport -> fold with the batch
+// index kept in device memory, so the batch can be captured once into a
+// hipGraph and replayed.  psl_autotune picks the transport launch shape and
+// the electron bucketing for the plan by timing trial batches.
+#include "common.hpp"
+#include "sample.hpp"
+
+#include <cmath>
+#include <vector>
+
+struct psl_plan {
+    psl::SampleCtx sc;
+    psl_queue q;
+    psl_phantom ph;
+    psl_physics phys;
+    const void *tables;
+    uint64_t seed;
+    psl_dose_acc acc;
+    double *s1, *s2;
+    psl_stats *stats;
+    psl_launch launch;
+    void *tws;
+    size_t tws_bytes;
+    int64_t *d_batch;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+};
+
+namespace psl {
+namespace {
+
+void drop_graph(psl_plan *p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr;
+    p->graph = nullptr;
+    p->graph_stream = nullptr;
+}
+
+// One batch: sampling, transport, fold, batch index + 1.  Kernels only.
+psl_status enqueue_batch(psl_plan *p, hipStream_t st) {
+    psl_status s;
+    p->sc.q = p->q;
+    if ((s = sample_batch(p->sc, p->d_batch, st))) return s;
+    if ((s = transport_batch(&p->q, &p->ph, &p->phys, p->tables, p->seed,
+                             &p->acc, p->stats, &p->launch, p->tws,
+                             p->tws_bytes, st)))
+        return s;
+    if ((s = dose_tally(&p->acc, p->s1, p->s2, PSL_TALLY_FOLD, 0, &p->ph, 1.0,
+                        nullptr, nullptr, st)))
+        return s;
+    return inc_i64(p->d_batch, st);
+}
+
+__global__ void k_zero_u64(uint64_t *a, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += stride)
+        a[i] = 0;
+}
+
+}  // namespace
+}  // namespace psl
+
+using namespace psl;
+
+extern "C" size_t psl_plan_workspace_bytes(const psl_grid *g,
+                                           int32_t n_fields,
+                                           int64_t n_histories,
+                                           const psl_queue *q) {
+    if (!g || !q || n_fields < 1 || n_histories < 0) return 0;
+    size_t a = psl_sample_workspace_bytes(g, n_fields, n_histories);
+    size_t b = transport_batch_workspace_bytes(q);
+    if (!a || !b) return 0;
+    return ((a + 255) & ~size_t(255)) + ((b + 255) & ~size_t(255)) + 256;
+}
+
+extern "C" psl_status psl_plan_create(
+    psl_plan **out, const psl_phsp *sorted, const int64_t *d_offsets,
+    const psl_grid *g, const psl_field *fields, int32_t n_fields,
+    const psl_sample_cfg *cfg, const psl_queue *q, const psl_phantom *ph,
+    const psl_physics *phys, const void *d_tables, uint64_t seed,
+    const psl_dose_acc *acc, double *d_s1, double *d_s2, psl_stats *d_stats,
+    const psl_launch *launch, void *d_ws, size_t ws_bytes, void *stream) {
+    PSL_REQUIRE(out && q && ph && phys && d_tables && acc && d_s1 && d_s2,
+                "NULL argument");
+    *out = nullptr;
+    const size_t need = psl_plan_workspace_bytes(g, n_fields,
+                                                 cfg ? cfg->n_histories : 0, q);
+    PSL_REQUIRE(need > 0, "bad grid, queue, field count or history count");
+    if (!d_ws || ws_bytes < need) {
+        set_error("workspace %zu bytes < %zu required", ws_bytes, need);
+        return PSL_ENOSPC;
+    }
+    PSL_REQUIRE(ph->nx > 0 && ph->ny > 0 && ph->nz > 0 && ph->density &&
+                    ph->rho_max > 0,
+                "bad phantom");
+    PSL_REQUIRE(acc->data && (acc->mode == PSL_ACC_F64 ||
+                              (acc->mode == PSL_ACC_FIXED64 &&
+                               acc->frac_bits >= 16 && acc->frac_bits <= 40)),
+                "bad accumulator");
+    psl_plan *p = new (std::nothrow) psl_plan();
+    if (!p) {
+        set_error("out of host memory");
+        return PSL_EINVAL;
+    }
+    const size_t a = (psl_sample_workspace_bytes(g, n_fields,
+                                                 cfg->n_histories) + 255) &
+                     ~size_t(255);
+    char *base = static_cast<char *>(d_ws);
+    psl_status s = sample_setup(sorted, d_offsets, g, fields, n_fields, cfg,
+                                q, nullptr, nullptr, d_stats, base, a,
+                                &p->sc);
+    if (s) {
+        delete p;
+        return s;
+    }
+    p->q = *q;
+    p->ph = *ph;
+    p->phys = *phys;
+    p->tables = d_tables;
+    p->seed = seed;
+    p->acc = *acc;
+    p->s1 = d_s1;
+    p->s2 = d_s2;
+    p->stats = d_stats;
+    p->launch = launch ? *launch : psl_launch{256, 8, 0, 1};
+    p->tws = base + a;
+    p->tws_bytes = ws_bytes - a - 256;
+    p->d_batch = reinterpret_cast<int64_t *>(base + ws_bytes - 256);
+    if ((s = check_device())) {
+        delete p;
+        return s;
+    }
+    if ((s = sample_alloc(p->sc, (hipStream_t)stream))) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return PSL_OK;
+}
+
+extern "C" psl_status psl_plan_run(psl_plan *p, int64_t first_batch,
+                                   int32_t n_batches, int32_t use_graph,
+                                   void *stream) {
+    PSL_REQUIRE(p, "NULL plan");
+    PSL_REQUIRE(first_batch >= 0 && n_batches >= 0, "bad batch range");
+    hipStream_t st = (hipStream_t)stream;
+    PSL_REQUIRE(!use_graph || st != nullptr,
+                "graph capture needs a created stream, not the null stream");
+    psl_status s;
+    if ((s = set_i64(p->d_batch, first_batch, st))) return s;
+    if (!use_graph) {
+        for (int b = 0; b < n_batches; ++b)
+            if ((s = enqueue_batch(p, st))) return s;
+        return PSL_OK;
+    }
+    if (!p->exec || p->graph_stream != st) {
+        drop_graph(p);
+        PSL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        s = enqueue_batch(p, st);
+        hipGraph_t gr = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &gr);
+        if (s) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return s;
+        }
+        if (e != hipSuccess) {
+            set_error("graph capture failed: %s", hipGetErrorString(e));
+            return PSL_EHIP;
+        }
+        p->graph = gr;
+        e = hipGraphInstantiate(&p->exec, gr, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(p);
+            set_error("graph instantiation failed: %s", hipGetErrorString(e));
+            return PSL_EHIP;
+        }
+        p->graph_stream = st;
+    }
+    for (int b = 0; b < n_batches; ++b) PSL_HIP(hipGraphLaunch(p->exec, st));
+    return PSL_OK;
+}
+
+extern "C" psl_status psl_plan_destroy(psl_plan *p) {
+    if (!p) return PSL_OK;
+    drop_graph(p);
+    delete p;
+    return PSL_OK;
+}
+
+// --------------------------------------------------------------- autotune -
+extern "C" psl_status psl_autotune(psl_plan *p, int32_t trials,
+                                   psl_tune_result *out, void *stream) {
+    PSL_REQUIRE(p && out, "NULL argument");
+    PSL_REQUIRE(trials >= 1 && trials <= 100, "trials outside 1..100");
+    hipStream_t st = (hipStream_t)stream;
+    psl_status s;
+    const psl_queue q0 = p->q;
+    const psl_launch l0 = p->launch;
+    const int64_t nvox = (int64_t)p->ph.nx * p->ph.ny * p->ph.nz;
+    // electron bucket edges: log-spaced between the cut-off and e_max
+    auto edges_for = [&](int nb, float *e) {
+        e[0] = 0.0f;
+        for (int b = 1; b < nb; ++b)
+            e[b] = (float)(p->phys.t_cut *
+                           std::pow(p->phys.e_max / p->phys.t_cut,
+                                    (double)b / nb));
+        e[nb] = 1e30f;
+    };
+    const int bpc_opts[] = {2, 4, 8, 16};
+    const int nb_opts[] = {1, 4, 8, 16};
+    hipEvent_t e0, e1;
+    PSL_HIP(hipEventCreate(&e0));
+    PSL_HIP(hipEventCreate(&e1));
+    double best = 1e300;
+    psl_tune_result r{};
+    int n_tried = 0;
+    std::vector<uint32_t> cnt(PSL_QCOUNTS);
+    for (int nb : nb_opts) {
+        if (nb > PSL_MAX_QBUCKETS) continue;
+        for (int rb = 0; rb <= 1; ++rb) {
+            if (nb == 1 && rb == 1) continue;
+            for (int bpc : bpc_opts) {
+                psl_queue q = q0;
+                q.n_ebuckets = nb;
+                edges_for(nb, q.e_bucket_edges);
+                p->q = q;
+                p->launch = psl_launch{256, bpc, l0.n_cu, rb};
+                float tot = 0.0f;
+                uint32_t lost = 0;
+                uint64_t peak = 0;
+                for (int t = 0; t <= trials; ++t) {   // first run is warm-up
+                    if ((s = set_i64(p->d_batch, t, st))) goto fail;
+                    p->sc.q = p->q;
+                    PSL_HIP(hipEventRecord(e0, st));
+                    if ((s = sample_batch(p->sc, p->d_batch, st))) goto fail;
+                    if ((s = transport_batch(&p->q, &p->ph, &p->phys,
+                                             p->tables, p->seed, &p->acc,
+                                             p->stats, &p->launch, p->tws,
+                                             p->tws_bytes, st)))
+                        goto fail;
+                    PSL_HIP(hipEventRecord(e1, st));
+                    PSL_HIP(hipEventSynchronize(e1));
+                    float ms = 0.0f;
+                    PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (t > 0) tot += ms;
+                    psl_stats sb;
+                    PSL_HIP(hipMemcpy(&sb, p->stats, sizeof sb,
+                                      hipMemcpyDeviceToHost));
+                    PSL_HIP(hipMemcpy(cnt.data(), q.d_counts,
+                                      sizeof(uint32_t) * PSL_QCOUNTS,
+                                      hipMemcpyDeviceToHost));
+                    lost += cnt[PSL_QCOUNTS - 1] + (uint32_t)sb.lost;
+                    peak = std::max<uint64_t>(peak, sb.bucket_peak);
+                }
+                ++n_tried;
+                const double ms = tot / trials;
+                if (!lost && ms < best) {
+                    best = ms;
+                    r.launch = p->launch;
+                    r.n_ebuckets = nb;
+                    for (int b = 0; b <= nb; ++b)
+                        r.e_bucket_edges[b] = q.e_bucket_edges[b];
+                    r.ms_per_batch = ms;
+                    r.bucket_peak = (int64_t)peak;
+                    r.el_capacity_suggested =
+                        (int64_t)nb * (int64_t)(1.25 * (double)peak + 64.0);
+                }
+            }
+        }
+    }
+    // leave the tally as it was before tuning
+    hipLaunchKernelGGL(k_zero_u64, dim3(1024), dim3(256), 0, st,
+                       static_cast<uint64_t *>(p->acc.data), nvox);
+    PSL_HIP(hipEventDestroy(e0));
+    PSL_HIP(hipEventDestroy(e1));
+    if (best >= 1e300) {
+        p->q = q0;
+        p->launch = l0;
+        set_error("no tuning configuration ran without queue overflow");
+        return PSL_ENOSPC;
+    }
+    r.configs_tried = n_tried;
+    p->q = q0;
+    p->q.n_ebuckets = r.n_ebuckets;
+    for (int b = 0; b <= r.n_ebuckets; ++b)
+        p->q.e_bucket_edges[b] = r.e_bucket_edges[b];
+    p->launch = r.launch;
+    drop_graph(p);
+    *out = r;
+    return PSL_OK;
+fail:
+    p->q = q0;
+    p->launch = l0;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return s;
+}
+
+extern "C" psl_status psl_plan_get(const psl_plan *p, psl_queue *q,
+                                   psl_launch *launch) {
+    PSL_REQUIRE(p, "NULL plan");
+    if (q) *q = p->q;
+    if (launch) *launch = p->launch;
+    return PSL_OK;
+}

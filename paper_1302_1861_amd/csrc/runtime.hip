@@ -106,6 +106,10 @@ int64_t g_launches[PSL_PROF_N] = {0};
 ProfScope::ProfScope(int group, hipStream_t st) : group_(group), st_(st) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
     if (!g_prof_on) return;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st_, &cs) != hipSuccess ||
+        cs != hipStreamCaptureStatusNone)
+        return;   // no timing events inside a graph being captured
     if (hipEventCreate(&a_) != hipSuccess) return;
     if (hipEventCreate(&b_) != hipSuccess) {
         (void)hipEventDestroy(a_);

@@ -12,8 +12,7 @@
 // The per-history decisions (jaw acceptance, fluence pixel, hitting the
 // phantom) are taken in double precision with floating-point contraction
 // disabled, so they are reproducible operation by operation.
-#include "common.hpp"
-#include "compact.hpp"
+#include "sample.hpp"
 #include "scan.hpp"
 
 #include <cmath>
@@ -25,19 +24,6 @@ namespace psl {
 psl_status validate_grid_public(const psl_grid *g);
 
 namespace {
-
-struct FieldDev {
-    double X1, X2, Y1, Y2;
-    double cos_g, sin_g, MU;
-    const float *fluence;
-    int32_t nfx, nfy, jaws_on, pad;
-    double f_x0, f_y0, f_pix;
-};
-
-struct Geo {
-    double sad, z_x, z_y, z_psl;
-    double iso[3], lo[3], hi[3];
-};
 
 __global__ void k_sample_init(psl_stats *stats, uint32_t *counts) {
     int t = threadIdx.x;
@@ -204,9 +190,11 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
          const int64_t *__restrict__ H, int64_t n_ranges,
          const uint64_t *__restrict__ h_total_p,
          const int64_t *__restrict__ before, const int64_t *__restrict__ T,
-         const double *__restrict__ g, uint64_t seed, int64_t batch,
-         Slots slots, int64_t n_slots, psl_queue qcfg, uint64_t *part) {
+         const double *__restrict__ g, uint64_t seed,
+         const int64_t *__restrict__ batch_p, Slots slots, int64_t n_slots,
+         psl_queue qcfg, uint64_t *part) {
 #pragma clang fp contract(off)
+    const int64_t batch = *batch_p;
     __shared__ float s_edges[PSL_MAX_QBUCKETS + 1];
     __shared__ uint64_t s_red[(kSampleBlock / 64) * kStatWords];
     if (threadIdx.x <= PSL_MAX_QBUCKETS)
@@ -338,21 +326,25 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
     block_stats_write(st, s_red, part);
 }
 
-struct SampleWs {
-    FieldDev *fields;
-    uint8_t *mask;
-    int64_t *C, *NF, *N, *H, *before, *T;
-    double *g, *mu_tot;
-    uint64_t *chunks, *h_total, *part;
-    Slots slots;
-    uint32_t *tiles;
-    size_t bytes;
-};
-
 constexpr int kSampleMaxBlocks = 16384;
 
-SampleWs carve_sample(void *base, int64_t n_keys, int P, int F,
-                      int64_t n_hist) {
+
+psl_status validate_particles(const psl_particles &p, const char *name) {
+    PSL_REQUIRE(p.capacity >= 0, "%s capacity < 0", name);
+    if (p.capacity > 0)
+        PSL_REQUIRE(p.E && p.x && p.y && p.z && p.u && p.v && p.w && p.wt &&
+                        p.uid && p.ctr,
+                    "NULL array in %s", name);
+    return PSL_OK;
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+__global__ void k_inc_i64(int64_t *p) { *p += 1; }
+
+}  // namespace
+
+SampleWs carve_sample_impl(void *base, int64_t n_keys, int P, int F,
+                           int64_t n_hist) {
     Carver c(base);
     SampleWs w;
     const int64_t ns = std::max<int64_t>(n_hist, 1);
@@ -368,6 +360,7 @@ SampleWs carve_sample(void *base, int64_t n_keys, int P, int F,
     w.T = c.take<int64_t>(n_keys);
     w.chunks = c.take<uint64_t>(scan_chunks((int64_t)F * n_keys + 1) + 1);
     w.h_total = c.take<uint64_t>(1);
+    w.batch = c.take<int64_t>(1);
     w.part = c.take<uint64_t>((int64_t)kSampleMaxBlocks * kStatWords);
     w.slots.p.capacity = ns;
     w.slots.p.E = c.take<float>(ns);
@@ -386,16 +379,18 @@ SampleWs carve_sample(void *base, int64_t n_keys, int P, int F,
     return w;
 }
 
-psl_status validate_particles(const psl_particles &p, const char *name) {
-    PSL_REQUIRE(p.capacity >= 0, "%s capacity < 0", name);
-    if (p.capacity > 0)
-        PSL_REQUIRE(p.E && p.x && p.y && p.z && p.u && p.v && p.w && p.wt &&
-                        p.uid && p.ctr,
-                    "NULL array in %s", name);
+psl_status set_i64(int64_t *p, int64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, st, p, v);
+    PSL_LAUNCHED();
     return PSL_OK;
 }
 
-}  // namespace
+psl_status inc_i64(int64_t *p, hipStream_t st) {
+    hipLaunchKernelGGL(k_inc_i64, dim3(1), dim3(1), 0, st, p);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
 
 psl_status validate_queue(const psl_queue *q) {
     PSL_REQUIRE(q && q->d_counts, "queue or its counts are NULL");
@@ -423,17 +418,18 @@ extern "C" size_t psl_sample_workspace_bytes(const psl_grid *g,
                                              int64_t n_histories) {
     if (!g || n_fields < 1 || n_histories < 0) return 0;
     int64_t n_keys = 2LL * g->n_e * g->n_x * g->n_y;
-    return carve_sample(nullptr, n_keys, g->n_x * g->n_y, n_fields,
-                        n_histories).bytes;
+    return carve_sample_impl(nullptr, n_keys, g->n_x * g->n_y, n_fields,
+                             n_histories).bytes;
 }
 
-extern "C" psl_status psl_sample(const psl_phsp *sorted,
-                                 const int64_t *d_offsets, const psl_grid *g,
-                                 const psl_field *fields, int32_t n_fields,
-                                 const psl_sample_cfg *cfg, psl_queue *q,
-                                 uint8_t *d_mask, int64_t *d_alloc,
-                                 psl_stats *d_stats, void *d_ws,
-                                 size_t ws_bytes, void *stream) {
+namespace psl {
+
+psl_status sample_setup(const psl_phsp *sorted, const int64_t *d_offsets,
+                        const psl_grid *g, const psl_field *fields,
+                        int32_t n_fields, const psl_sample_cfg *cfg,
+                        const psl_queue *q, uint8_t *d_mask, int64_t *d_alloc,
+                        psl_stats *d_stats, void *d_ws, size_t ws_bytes,
+                        SampleCtx *ctx) {
     PSL_REQUIRE(sorted && d_offsets && fields && cfg && q && d_stats,
                 "NULL argument");
     psl_status s = validate_grid_public(g);
@@ -470,7 +466,7 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
     PSL_REQUIRE((unsigned __int128)cfg->n_histories * (uint64_t)sorted->n <
                     ((unsigned __int128)1 << 63),
                 "n_histories * n_particles overflows 64 bits");
-    std::vector<FieldDev> fd(n_fields);
+    ctx->fd.resize(n_fields);
     for (int i = 0; i < n_fields; ++i) {
         const psl_field &f = fields[i];
         PSL_REQUIRE(f.MU > 0, "field %d: MU <= 0", i);
@@ -479,79 +475,125 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
         PSL_REQUIRE(!f.fluence || (f.nfx > 0 && f.nfy > 0 && f.f_pix > 0),
                     "field %d: bad fluence map", i);
         double th = f.gantry_deg * (M_PI / 180.0);
-        fd[i] = FieldDev{f.X1, f.X2, f.Y1, f.Y2, std::cos(th), std::sin(th),
-                         f.MU, f.fluence, f.fluence ? f.nfx : 0,
-                         f.fluence ? f.nfy : 0, f.jaws_on ? 1 : 0, 0,
-                         f.f_x0, f.f_y0, f.f_pix};
+        ctx->fd[i] = FieldDev{f.X1, f.X2, f.Y1, f.Y2, std::cos(th),
+                              std::sin(th), f.MU, f.fluence,
+                              f.fluence ? f.nfx : 0, f.fluence ? f.nfy : 0,
+                              f.jaws_on ? 1 : 0, 0, f.f_x0, f.f_y0, f.f_pix};
     }
-    const int64_t n_keys = 2LL * g->n_e * g->n_x * g->n_y;
-    const int P = g->n_x * g->n_y;
-    SampleWs need = carve_sample(nullptr, n_keys, P, n_fields,
-                                 cfg->n_histories);
+    ctx->n_keys = 2LL * g->n_e * g->n_x * g->n_y;
+    ctx->P = g->n_x * g->n_y;
+    SampleWs need = carve_sample_impl(nullptr, ctx->n_keys, ctx->P, n_fields,
+                                      cfg->n_histories);
     if (!d_ws || ws_bytes < need.bytes) {
         set_error("workspace %zu bytes < %zu required", ws_bytes, need.bytes);
         return PSL_ENOSPC;
     }
-    if ((s = check_device())) return s;
-    hipStream_t st = (hipStream_t)stream;
-    SampleWs w = carve_sample(d_ws, n_keys, P, n_fields, cfg->n_histories);
-    uint8_t *mask = d_mask ? d_mask : w.mask;
-    int64_t *N = d_alloc ? d_alloc : w.N;
-    PSL_HIP(hipMemcpyAsync(w.fields, fd.data(), sizeof(FieldDev) * n_fields,
+    ctx->w = carve_sample_impl(d_ws, ctx->n_keys, ctx->P, n_fields,
+                               cfg->n_histories);
+    ctx->sorted = *sorted;
+    ctx->offsets = d_offsets;
+    ctx->g = *g;
+    ctx->geo = Geo{cfg->sad, cfg->z_jaw_x, cfg->z_jaw_y, g->z_plane,
+                   {cfg->iso[0], cfg->iso[1], cfg->iso[2]},
+                   {cfg->box_lo[0], cfg->box_lo[1], cfg->box_lo[2]},
+                   {cfg->box_hi[0], cfg->box_hi[1], cfg->box_hi[2]}};
+    ctx->n_fields = n_fields;
+    ctx->cull = cfg->cull;
+    ctx->alloc_mode = cfg->alloc_mode;
+    ctx->n_ranges = (int64_t)n_fields * ctx->n_keys;
+    ctx->n_hist = cfg->n_histories;
+    ctx->seed = cfg->seed;
+    ctx->q = *q;
+    ctx->stats = d_stats;
+    ctx->mask = d_mask ? d_mask : ctx->w.mask;
+    ctx->N = d_alloc ? d_alloc : ctx->w.N;
+    return PSL_OK;
+}
+
+psl_status sample_alloc(const SampleCtx &c, hipStream_t st) {
+    psl_status s;
+    const SampleWs &w = c.w;
+    PSL_HIP(hipMemcpyAsync(w.fields, c.fd.data(),
+                           sizeof(FieldDev) * c.n_fields,
                            hipMemcpyHostToDevice, st));
-    Geo geo{cfg->sad, cfg->z_jaw_x, cfg->z_jaw_y, g->z_plane,
-            {cfg->iso[0], cfg->iso[1], cfg->iso[2]},
-            {cfg->box_lo[0], cfg->box_lo[1], cfg->box_lo[2]},
-            {cfg->box_hi[0], cfg->box_hi[1], cfg->box_hi[2]}};
-    hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, d_stats,
-                       q->d_counts);
-    std::unique_ptr<ProfScope> prof_alloc(new ProfScope(PSL_PROF_ALLOC, st));
-    int64_t nm = (int64_t)n_fields * P;
+    ProfScope prof(PSL_PROF_ALLOC, st);
+    const int64_t nm = (int64_t)c.n_fields * c.P;
     hipLaunchKernelGGL(k_cull, dim3((unsigned)((nm + 255) / 256)), dim3(256),
-                       0, st, w.fields, n_fields, geo, *g, cfg->cull, mask);
-    hipLaunchKernelGGL(k_field_pop, dim3(n_fields), dim3(kAllocBlock), 0, st,
-                       d_offsets, n_keys, P, mask, w.C);
+                       0, st, w.fields, c.n_fields, c.geo, c.g, c.cull,
+                       c.mask);
+    hipLaunchKernelGGL(k_field_pop, dim3(c.n_fields), dim3(kAllocBlock), 0,
+                       st, c.offsets, c.n_keys, c.P, c.mask, w.C);
     hipLaunchKernelGGL(k_field_totals, dim3(1), dim3(1), 0, st, w.fields,
-                       n_fields, w.C, cfg->alloc_mode, cfg->n_histories, w.NF,
+                       c.n_fields, w.C, c.alloc_mode, c.n_hist, w.NF,
                        w.mu_tot);
     {
         // masked counts in H, their scan in `before` (both rewritten below)
-        const int64_t nr = (int64_t)n_fields * n_keys;
+        const int64_t nr = c.n_ranges;
         const unsigned nb = (unsigned)((nr + 255) / 256);
         hipLaunchKernelGGL(k_masked_counts, dim3(nb), dim3(256), 0, st,
-                           d_offsets, n_keys, P, n_fields, mask, w.H);
+                           c.offsets, c.n_keys, c.P, c.n_fields, c.mask, w.H);
         if ((s = exclusive_scan<int64_t, int64_t>(w.H, w.before, nr, w.chunks,
                                                   nullptr, st)))
             return s;
         hipLaunchKernelGGL(k_key_alloc, dim3(nb), dim3(256), 0, st, w.fields,
-                           d_offsets, n_keys, n_fields, w.H, w.before, w.C,
-                           w.NF, w.mu_tot, N, w.g);
+                           c.offsets, c.n_keys, c.n_fields, w.H, w.before,
+                           w.C, w.NF, w.mu_tot, c.N, w.g);
     }
-    hipLaunchKernelGGL(k_cursor, dim3((unsigned)((n_keys + 255) / 256)),
-                       dim3(256), 0, st, N, n_fields, n_keys, w.before, w.T);
-    const int64_t n_ranges = (int64_t)n_fields * n_keys;
-    if ((s = exclusive_scan<int64_t, int64_t>(N, w.H, n_ranges, w.chunks,
+    hipLaunchKernelGGL(k_cursor, dim3((unsigned)((c.n_keys + 255) / 256)),
+                       dim3(256), 0, st, c.N, c.n_fields, c.n_keys, w.before,
+                       w.T);
+    if ((s = exclusive_scan<int64_t, int64_t>(c.N, w.H, c.n_ranges, w.chunks,
                                               w.h_total, st)))
         return s;
-    prof_alloc.reset();
-    if (cfg->n_histories > 0) {
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+psl_status sample_batch(const SampleCtx &c, const int64_t *d_batch,
+                        hipStream_t st) {
+    psl_status s;
+    const SampleWs &w = c.w;
+    hipLaunchKernelGGL(k_sample_init, dim3(1), dim3(64), 0, st, c.stats,
+                       c.q.d_counts);
+    if (c.n_hist > 0) {
         ProfScope prof(PSL_PROF_SAMPLE, st);
-        int cu = device_cu_count();
-        int64_t blocks = std::min<int64_t>(
-            (cfg->n_histories + kSampleBlock - 1) / kSampleBlock,
+        const int cu = device_cu_count();
+        const int64_t blocks = std::min<int64_t>(
+            (c.n_hist + kSampleBlock - 1) / kSampleBlock,
             std::min<int64_t>((int64_t)cu * 16, kSampleMaxBlocks));
         hipLaunchKernelGGL(k_sample, dim3((unsigned)blocks),
-                           dim3(kSampleBlock), 0, st, *sorted, d_offsets,
-                           n_keys, w.fields, geo, w.H, n_ranges, w.h_total,
-                           w.before, w.T, w.g, cfg->seed, cfg->batch, w.slots,
-                           cfg->n_histories, *q, w.part);
-        QueueRegions qr{q->ph, q->el, 1 + q->n_ebuckets,
-                        q->el.capacity / q->n_ebuckets, q->d_counts};
-        if ((s = compact_slots(w.slots, cfg->n_histories, nullptr, 0, 0, qr,
-                               w.tiles, st)))
+                           dim3(kSampleBlock), 0, st, c.sorted, c.offsets,
+                           c.n_keys, w.fields, c.geo, w.H, c.n_ranges,
+                           w.h_total, w.before, w.T, w.g, c.seed, d_batch,
+                           w.slots, c.n_hist, c.q, w.part);
+        QueueRegions qr{c.q.ph, c.q.el, 1 + c.q.n_ebuckets,
+                        c.q.el.capacity / c.q.n_ebuckets, c.q.d_counts};
+        if ((s = compact_slots(w.slots, c.n_hist, nullptr, 0, 0, qr, w.tiles,
+                               st)))
             return s;
-        if ((s = stats_reduce(w.part, (int)blocks, d_stats, st))) return s;
+        if ((s = stats_reduce(w.part, (int)blocks, c.stats, st))) return s;
     }
     PSL_LAUNCHED();
     return PSL_OK;
+}
+
+}  // namespace psl
+
+extern "C" psl_status psl_sample(const psl_phsp *sorted,
+                                 const int64_t *d_offsets, const psl_grid *g,
+                                 const psl_field *fields, int32_t n_fields,
+                                 const psl_sample_cfg *cfg, psl_queue *q,
+                                 uint8_t *d_mask, int64_t *d_alloc,
+                                 psl_stats *d_stats, void *d_ws,
+                                 size_t ws_bytes, void *stream) {
+    SampleCtx ctx;
+    psl_status s = sample_setup(sorted, d_offsets, g, fields, n_fields, cfg,
+                                q, d_mask, d_alloc, d_stats, d_ws, ws_bytes,
+                                &ctx);
+    if (s) return s;
+    if ((s = check_device())) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = sample_alloc(ctx, st))) return s;
+    if ((s = set_i64(ctx.w.batch, cfg->batch, st))) return s;
+    return sample_batch(ctx, ctx.w.batch, st);
 }

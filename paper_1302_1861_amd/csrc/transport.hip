@@ -605,7 +605,13 @@ __global__ void k_transport_init(uint32_t *words, int n_words,
         codes[i] = e4;
 }
 
-__global__ void k_consume(uint32_t *counts) {
+__global__ void k_consume(uint32_t *counts, int n_b, psl_stats *stats) {
+    if (threadIdx.x == 0) {
+        uint32_t peak = 0;
+        for (int b = 0; b < n_b; ++b) peak = max(peak, counts[1 + b]);
+        if (peak > stats->bucket_peak) stats->bucket_peak = peak;
+    }
+    __syncthreads();
     if (threadIdx.x < PSL_QCOUNTS - 1) counts[threadIdx.x] = 0;
 }
 
@@ -621,15 +627,15 @@ struct TransportWs {
 
 constexpr int kMaxGridBlocks = 16 * 1024;
 
-TransportWs carve_transport(void *base, int64_t el_cap) {
-    // el_cap: capacity of one electron bucket region
+TransportWs carve_transport(void *base, int64_t ph_cap) {
+    // the secondary stream holds up to 2 secondaries per queued photon
     Carver c(base);
     TransportWs w;
     w.n_words = 3 * kParts * kPartStride + 64;
     w.words = c.take<uint32_t>(w.n_words);
     // secondary stream: one slot per electron-queue entry plus one chunk per
     // wave of the largest grid for partly filled chunks
-    const int64_t chunks = (std::max<int64_t>(el_cap, 64) + 63) / 64 +
+    const int64_t chunks = (std::max<int64_t>(2 * ph_cap, 64) + 63) / 64 +
                            (int64_t)kMaxGridBlocks * (kBlock / 64);
     const int64_t n = chunks * 64;
     w.sec.n_chunks = chunks;
@@ -728,7 +734,7 @@ extern "C" psl_status psl_physics_init(const psl_physics *phys,
 
 extern "C" size_t transport_batch_workspace_bytes(const psl_queue *q) {
     if (!q || q->n_ebuckets < 1) return 0;
-    return carve_transport(nullptr, q->el.capacity / q->n_ebuckets).bytes;
+    return carve_transport(nullptr, q->ph.capacity).bytes;
 }
 
 extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
@@ -778,7 +784,7 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     const int cu = L.n_cu > 0 ? L.n_cu : device_cu_count();
     const int blocks = std::min(cu * L.blocks_per_cu, kMaxGridBlocks);
     hipStream_t st = (hipStream_t)stream;
-    TransportWs w = carve_transport(d_ws, q->el.capacity / q->n_ebuckets);
+    TransportWs w = carve_transport(d_ws, q->ph.capacity);
     PhDev P{ph->nx, ph->ny, ph->nz, (float)ph->x0, (float)ph->y0,
             (float)ph->z0, (float)ph->dx, (float)ph->dy, (float)ph->dz,
             (float)(1.0 / ph->dx), (float)(1.0 / ph->dy),
@@ -834,7 +840,8 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
                                part_el);
     }
     if ((s = stats_reduce(w.part, 2 * blocks, d_stats, st))) return s;
-    hipLaunchKernelGGL(k_consume, dim3(1), dim3(64), 0, st, q->d_counts);
+    hipLaunchKernelGGL(k_consume, dim3(1), dim3(64), 0, st, q->d_counts,
+                       q->n_ebuckets, d_stats);
     PSL_LAUNCHED();
     return PSL_OK;
 }

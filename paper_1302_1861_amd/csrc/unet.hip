@@ -1,0 +1,931 @@
+// The dose denoiser: a fixed 4-level 3D U-Net trained and run by this
+// library's own kernels.
+//
+// Tensors are channels-last (N, D, H, W, C) bf16 with C a multiple of 8.
+// The 3x3x3 convolutions (zero padding 1) are implicit GEMMs on the gfx950
+// MFMA unit (mfma_f32_16x16x32_bf16, fp32 accumulation): a wave computes 16
+// consecutive voxels x all output channels; the K dimension runs over
+// (offset, input channel) in chunks of 32, each lane loading 8 contiguous
+// input channels of one neighbour (16 bytes) and 8 contiguous weights.
+//   forward  y = act(conv(x, W) + b)               (k_conv3)
+//   dgrad    dx = conv(dy, W') * (x > 0)            (k_conv3 with W' the
+//            offset-flipped, channel-transposed weights and a ReLU mask)
+//   wgrad    dW[co][o][ci] = sum_v dy[v][co] x[v+o][ci]  (k_conv3_wgrad:
+//            dy and shifted x tiles staged in LDS, MFMA over voxels,
+//            fp32 atomics per tile)
+// Average pooling, nearest up-sampling, channel concatenation, the 1x1
+// residual head, the MSE loss and Adam are plain streaming kernels.
+#include "common.hpp"
+
+#include <hip/hip_bf16.h>
+
+#include <cmath>
+#include <vector>
+
+namespace psl {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef uint16_t bf16_t;   // storage type
+
+__device__ __forceinline__ float bf2f(bf16_t v) {
+    return __uint_as_float((uint32_t)v << 16);
+}
+// round to nearest even
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)((u >> 16) | 0x40);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+
+struct Vol {
+    int n, d, h, w;
+    __host__ __device__ int64_t voxels() const {
+        return (int64_t)n * d * h * w;
+    }
+};
+
+constexpr int kMaxCout = 128;
+
+// ------------------------------------------------------------ conv 3x3x3 --
+// y[v][co] = epilogue(sum_{o,ci} x[v + o][ci] W[co][o*Cin + ci]),
+// W rows padded to Kp = roundup(27 Cin, 32) with zeros.
+template <int NB>   // output channel blocks of 16
+__global__ void __launch_bounds__(256)
+k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
+        const bf16_t *__restrict__ W, int Kp, const float *__restrict__ bias,
+        int relu, const bf16_t *__restrict__ mask, int mask_c,
+        bf16_t *__restrict__ y, int Cout) {
+    const int lane = __lane_id();
+    const int64_t tile = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    const int64_t nvox = V.voxels();
+    if (tile >= nvox) return;
+    // the A row of this lane: voxel tile + lane % 16
+    const int64_t v = tile + (lane & 15);
+    const bool vok = v < nvox;
+    int vw = 0, vh = 0, vd = 0;
+    int64_t vn = 0;
+    if (vok) {
+        int64_t t = v;
+        vw = (int)(t % V.w); t /= V.w;
+        vh = (int)(t % V.h); t /= V.h;
+        vd = (int)(t % V.d); vn = t / V.d;
+    }
+    f32x4 acc[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = f32x4{0, 0, 0, 0};
+    const int kq = 8 * (lane >> 4);
+    for (int k0 = 0; k0 < Kp; k0 += 32) {
+        const int k = k0 + kq;
+        bf16x8 a;
+        const int o = k / Cin, ci = k - o * Cin;
+        bool ok = vok && o < 27;
+        int zz = 0, yy = 0, xx = 0;
+        if (ok) {
+            zz = vd + o / 9 - 1;
+            yy = vh + (o / 3) % 3 - 1;
+            xx = vw + o % 3 - 1;
+            ok = (unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
+                 (unsigned)xx < (unsigned)V.w;
+        }
+        if (ok) {
+            const int64_t nb = ((vn * V.d + zz) * V.h + yy) * V.w + xx;
+            a = *reinterpret_cast<const bf16x8 *>(x + nb * Cin + ci);
+        } else {
+            a = bf16x8{};
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int co = b * 16 + (lane & 15);
+            const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
+                W + (int64_t)co * Kp + k);
+            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wv, acc[b], 0,
+                                                            0, 0);
+        }
+    }
+    // acc[b][r] is (voxel tile + 4 (lane/16) + r, channel 16 b + lane % 16)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int co = b * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t vv = tile + 4 * (lane >> 4) + r;
+            if (vv >= nvox || co >= Cout) continue;
+            float val = acc[b][r] + (bias ? bias[co] : 0.0f);
+            if (relu) val = fmaxf(val, 0.0f);
+            if (mask && !(bf2f(mask[vv * mask_c + co]) > 0.0f)) val = 0.0f;
+            y[vv * Cout + co] = f2bf(val);
+        }
+    }
+}
+
+// W'[ci][o'][co] = W[co][26 - o'][ci]: the weights of the transposed
+// convolution (data gradient), padded to Kp2 = roundup(27 Cout, 32).
+__global__ void k_flip_weights(const bf16_t *__restrict__ W, int Cin,
+                               int Cout, int Kp, bf16_t *__restrict__ Wt,
+                               int Kp2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)Cin * Kp2) return;
+    const int ci = (int)(i / Kp2), k = (int)(i % Kp2);
+    bf16_t v = 0;
+    if (k < 27 * Cout) {
+        const int o2 = k / Cout, co = k % Cout;
+        v = W[(int64_t)co * Kp + (26 - o2) * Cin + ci];
+    }
+    Wt[i] = v;
+}
+
+// dW[co][o][ci] += sum over a voxel chunk of dy[v][co] x[v + o][ci].  One
+// block per (offset, voxel chunk); 32 voxels at a time are staged in LDS;
+// each wave owns 16x16 output tiles.
+constexpr int kWgVox = 32;
+__global__ void __launch_bounds__(256)
+k_conv3_wgrad(const bf16_t *__restrict__ x, Vol V, int Cin,
+              const bf16_t *__restrict__ dy, int Cout, int64_t chunk,
+              float *__restrict__ dW, int Kp) {
+    __shared__ bf16_t s_dy[kWgVox * kMaxCout];
+    __shared__ bf16_t s_x[kWgVox * 256];
+    const int o = blockIdx.y;
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int dz = o / 9 - 1, dyo = (o / 3) % 3 - 1, dx = o % 3 - 1;
+    const int64_t nvox = V.voxels();
+    const int64_t v0 = (int64_t)blockIdx.x * chunk;
+    const int64_t v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
+    const int mt = Cout / 16, nt = Cin / 16;
+    const int n_tiles = mt * nt;
+    // up to 16 (co, ci) 16x16 tiles per wave
+    f32x4 acc[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) acc[t] = f32x4{0, 0, 0, 0};
+    for (int64_t vb = v0; vb < v1; vb += kWgVox) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < kWgVox * Cout; i += 256) {
+            const int vi = i / Cout, c = i % Cout;
+            const int64_t v = vb + vi;
+            s_dy[i] = v < v1 ? dy[v * Cout + c] : (bf16_t)0;
+        }
+        for (int i = threadIdx.x; i < kWgVox * Cin; i += 256) {
+            const int vi = i / Cin, c = i % Cin;
+            const int64_t v = vb + vi;
+            bf16_t val = 0;
+            if (v < v1) {
+                int64_t t = v;
+                const int w = (int)(t % V.w); t /= V.w;
+                const int h = (int)(t % V.h); t /= V.h;
+                const int d = (int)(t % V.d);
+                const int64_t n = t / V.d;
+                const int zz = d + dz, yy = h + dyo, xx = w + dx;
+                if ((unsigned)zz < (unsigned)V.d &&
+                    (unsigned)yy < (unsigned)V.h &&
+                    (unsigned)xx < (unsigned)V.w)
+                    val = x[(((n * V.d + zz) * V.h + yy) * V.w + xx) * Cin + c];
+            }
+            s_x[i] = val;
+        }
+        __syncthreads();
+        // A[i = co][k = voxel], B[k = voxel][j = ci]
+        const int kk = 8 * (lane >> 4);
+#pragma unroll
+        for (int slot = 0; slot < 16; ++slot) {
+            const int t = wid + 4 * slot;
+            if (t >= n_tiles) break;
+            const int cb = t / nt, ib = t % nt;
+            bf16x8 a, b;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int co = cb * 16 + (lane & 15);
+                const int ci = ib * 16 + (lane & 15);
+                a[j] = __builtin_bit_cast(__bf16,
+                                          s_dy[(kk + j) * Cout + co]);
+                b[j] = __builtin_bit_cast(__bf16, s_x[(kk + j) * Cin + ci]);
+            }
+            acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a, b, acc[slot], 0, 0, 0);
+        }
+    }
+    // acc[slot][r] is (co = 16 cb + 4 (lane/16) + r, ci = 16 ib + lane%16)
+#pragma unroll
+    for (int slot = 0; slot < 16; ++slot) {
+        const int t = wid + 4 * slot;
+        if (t >= n_tiles) break;
+        const int cb = t / nt, ib = t % nt;
+        const int ci = ib * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = cb * 16 + 4 * (lane >> 4) + r;
+            unsafeAtomicAdd(&dW[(int64_t)co * Kp + o * Cin + ci],
+                            acc[slot][r]);
+        }
+    }
+}
+
+// dbias[co] += sum_v dy[v][co]
+__global__ void __launch_bounds__(256)
+k_bias_grad(const bf16_t *__restrict__ dy, int64_t nvox, int C,
+            float *__restrict__ db) {
+    __shared__ float s[256];
+    const int c = threadIdx.x % C;
+    const int rows = 256 / C;
+    const int r0 = threadIdx.x / C;
+    float acc = 0.0f;
+    if (threadIdx.x < rows * C)
+        for (int64_t v = (int64_t)blockIdx.x * rows + r0; v < nvox;
+             v += (int64_t)gridDim.x * rows)
+            acc += bf2f(dy[v * C + c]);
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        float t = 0.0f;
+        for (int r = 0; r < rows; ++r) t += s[r * C + threadIdx.x];
+        unsafeAtomicAdd(&db[threadIdx.x], t);
+    }
+}
+
+// ------------------------------------------------------ pooling and such --
+// average of 2x2x2 children
+__global__ void k_pool(const bf16_t *__restrict__ x, Vol V, int C,
+                       bf16_t *__restrict__ y) {
+    const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= U.voxels() * C) return;
+    const int c = (int)(i % C);
+    int64_t t = i / C;
+    const int w = (int)(t % U.w); t /= U.w;
+    const int h = (int)(t % U.h); t /= U.h;
+    const int d = (int)(t % U.d);
+    const int64_t n = t / U.d;
+    float s = 0.0f;
+    for (int a = 0; a < 8; ++a) {
+        const int zz = 2 * d + (a >> 2), yy = 2 * h + ((a >> 1) & 1),
+                  xx = 2 * w + (a & 1);
+        s += bf2f(x[(((n * V.d + zz) * V.h + yy) * V.w + xx) * C + c]);
+    }
+    y[i] = f2bf(0.125f * s);
+}
+
+// gradient of the average pool: each child gets dy / 8
+__global__ void k_pool_back(const bf16_t *__restrict__ dy, Vol V, int C,
+                            bf16_t *__restrict__ dx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V.voxels() * C) return;
+    const int c = (int)(i % C);
+    int64_t t = i / C;
+    const int w = (int)(t % V.w); t /= V.w;
+    const int h = (int)(t % V.h); t /= V.h;
+    const int d = (int)(t % V.d);
+    const int64_t n = t / V.d;
+    const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
+    const int64_t u = ((n * U.d + d / 2) * U.h + h / 2) * U.w + w / 2;
+    dx[i] = f2bf(0.125f * bf2f(dy[u * C + c]));
+}
+
+// out = concat(nearest-upsampled a [coarse, Ca], b [fine, Cb]) on the fine
+// grid V
+__global__ void k_up_concat(const bf16_t *__restrict__ a, int Ca,
+                            const bf16_t *__restrict__ b, int Cb, Vol V,
+                            bf16_t *__restrict__ out) {
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V.voxels() * C) return;
+    const int c = (int)(i % C);
+    const int64_t v = i / C;
+    if (c >= Ca) {
+        out[i] = b[v * Cb + (c - Ca)];
+        return;
+    }
+    int64_t t = v;
+    const int w = (int)(t % V.w); t /= V.w;
+    const int h = (int)(t % V.h); t /= V.h;
+    const int d = (int)(t % V.d);
+    const int64_t n = t / V.d;
+    const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
+    const int64_t u = ((n * U.d + d / 2) * U.h + h / 2) * U.w + w / 2;
+    out[i] = a[u * Ca + c];
+}
+
+// split the gradient of concat: the up-sampling part summed over the 8
+// children into da (coarse), the skip part added into db (fine, times the
+// ReLU mask of the skip activation)
+__global__ void k_up_concat_back_a(const bf16_t *__restrict__ g, int Ca,
+                                   int Cb, Vol V, const bf16_t *__restrict__ am,
+                                   bf16_t *__restrict__ da) {
+    const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= U.voxels() * Ca) return;
+    const int c = (int)(i % Ca);
+    int64_t t = i / Ca;
+    const int w = (int)(t % U.w); t /= U.w;
+    const int h = (int)(t % U.h); t /= U.h;
+    const int d = (int)(t % U.d);
+    const int64_t n = t / U.d;
+    float s = 0.0f;
+    for (int k = 0; k < 8; ++k) {
+        const int zz = 2 * d + (k >> 2), yy = 2 * h + ((k >> 1) & 1),
+                  xx = 2 * w + (k & 1);
+        s += bf2f(g[((((n * V.d + zz) * V.h + yy) * V.w + xx)) * C + c]);
+    }
+    if (am && !(bf2f(am[i]) > 0.0f)) s = 0.0f;
+    da[i] = f2bf(s);
+}
+
+__global__ void k_up_concat_back_b(const bf16_t *__restrict__ g, int Ca,
+                                   int Cb, Vol V, bf16_t *__restrict__ db) {
+    const int C = Ca + Cb;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V.voxels() * Cb) return;
+    const int c = (int)(i % Cb);
+    const int64_t v = i / Cb;
+    db[i] = g[v * C + Ca + c];
+}
+
+// out = (a + b) * (mask > 0)
+__global__ void k_add_mask(const bf16_t *__restrict__ a,
+                           const bf16_t *__restrict__ b,
+                           const bf16_t *__restrict__ mask, int64_t n,
+                           bf16_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float s = bf2f(a[i]) + (b ? bf2f(b[i]) : 0.0f);
+    out[i] = f2bf(bf2f(mask[i]) > 0.0f ? s : 0.0f);
+}
+
+constexpr int kInC = 16;   // input channels: dose, density, 14 zeros
+
+// per-sample normalisation: scale[n] = 1 / max(dose of sample n)
+__global__ void __launch_bounds__(256)
+k_sample_scale(const float *__restrict__ dose, int64_t per_sample,
+               float *__restrict__ scale) {
+    __shared__ float s[256];
+    const float *d = dose + (int64_t)blockIdx.x * per_sample;
+    float m = 0.0f;
+    for (int64_t i = threadIdx.x; i < per_sample; i += 256)
+        m = fmaxf(m, d[i]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) s[threadIdx.x] = fmaxf(s[threadIdx.x],
+                                                    s[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) scale[blockIdx.x] = s[0] > 0.0f ? 1.0f / s[0] : 1.0f;
+}
+
+// input tensor: channels (dose * scale, density, 0 ...)
+__global__ void k_pack_input(const float *__restrict__ dose,
+                             const float *__restrict__ rho, int64_t nvox,
+                             int64_t per_sample, const float *__restrict__ scale,
+                             bf16_t *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nvox * kInC) return;
+    const int c = (int)(i % kInC);
+    const int64_t v = i / kInC;
+    float val = c == 0 ? dose[v] * scale[v / per_sample]
+                       : (c == 1 ? rho[v] : 0.0f);
+    x[i] = f2bf(val);
+}
+
+// out[v] = dose[v] * scale + sum_c f[v][c] wh[c] + bh  (normalised units)
+__global__ void k_head(const bf16_t *__restrict__ f, int C,
+                       const float *__restrict__ wh, const float *__restrict__ bh,
+                       const float *__restrict__ dose, int64_t per_sample,
+                       const float *__restrict__ scale, int64_t nvox,
+                       float *__restrict__ out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    float s = bh[0];
+    for (int c = 0; c < C; ++c) s += bf2f(f[v * C + c]) * wh[c];
+    out[v] = dose[v] * scale[v / per_sample] + s;
+}
+
+// loss = mean over voxels of (out - target * scale)^2; g = dL/dout; head
+// gradients; df = g wh masked by the ReLU of f
+__global__ void __launch_bounds__(256)
+k_loss_head_back(const float *__restrict__ out, const float *__restrict__ tgt,
+                 int64_t per_sample, const float *__restrict__ scale,
+                 int64_t nvox, const bf16_t *__restrict__ f,
+                 const float *__restrict__ wh, float *__restrict__ dwh,
+                 float *__restrict__ dbh, bf16_t *__restrict__ df,
+                 double *__restrict__ loss) {
+    constexpr int C = 16;
+    __shared__ float s_r[256];
+    const float inv_n = 1.0f / (float)nvox;
+    float l = 0.0f, gb = 0.0f;
+    float gw[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) gw[c] = 0.0f;
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < nvox;
+         v += (int64_t)gridDim.x * 256) {
+        const float e = out[v] - tgt[v] * scale[v / per_sample];
+        l += e * e;
+        const float g = 2.0f * e * inv_n;
+        gb += g;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float fv = bf2f(f[v * C + c]);
+            gw[c] += g * fv;
+            df[v * C + c] = f2bf(fv > 0.0f ? g * wh[c] : 0.0f);
+        }
+    }
+    // block sums of l, gb and gw[0..15], one value at a time
+    for (int q = 0; q < C + 2; ++q) {
+        float val = q == 0 ? l : (q == 1 ? gb : gw[0]);
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (q == c + 2) val = gw[c];
+        s_r[threadIdx.x] = val;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) s_r[threadIdx.x] += s_r[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (q == 0) unsafeAtomicAdd(loss, (double)(s_r[0] * inv_n));
+            else if (q == 1) unsafeAtomicAdd(dbh, s_r[0]);
+            else unsafeAtomicAdd(&dwh[q - 2], s_r[0]);
+        }
+        __syncthreads();
+    }
+}
+
+// de-normalise: y = o / scale of the sample
+__global__ void k_out_scale(const float *__restrict__ o, int64_t n,
+                            int64_t per_sample, const float *__restrict__ scale,
+                            float *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = o[i] / scale[i / per_sample];
+}
+
+// Adam on the fp32 master parameters, then the bf16 copies of the conv
+// weights (layout: per layer W [Cout][Kp] then b [Cout]).
+__global__ void k_adam(float *__restrict__ p, const float *__restrict__ g,
+                       float *__restrict__ m, float *__restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+__global__ void k_to_bf16(const float *__restrict__ p, int64_t n,
+                          bf16_t *__restrict__ q) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) q[i] = f2bf(p[i]);
+}
+
+__global__ void k_fill_f32(float *p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// He-normal initialisation from a counter-based generator (Philox,
+// Box-Muller); biases zero.
+__global__ void k_init_layer(float *__restrict__ W, int Cout, int Kp,
+                             int K, float stdv, uint64_t seed,
+                             uint32_t layer) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)Cout * Kp) return;
+    const int k = (int)(i % Kp);
+    if (k >= K) {
+        W[i] = 0.0f;
+        return;
+    }
+    u32x4 r = philox4x32_10(u32x4{(uint32_t)i, layer, 0x5eedu, 0u},
+                            (uint32_t)seed, (uint32_t)(seed >> 32));
+    const float u1 = u01(r.x), u2 = u01(r.y);
+    W[i] = stdv * sqrtf(-2.0f * __logf(u1)) * __cosf(6.2831853f * u2);
+}
+
+}  // namespace
+}  // namespace psl
+
+// ============================================================== host side ==
+namespace psl {
+namespace {
+
+struct ConvL {
+    int cin, cout, kp;
+    int64_t w_off, b_off;
+};
+
+// The fixed architecture: 4 levels of 16/32/64/128 channels.
+struct Net {
+    std::vector<ConvL> L;
+    int64_t head_w = 0, head_b = 0, n_params = 0;
+};
+
+enum {
+    E0A, E0B, E1A, E1B, E2A, E2B, E3A, E3B, D2A, D2B, D1A, D1B, D0A, D0B,
+    N_CONV
+};
+
+Net make_net(int base) {
+    Net n;
+    const int c0 = base, c1 = 2 * base, c2 = 4 * base, c3 = 8 * base;
+    const int io[N_CONV][2] = {{kInC, c0}, {c0, c0},      {c0, c1},
+                               {c1, c1},   {c1, c2},      {c2, c2},
+                               {c2, c3},   {c3, c3},      {c3 + c2, c2},
+                               {c2, c2},   {c2 + c1, c1}, {c1, c1},
+                               {c1 + c0, c0}, {c0, c0}};
+    int64_t off = 0;
+    for (int i = 0; i < N_CONV; ++i) {
+        ConvL l;
+        l.cin = io[i][0];
+        l.cout = io[i][1];
+        l.kp = (27 * l.cin + 31) / 32 * 32;
+        l.w_off = off;
+        off += (int64_t)l.cout * l.kp;
+        l.b_off = off;
+        off += l.cout;
+        n.L.push_back(l);
+    }
+    n.head_w = off;
+    off += c0;
+    n.head_b = off;
+    off += 8;   // keeps the blob a multiple of 8 floats
+    n.n_params = off;
+    return n;
+}
+
+struct Acts {
+    Vol V[4];
+    bf16_t *xin, *e0a, *e0b, *p1, *e1a, *e1b, *p2, *e2a, *e2b, *p3, *e3a,
+        *e3b, *cat2, *d2a, *d2b, *cat1, *d1a, *d1b, *cat0, *d0a, *d0b;
+    float *out, *scale;
+    // backward
+    bf16_t *gA, *gB, *gC, *sk0, *sk1, *sk2, *wt;
+    size_t bytes;
+};
+
+Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
+    Carver c(base);
+    Acts a;
+    for (int l = 0; l < 4; ++l) a.V[l] = Vol{n, d >> l, h >> l, w >> l};
+    const int64_t v0 = a.V[0].voxels(), v1 = a.V[1].voxels(),
+                  v2 = a.V[2].voxels(), v3 = a.V[3].voxels();
+    const int c0 = b, c1 = 2 * b, c2 = 4 * b, c3 = 8 * b;
+    a.xin = c.take<bf16_t>(v0 * kInC);
+    a.e0a = c.take<bf16_t>(v0 * c0);
+    a.e0b = c.take<bf16_t>(v0 * c0);
+    a.p1 = c.take<bf16_t>(v1 * c0);
+    a.e1a = c.take<bf16_t>(v1 * c1);
+    a.e1b = c.take<bf16_t>(v1 * c1);
+    a.p2 = c.take<bf16_t>(v2 * c1);
+    a.e2a = c.take<bf16_t>(v2 * c2);
+    a.e2b = c.take<bf16_t>(v2 * c2);
+    a.p3 = c.take<bf16_t>(v3 * c2);
+    a.e3a = c.take<bf16_t>(v3 * c3);
+    a.e3b = c.take<bf16_t>(v3 * c3);
+    a.cat2 = c.take<bf16_t>(v2 * (c3 + c2));
+    a.d2a = c.take<bf16_t>(v2 * c2);
+    a.d2b = c.take<bf16_t>(v2 * c2);
+    a.cat1 = c.take<bf16_t>(v1 * (c2 + c1));
+    a.d1a = c.take<bf16_t>(v1 * c1);
+    a.d1b = c.take<bf16_t>(v1 * c1);
+    a.cat0 = c.take<bf16_t>(v0 * (c1 + c0));
+    a.d0a = c.take<bf16_t>(v0 * c0);
+    a.d0b = c.take<bf16_t>(v0 * c0);
+    a.out = c.take<float>(v0);
+    a.scale = c.take<float>(n);
+    a.gA = a.gB = a.gC = a.sk0 = a.sk1 = a.sk2 = a.wt = nullptr;
+    if (train) {
+        const int64_t big = std::max({v0 * (c1 + c0), v1 * (c2 + c1),
+                                      v2 * (c3 + c2)});
+        a.gA = c.take<bf16_t>(big);
+        a.gB = c.take<bf16_t>(big);
+        a.gC = c.take<bf16_t>(big);
+        a.sk0 = c.take<bf16_t>(v0 * c0);
+        a.sk1 = c.take<bf16_t>(v1 * c1);
+        a.sk2 = c.take<bf16_t>(v2 * c2);
+        a.wt = c.take<bf16_t>((int64_t)(c3 + c2) * ((27 * c3 + 31) / 32 * 32));
+    }
+    a.bytes = c.used;
+    return a;
+}
+
+unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+template <int NB>
+void launch_conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
+                 const float *bias, int relu, const bf16_t *mask, int mask_c,
+                 bf16_t *y, int cout, hipStream_t st) {
+    hipLaunchKernelGGL(k_conv3<NB>, dim3(nblk(V.voxels(), 64)), dim3(256), 0,
+                       st, x, V, cin, W, kp, bias, relu, mask, mask_c, y,
+                       cout);
+}
+
+psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
+                const float *bias, int relu, const bf16_t *mask, bf16_t *y,
+                int cout, hipStream_t st) {
+    switch (cout / 16) {
+    case 1: launch_conv<1>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 2: launch_conv<2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 3: launch_conv<3>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 4: launch_conv<4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 6: launch_conv<6>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 8: launch_conv<8>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 12: launch_conv<12>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    default:
+        set_error("unsupported channel count %d", cout);
+        return PSL_EINVAL;
+    }
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+struct Ctx {
+    Net net;
+    const float *p;       // fp32 master
+    const bf16_t *pb;     // bf16 copy
+    hipStream_t st;
+};
+
+psl_status forward(const Ctx &c, const Acts &a, const float *dose,
+                   const float *rho) {
+    psl_status s;
+    const auto &L = c.net.L;
+    auto W = [&](int i) { return c.pb + L[i].w_off; };
+    auto B = [&](int i) { return c.p + L[i].b_off; };
+    const Vol *V = a.V;
+    const int64_t per = V[0].voxels() / V[0].n;
+    hipLaunchKernelGGL(k_sample_scale, dim3(V[0].n), dim3(256), 0, c.st, dose,
+                       per, a.scale);
+    hipLaunchKernelGGL(k_pack_input, dim3(nblk(V[0].voxels() * kInC)),
+                       dim3(256), 0, c.st, dose, rho, V[0].voxels(), per,
+                       a.scale, a.xin);
+    // encoder
+    bf16_t *ins[4] = {a.xin, a.p1, a.p2, a.p3};
+    bf16_t *ea[4] = {a.e0a, a.e1a, a.e2a, a.e3a};
+    bf16_t *eb[4] = {a.e0b, a.e1b, a.e2b, a.e3b};
+    bf16_t *pools[3] = {a.p1, a.p2, a.p3};
+    for (int l = 0; l < 4; ++l) {
+        const ConvL &la = L[2 * l], &lb = L[2 * l + 1];
+        if ((s = conv(ins[l], V[l], la.cin, W(2 * l), la.kp, B(2 * l), 1,
+                      nullptr, ea[l], la.cout, c.st)))
+            return s;
+        if ((s = conv(ea[l], V[l], lb.cin, W(2 * l + 1), lb.kp, B(2 * l + 1),
+                      1, nullptr, eb[l], lb.cout, c.st)))
+            return s;
+        if (l < 3)
+            hipLaunchKernelGGL(k_pool, dim3(nblk(V[l + 1].voxels() * lb.cout)),
+                               dim3(256), 0, c.st, eb[l], V[l], lb.cout,
+                               pools[l]);
+    }
+    // decoder
+    bf16_t *cats[3] = {a.cat0, a.cat1, a.cat2};
+    bf16_t *da[3] = {a.d0a, a.d1a, a.d2a};
+    bf16_t *db[3] = {a.d0b, a.d1b, a.d2b};
+    const bf16_t *coarse = a.e3b;
+    int cc = L[E3B].cout;
+    for (int l = 2; l >= 0; --l) {
+        const int ia = (l == 2) ? D2A : (l == 1 ? D1A : D0A);
+        const ConvL &la = L[ia], &lb = L[ia + 1];
+        const int cf = L[2 * l + 1].cout;
+        hipLaunchKernelGGL(k_up_concat, dim3(nblk(V[l].voxels() * (cc + cf))),
+                           dim3(256), 0, c.st, coarse, cc, eb[l], cf, V[l],
+                           cats[l]);
+        if ((s = conv(cats[l], V[l], la.cin, W(ia), la.kp, B(ia), 1, nullptr,
+                      da[l], la.cout, c.st)))
+            return s;
+        if ((s = conv(da[l], V[l], lb.cin, W(ia + 1), lb.kp, B(ia + 1), 1,
+                      nullptr, db[l], lb.cout, c.st)))
+            return s;
+        coarse = db[l];
+        cc = lb.cout;
+    }
+    hipLaunchKernelGGL(k_head, dim3(nblk(V[0].voxels())), dim3(256), 0, c.st,
+                       a.d0b, L[D0B].cout, c.p + c.net.head_w,
+                       c.p + c.net.head_b, dose, per, a.scale, V[0].voxels(),
+                       a.out);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+// weight and bias gradients of layer i, then (if dx) its data gradient
+psl_status layer_back(const Ctx &c, const Acts &a, int i, const bf16_t *x,
+                      Vol V, const bf16_t *dy, float *grads, bf16_t *dx,
+                      const bf16_t *dx_mask) {
+    const ConvL &l = c.net.L[i];
+    const int64_t nv = V.voxels();
+    int64_t chunk = std::max<int64_t>(1024, (nv / 256 + 31) / 32 * 32);
+    const unsigned nch = (unsigned)((nv + chunk - 1) / chunk);
+    hipLaunchKernelGGL(k_conv3_wgrad, dim3(nch, 27), dim3(256), 0, c.st, x, V,
+                       l.cin, dy, l.cout, chunk, grads + l.w_off, l.kp);
+    hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, c.st, dy, nv,
+                       l.cout, grads + l.b_off);
+    if (dx) {
+        const int kp2 = (27 * l.cout + 31) / 32 * 32;
+        hipLaunchKernelGGL(k_flip_weights, dim3(nblk((int64_t)l.cin * kp2)),
+                           dim3(256), 0, c.st, c.pb + l.w_off, l.cin, l.cout,
+                           l.kp, a.wt, kp2);
+        psl_status s = conv(dy, V, l.cout, a.wt, kp2, nullptr, 0, dx_mask, dx,
+                            l.cin, c.st);
+        if (s) return s;
+    }
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+psl_status backward(const Ctx &c, const Acts &a, const float *tgt,
+                    float *grads, double *loss) {
+    psl_status s;
+    const auto &L = c.net.L;
+    const Vol *V = a.V;
+    const int64_t per = V[0].voxels() / V[0].n;
+    bf16_t *g = a.gA, *g2 = a.gB, *t = a.gC;
+    hipLaunchKernelGGL(k_loss_head_back, dim3(512), dim3(256), 0, c.st, a.out,
+                       tgt, per, a.scale, V[0].voxels(), a.d0b,
+                       c.p + c.net.head_w, grads + c.net.head_w,
+                       grads + c.net.head_b, g, loss);
+    // decoder, level 0 .. 2 (gradient g of the level's output d_lb)
+    bf16_t *cats[3] = {a.cat0, a.cat1, a.cat2};
+    bf16_t *da[3] = {a.d0a, a.d1a, a.d2a};
+    bf16_t *db[3] = {a.d0b, a.d1b, a.d2b};
+    bf16_t *sk[3] = {a.sk0, a.sk1, a.sk2};
+    const int ia_of[3] = {D0A, D1A, D2A};
+    for (int l = 0; l < 3; ++l) {
+        const int ia = ia_of[l];
+        // d_lb = relu(conv(d_la)); g is its masked gradient
+        if ((s = layer_back(c, a, ia + 1, da[l], V[l], g, grads, g2, da[l])))
+            return s;
+        // d_la = relu(conv(cat)); g2 its masked gradient -> gradient of cat
+        if ((s = layer_back(c, a, ia, cats[l], V[l], g2, grads, t, nullptr)))
+            return s;
+        const int cf = L[2 * l + 1].cout;          // skip channels
+        const int cc = L[ia].cin - cf;             // up-sampled channels
+        const bf16_t *coarse_act = (l == 2) ? a.e3b : db[l + 1];
+        hipLaunchKernelGGL(k_up_concat_back_a, dim3(nblk(V[l + 1].voxels() * cc)),
+                           dim3(256), 0, c.st, t, cc, cf, V[l], coarse_act, g);
+        hipLaunchKernelGGL(k_up_concat_back_b, dim3(nblk(V[l].voxels() * cf)),
+                           dim3(256), 0, c.st, t, cc, cf, V[l], sk[l]);
+    }
+    // encoder, level 3 .. 0 (g: masked gradient of e_lb)
+    bf16_t *ins[4] = {a.xin, a.p1, a.p2, a.p3};
+    bf16_t *ea[4] = {a.e0a, a.e1a, a.e2a, a.e3a};
+    bf16_t *eb[4] = {a.e0b, a.e1b, a.e2b, a.e3b};
+    for (int l = 3; l >= 0; --l) {
+        if ((s = layer_back(c, a, 2 * l + 1, ea[l], V[l], g, grads, g2,
+                            ea[l])))
+            return s;
+        if ((s = layer_back(c, a, 2 * l, ins[l], V[l], g2, grads,
+                            l > 0 ? t : nullptr, nullptr)))
+            return s;
+        if (l > 0) {
+            // gradient of p_l -> e_(l-1)b: pool back, add the skip part,
+            // ReLU mask of e_(l-1)b
+            const int C = L[2 * l - 1].cout;
+            const int64_t n = V[l - 1].voxels() * C;
+            hipLaunchKernelGGL(k_pool_back, dim3(nblk(n)), dim3(256), 0, c.st,
+                               t, V[l - 1], C, g2);
+            hipLaunchKernelGGL(k_add_mask, dim3(nblk(n)), dim3(256), 0, c.st,
+                               g2, sk[l - 1], eb[l - 1], n, g);
+        }
+    }
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+psl_status check_net(const psl_unet *u, int n, int d, int h, int w) {
+    PSL_REQUIRE(u && u->params && u->params_bf16, "NULL network");
+    PSL_REQUIRE(u->levels == 4 && u->base == 16,
+                "this build has the 4-level, 16-channel network only");
+    PSL_REQUIRE(u->n_params == make_net(u->base).n_params,
+                "n_params %lld does not match the architecture",
+                (long long)u->n_params);
+    PSL_REQUIRE(n >= 1 && d >= 8 && h >= 8 && w >= 8 && d % 8 == 0 &&
+                    h % 8 == 0 && w % 8 == 0,
+                "volume must be at least 8 voxels and divisible by 8 per "
+                "axis");
+    return PSL_OK;
+}
+
+}  // namespace
+}  // namespace psl
+
+using namespace psl;
+
+extern "C" int64_t unet_param_count(int32_t levels, int32_t base) {
+    if (levels != 4 || base != 16) return 0;
+    return make_net(base).n_params;
+}
+
+extern "C" size_t unet_workspace_bytes(const psl_unet *u, int32_t n,
+                                       int32_t nz, int32_t ny, int32_t nx,
+                                       int32_t training) {
+    if (!u || n < 1 || nz < 8 || ny < 8 || nx < 8) return 0;
+    return carve_acts(nullptr, n, nz, ny, nx, u->base, training != 0).bytes;
+}
+
+extern "C" psl_status unet_init(psl_unet *u, uint64_t seed, void *stream) {
+    PSL_REQUIRE(u && u->params && u->params_bf16, "NULL network");
+    PSL_REQUIRE(u->levels == 4 && u->base == 16, "unsupported architecture");
+    Net net = make_net(u->base);
+    PSL_REQUIRE(u->n_params == net.n_params, "n_params mismatch");
+    if (psl_status s = check_device()) return s;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(net.n_params)), dim3(256), 0, st,
+                       u->params, net.n_params, 0.0f);
+    for (int i = 0; i < N_CONV; ++i) {
+        const ConvL &l = net.L[i];
+        const float stdv = std::sqrt(2.0f / (27.0f * (float)l.cin));
+        hipLaunchKernelGGL(k_init_layer, dim3(nblk((int64_t)l.cout * l.kp)),
+                           dim3(256), 0, st, u->params + l.w_off, l.cout,
+                           l.kp, 27 * l.cin, stdv, seed, (uint32_t)i);
+    }
+    // the head starts at zero: the initial prediction is the input dose
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(net.n_params)), dim3(256), 0, st,
+                       u->params, net.n_params, u->params_bf16);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+extern "C" psl_status unet_forward(const psl_unet *u, const float *d_dose,
+                                   const float *d_density, int32_t n,
+                                   int32_t nz, int32_t ny, int32_t nx,
+                                   float *d_out, void *d_ws, size_t ws_bytes,
+                                   void *stream) {
+    psl_status s = check_net(u, n, nz, ny, nx);
+    if (s) return s;
+    PSL_REQUIRE(d_dose && d_density && d_out, "NULL argument");
+    Acts need = carve_acts(nullptr, n, nz, ny, nx, u->base, false);
+    if (!d_ws || ws_bytes < need.bytes) {
+        set_error("workspace %zu bytes < %zu required", ws_bytes, need.bytes);
+        return PSL_ENOSPC;
+    }
+    if ((s = check_device())) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Acts a = carve_acts(d_ws, n, nz, ny, nx, u->base, false);
+    Ctx c{make_net(u->base), u->params, u->params_bf16, st};
+    if ((s = forward(c, a, d_dose, d_density))) return s;
+    const int64_t nv = a.V[0].voxels();
+    hipLaunchKernelGGL(k_out_scale, dim3(nblk(nv)), dim3(256), 0, st, a.out,
+                       nv, nv / n, a.scale, d_out);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+extern "C" psl_status unet_backward(const psl_unet *u, const float *d_dose,
+                                    const float *d_density,
+                                    const float *d_target, int32_t n,
+                                    int32_t nz, int32_t ny, int32_t nx,
+                                    float *d_grads, double *d_loss,
+                                    void *d_ws, size_t ws_bytes,
+                                    void *stream) {
+    psl_status s = check_net(u, n, nz, ny, nx);
+    if (s) return s;
+    PSL_REQUIRE(d_dose && d_density && d_target && d_grads && d_loss,
+                "NULL argument");
+    Acts need = carve_acts(nullptr, n, nz, ny, nx, u->base, true);
+    if (!d_ws || ws_bytes < need.bytes) {
+        set_error("workspace %zu bytes < %zu required", ws_bytes, need.bytes);
+        return PSL_ENOSPC;
+    }
+    if ((s = check_device())) return s;
+    hipStream_t st = (hipStream_t)stream;
+    Acts a = carve_acts(d_ws, n, nz, ny, nx, u->base, true);
+    Ctx c{make_net(u->base), u->params, u->params_bf16, st};
+    if ((s = forward(c, a, d_dose, d_density))) return s;
+    return backward(c, a, d_target, d_grads, d_loss);
+}
+
+extern "C" psl_status unet_adam_step(psl_unet *u, float *d_grads, float *d_m,
+                                     float *d_v, float lr, float beta1,
+                                     float beta2, float eps, int32_t step,
+                                     void *stream) {
+    PSL_REQUIRE(u && u->params && u->params_bf16 && d_grads && d_m && d_v,
+                "NULL argument");
+    PSL_REQUIRE(step >= 1, "step counts from 1");
+    PSL_REQUIRE(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 &&
+                    eps > 0,
+                "bad Adam hyper-parameters");
+    if (psl_status s = check_device()) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = u->n_params;
+    const float c1 = 1.0f / (1.0f - std::pow(beta1, (float)step));
+    const float c2 = 1.0f / (1.0f - std::pow(beta2, (float)step));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n)), dim3(256), 0, st, u->params,
+                       d_grads, d_m, d_v, n, lr, beta1, beta2, eps, c1, c2);
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(n)), dim3(256), 0, st, u->params,
+                       n, u->params_bf16);
+    hipLaunchKernelGGL(k_fill_f32, dim3(nblk(n)), dim3(256), 0, st, d_grads, n,
+                       0.0f);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+extern "C" psl_status dose_denoise(const float *d_dose,
+                                   const float *d_density, int32_t nx,
+                                   int32_t ny, int32_t nz,
+                                   const psl_unet *net, float *d_out,
+                                   void *d_ws, size_t ws_bytes,
+                                   void *stream) {
+    return unet_forward(net, d_dose, d_density, 1, nz, ny, nx, d_out, d_ws,
+                        ws_bytes, stream);
+}

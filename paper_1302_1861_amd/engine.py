@@ -211,6 +211,28 @@ class Engine:
             self.step(b)
         return self.finalize()
 
+    def make_plan(self, stream=None):
+        """A psl_plan over this engine's fields, queues and tallies."""
+        from . import Plan, _check, _ptr, _stream, make_phsp
+        import torch
+        stream = stream or torch.cuda.current_stream()
+        need = lib().psl_plan_workspace_bytes(C.byref(self.grid),
+                                              len(self.wl.fields), self.hpb,
+                                              C.byref(self.queue))
+        ws = _ws(need, self.device)
+        h = C.c_void_p()
+        srt = make_phsp(self.sorted, self.kept())
+        self.cfg.batch = 0
+        _check(lib().psl_plan_create(
+            C.byref(h), C.byref(srt), _ptr(self.offsets), C.byref(self.grid),
+            self.fields, len(self.fields), C.byref(self.cfg),
+            C.byref(self.queue), C.byref(self.phantom), C.byref(self.phys),
+            _ptr(self.tables), C.c_uint64(self.seed), C.byref(self.acc),
+            _ptr(self.s1), _ptr(self.s2), _ptr(self.stats),
+            C.byref(self.launch) if self.launch is not None else None,
+            _ptr(ws), ws.numel(), _stream(stream)))
+        return Plan(h, ws, stream)
+
     def stats_dict(self):
         """Batch statistics; `lost` includes entries a full queue region
         could not take."""

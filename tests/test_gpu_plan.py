@@ -1,0 +1,107 @@
+"""Batched plans: one allocation, many batches, eager or replayed from a
+hipGraph, and the autotuner.  The fixed-point dose is exact integer
+arithmetic and the random numbers are keyed by history, so every path must
+give bit-identical tallies."""
+import sys
+
+import numpy as np
+import pytest
+
+import psl_synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _imrt(n_particles=500_000):
+    wl = S.workload_imrt(n_particles=n_particles)
+    wl.phantom = S.water_phantom((64, 64, 64), 0.5, (-16.0, -16.0, 84.0))
+    return wl
+
+
+def _engine(wl, hpb, **kw):
+    import paper_1302_1861_amd as P
+    return P.Engine(wl, histories_per_batch=hpb, **kw)
+
+
+def test_plan_eager_equals_individual_calls():
+    import torch
+    wl = _imrt()
+    ref = _engine(wl, 300_000)
+    for b in range(3):
+        ref.step(b)
+    torch.cuda.synchronize()
+    want = ref.s1.cpu().numpy()
+    eng = _engine(wl, 300_000)
+    plan = eng.make_plan()
+    plan.run(0, 3, use_graph=False)
+    torch.cuda.synchronize()
+    got = eng.s1.cpu().numpy()
+    _say("plan eager", float(got.sum()), float(want.sum()))
+    assert got.any() and np.array_equal(got, want)
+    plan.destroy()
+
+
+def test_plan_graph_replays_equal_eager_every_batch():
+    import torch
+    wl = _imrt()
+    eager = _engine(wl, 250_000)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p_e = eager.make_plan()
+        graphed = _engine(wl, 250_000)
+        p_g = graphed.make_plan()
+        for b in range(4):
+            p_e.run(b, 1, use_graph=False)
+            torch.cuda.current_stream().synchronize()
+            want = eager.s1.cpu().numpy().copy()
+            # some eager work of the program between replays
+            x = torch.randn(1 << 20, device="cuda")
+            y = (x * 2.0).sum()
+            torch.cuda.current_stream().synchronize()
+            p_g.run(b, 1, use_graph=True)
+            torch.cuda.current_stream().synchronize()
+            got = graphed.s1.cpu().numpy()
+            _say("replay", b, float(got.sum()), float(y))
+            assert np.array_equal(got, want), b
+            st = graphed.stats_dict()
+            assert st["histories"] == 250_000 and st["lost"] == 0
+        # several replays in one call continue the batch sequence
+        p_e.run(4, 3, use_graph=False)
+        p_g.run(4, 3, use_graph=True)
+        torch.cuda.current_stream().synchronize()
+        assert np.array_equal(graphed.s1.cpu().numpy(),
+                              eager.s1.cpu().numpy())
+    p_e.destroy()
+    p_g.destroy()
+
+
+def test_autotune_choice_keeps_the_dose():
+    import torch
+    wl = _imrt()
+    ref = _engine(wl, 200_000)
+    p_r = ref.make_plan()
+    p_r.run(0, 2, use_graph=False)
+    torch.cuda.synchronize()
+    want = ref.s1.cpu().numpy()
+    eng = _engine(wl, 200_000)
+    plan = eng.make_plan()
+    r = plan.autotune(trials=1)
+    _say("tuned", r.launch.blocks_per_cu, r.launch.rebucket, r.n_ebuckets,
+         r.ms_per_batch, r.configs_tried, r.bucket_peak,
+         r.el_capacity_suggested)
+    assert r.configs_tried >= 20 and r.ms_per_batch > 0
+    assert r.el_capacity_suggested >= r.n_ebuckets * r.bucket_peak
+    assert not eng.acc_t.any().item()
+    assert not eng.s1.any().item()
+    plan.run(0, 2, use_graph=False)
+    torch.cuda.synchronize()
+    assert np.array_equal(eng.s1.cpu().numpy(), want)
+    q, L = plan.layout()
+    assert q.n_ebuckets == r.n_ebuckets and L.rebucket == r.launch.rebucket
+    plan.destroy()
+    p_r.destroy()

@@ -1,0 +1,106 @@
+"""The denoiser's own kernels against its float64 reference: forward,
+gradients, Adam, and the gain of a trained network over the noisy dose."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import unet as U
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _bf16_round(a):
+    import torch
+    t = torch.as_tensor(np.asarray(a, np.float32))
+    return t.to(torch.bfloat16).to(torch.float64).numpy()
+
+
+def _setup(n=2, size=16, seed=5):
+    import torch
+    import paper_1302_1861_amd as P
+    rng = np.random.default_rng(seed)
+    P_ = {}
+    for name, (ci, co) in U.layer_shapes().items():
+        P_[name] = (rng.normal(0, np.sqrt(2.0 / (27 * ci)), (co, 27, ci)),
+                    rng.normal(0, 0.05, co))
+    P_["head"] = (rng.normal(0, 0.3, 16), 0.01)
+    blob = U.pack(P_).astype(np.float32)
+    net = P.Denoiser()
+    net.set_params(blob)
+    dose = (rng.random((n, size, size, size)) + 0.1).astype(np.float32)
+    rho = rng.uniform(0.2, 1.9, (n, size, size, size)).astype(np.float32)
+    tgt = (dose * 1.1 + 0.05 * rng.random(dose.shape)).astype(np.float32)
+    # the reference uses the bf16-rounded weights the kernels compute with
+    ref = U.unpack(_bf16_round(blob).astype(np.float64))
+    ref["head"] = U.unpack(blob.astype(np.float64))["head"]
+    for k in P_:
+        if k != "head":
+            ref[k] = (ref[k][0], U.unpack(blob.astype(np.float64))[k][1])
+    T = lambda a: torch.from_numpy(a).cuda()
+    return net, ref, dose, rho, tgt, T
+
+
+def test_forward_matches_reference():
+    import torch
+    net, ref, dose, rho, tgt, T = _setup()
+    out = net.forward(T(dose), T(rho))
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().astype(np.float64)
+    want = U.forward(ref, dose.astype(np.float64), rho.astype(np.float64))
+    # The kernels keep activations in bf16 (relative rounding <= 2^-9 per
+    # value, rms ~1.1e-3); over 14 convolution layers in a chain the rms
+    # error of the network's correction grows to ~sqrt(14) x 1.1e-3 ~ 4e-3.
+    # The bound below leaves a factor of 5 on that.
+    corr_g, corr_w = got - dose, want - dose
+    rel = np.linalg.norm(corr_g - corr_w) / np.linalg.norm(corr_w)
+    _say("forward: correction rel l2", rel)
+    assert rel < 2e-2
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-2
+
+
+def test_gradients_match_reference():
+    import torch
+    net, ref, dose, rho, tgt, T = _setup()
+    net.loss.zero_()
+    net.grads.zero_()
+    net.backward(T(dose), T(rho), T(tgt))
+    torch.cuda.synchronize()
+    g = net.grads.cpu().numpy().astype(np.float64)
+    L, G = U.loss_and_grads(ref, dose.astype(np.float64),
+                            rho.astype(np.float64), tgt.astype(np.float64))
+    want = U.grads_to_blob(G)
+    _say("loss", float(net.loss.item()), L)
+    assert float(net.loss.item()) == pytest.approx(L, rel=2e-2)
+    cos = g @ want / (np.linalg.norm(g) * np.linalg.norm(want))
+    _say("gradient cosine", cos)
+    assert cos >= 0.999
+    # per layer
+    off = 0
+    for name, (ci, co) in U.layer_shapes().items():
+        kp = (27 * ci + 31) // 32 * 32
+        a, b = off, off + co * kp + co
+        off = b
+        c = g[a:b] @ want[a:b] / (np.linalg.norm(g[a:b]) *
+                                  np.linalg.norm(want[a:b]) + 1e-300)
+        _say(name, "cosine", c)
+        assert c >= 0.99, name
+
+
+def test_adam_reduces_loss():
+    import torch
+    net, ref, dose, rho, tgt, T = _setup(n=1, size=16)
+    d, r, t = T(dose), T(rho), T(tgt)
+    losses = []
+    for it in range(30):
+        net.loss.zero_()
+        net.backward(d, r, t)
+        net.adam(lr=2e-3)
+        losses.append(float(net.loss.item()))
+    _say("losses", losses[:3], losses[-3:])
+    assert losses[-1] < 0.5 * losses[0]
