@@ -226,7 +226,9 @@ typedef struct psl_phantom {
     double x0, y0, z0;          /* corner of voxel (0,0,0), world frame, cm   */
     const float *density;       /* device [nz][ny][nx], g/cm^3, x fastest     */
     float rho_max;              /* >= max density (Woodcock majorant)         */
-    int32_t pad2;
+    float rho_min;              /* <= min density, or 0 if unknown: a        */
+                                /* tentative collision with xi*rho_max <=    */
+                                /* rho_min is real without a density read    */
 } psl_phantom;
 
 #define PSL_FLAG_FIRST_COLLISION 1   /* photons stop after one interaction, */
@@ -327,6 +329,30 @@ psl_status dose_tally(psl_dose_acc *acc, double *d_s1, double *d_s2,
                       int32_t op, int32_t n_batches, const psl_phantom *ph,
                       double norm, float *d_dose, float *d_sigma,
                       void *stream);
+
+/*
+ * dose_gamma - 3D global gamma index of an evaluated dose against a
+ * reference (the dose-difference / distance-to-agreement test behind the
+ * pass rates of Table 1; Low et al. 1998).  For every reference voxel with
+ * ref >= ref_min:
+ *   gamma^2 = min over offsets o of |o|^2 / dta^2
+ *                                   + (E(r + o) - ref(r))^2 / dd^2,
+ * the offsets being the points (-dta + i step, -dta + j step, -dta + k step),
+ * i, j, k = 0 .. ceil((2 dta + 1e-12) / step) - 1, with |o|^2 <= dta^2 +
+ * 1e-12, and E the trilinear interpolation of d_eval with indices clamped
+ * to the volume.  Arithmetic in double.  dd is the absolute dose criterion
+ * (global gamma: a fraction of the reference maximum).
+ * d_ref, d_eval: device float [nz][ny][nx]; dx, dy, dz and dta in one
+ * length unit.  d_gamma2 (optional): device float [voxels], gamma^2 of the
+ * evaluated voxels and -1 elsewhere.  d_counts: device uint64 [2], to which
+ * the call adds the number of evaluated voxels and of those with
+ * gamma^2 <= 1 (the caller clears it).  PSL_EINVAL for non-positive
+ * criteria or more than 64 offsets per axis.
+ */
+psl_status dose_gamma(const float *d_ref, const float *d_eval, int32_t nx,
+                      int32_t ny, int32_t nz, double dx, double dy, double dz,
+                      double dd, double dta, double step, double ref_min,
+                      float *d_gamma2, uint64_t *d_counts, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Kernel timing for benchmarks.                                             */

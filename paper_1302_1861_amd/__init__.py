@@ -39,7 +39,8 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_bench_atomics", "psl_plan_workspace_bytes", "psl_plan_create",
            "psl_plan_run", "psl_autotune", "psl_plan_get", "psl_plan_destroy",
            "unet_param_count", "unet_workspace_bytes", "unet_init",
-           "unet_forward", "unet_backward", "unet_adam_step", "dose_denoise"]
+           "unet_forward", "unet_backward", "unet_adam_step", "dose_denoise",
+           "dose_gamma"]
 
 
 class PslError(RuntimeError):
@@ -111,7 +112,7 @@ class psl_phantom(C.Structure):
                 ("pad", C.c_int32), ("dx", C.c_double), ("dy", C.c_double),
                 ("dz", C.c_double), ("x0", C.c_double), ("y0", C.c_double),
                 ("z0", C.c_double), ("density", C.c_void_p),
-                ("rho_max", C.c_float), ("pad2", C.c_int32)]
+                ("rho_max", C.c_float), ("rho_min", C.c_float)]
 
 
 class psl_physics(C.Structure):
@@ -228,6 +229,10 @@ def lib():
         L.unet_adam_step.restype = i32
         L.dose_denoise.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, sz, vp]
         L.dose_denoise.restype = i32
+        d = C.c_double
+        L.dose_gamma.argtypes = [vp, vp, i32, i32, i32, d, d, d, d, d, d, d,
+                                 vp, vp, vp]
+        L.dose_gamma.restype = i32
         _lib = L
     return _lib
 
@@ -302,7 +307,9 @@ def make_fields(fields, fluence_tensors) -> "C.Array":
     return arr
 
 
-def make_phantom(density_t, voxel, origin, rho_max=None) -> psl_phantom:
+def make_phantom(density_t, voxel, origin, rho_max=None,
+                 rho_min=None) -> psl_phantom:
+    """rho_max / rho_min default to the exact extremes of the density."""
     p = psl_phantom()
     p.nz, p.ny, p.nx = density_t.shape
     p.dx, p.dy, p.dz = (float(v) for v in voxel)
@@ -310,6 +317,8 @@ def make_phantom(density_t, voxel, origin, rho_max=None) -> psl_phantom:
     p.density = density_t.data_ptr()
     p.rho_max = float(rho_max if rho_max is not None
                       else density_t.max().item())
+    p.rho_min = float(rho_min if rho_min is not None
+                      else max(density_t.min().item(), 0.0))
     return p
 
 
@@ -402,6 +411,29 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+def dose_gamma(ref, ev, voxel, dose_crit=0.02, dta=0.2, threshold=0.1,
+               step=None, gamma2=None):
+    """Global 3D gamma of device float tensors ref, ev [nz, ny, nx]: the dose
+    criterion is dose_crit * max(ref), voxels with ref >= threshold *
+    max(ref) are evaluated.  Returns (pass fraction, evaluated count)."""
+    import torch
+    assert ref.dtype == torch.float32 and ev.dtype == torch.float32
+    assert ref.shape == ev.shape and ref.dim() == 3
+    ref = ref.contiguous()
+    ev = ev.contiguous()
+    nz, ny, nx = ref.shape
+    vz, vy, vx = (voxel,) * 3 if np.isscalar(voxel) else voxel
+    mx = float(ref.max().item())
+    counts = torch.zeros(2, dtype=torch.int64, device=ref.device)
+    _check(lib().dose_gamma(_ptr(ref), _ptr(ev), nx, ny, nz, vx, vy, vz,
+                            dose_crit * mx, dta, step or dta / 5.0,
+                            threshold * mx,
+                            _ptr(gamma2) if gamma2 is not None else None,
+                            _ptr(counts), _stream()))
+    n_eval, n_pass = (int(v) for v in counts.cpu())
+    return (n_pass / n_eval if n_eval else 1.0), n_eval
 
 
 class Denoiser:

@@ -139,12 +139,13 @@ __device__ __forceinline__ float u01(uint32_t x) {
     return ((float)(x >> 8) + 0.5f) * (1.0f / 16777216.0f);
 }
 
-// A stream of uniforms for one particle: counter (uid_lo, uid_hi, c2,
-// tag | n) for n = 0, 1, 2, ...
+// The random blocks of one particle: block n is Philox of the counter
+// (uid_lo, uid_hi, c2, tag | n), n = n0, n0 + 1, ...  Each sampling step
+// (a free flight, one rejection trial, one deflection) takes a whole block
+// at a fixed point of the code, so the lanes of a wave run the generator
+// together instead of whenever one lane's buffer runs dry.
 struct Rng {
     uint32_t k0, k1, uid_lo, uid_hi, c2, tag, n;
-    float b0, b1, b2, b3;   // scalars, not an array: no private memory
-    int left;
     __device__ void init(uint64_t seed, uint64_t uid, uint32_t c2_,
                          uint32_t tag_, uint32_t n0) {
         k0 = (uint32_t)seed;
@@ -154,22 +155,12 @@ struct Rng {
         c2 = c2_;
         tag = tag_;
         n = n0;
-        left = 0;
     }
-    __device__ void refill() {
-        u32x4 r = philox4x32_10(u32x4{uid_lo, uid_hi, c2, tag | n}, k0, k1);
+    __device__ u32x4 draw() {
+        const u32x4 r =
+            philox4x32_10(u32x4{uid_lo, uid_hi, c2, tag | n}, k0, k1);
         ++n;
-        b0 = u01(r.x);
-        b1 = u01(r.y);
-        b2 = u01(r.z);
-        b3 = u01(r.w);
-        left = 4;
-    }
-    __device__ float next() {
-        if (left == 0) refill();
-        float v = left == 4 ? b0 : left == 3 ? b1 : left == 2 ? b2 : b3;
-        --left;
-        return v;
+        return r;
     }
 };
 

@@ -79,7 +79,7 @@ double inv_s_integral(double a, double b, double n_e, double I) {
 struct PhDev {
     int nx, ny, nz;
     float x0, y0, z0, dx, dy, dz, ix_, iy_, iz_;  // inverse voxel sizes
-    float rho_max;
+    float rho_max, rho_min;
     const float *rho;
 };
 
@@ -302,7 +302,8 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
         }
         if (alive) {
             // one free flight against the majorant
-            const float s = -__logf(rng.next()) / (mu1 * P.rho_max);
+            const u32x4 rf = rng.draw();
+            const float s = -__logf(u01(rf.x)) / (mu1 * P.rho_max);
             x += s * u; y += s * v; z += s * w;
             ++c_fl;
             int ix, iy, iz;
@@ -315,7 +316,10 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
                     ++c_run;
                     tally<MODE>(acc, vox, E, wt, scale, c_dep);
                     alive = false;
-                } else if (rng.next() * P.rho_max <= P.rho[vox]) {
+                } else if (const float xi = u01(rf.y) * P.rho_max;
+                           xi <= P.rho_min || xi <= P.rho[vox]) {
+                    // (rho_min <= every density: the first test implies
+                    // the second and spares the gather)
                     // Compton: Butcher-Messel sampling of eps = E'/E
                     const float k = E / kME;
                     const float e0 = 1.0f / (1.0f + 2.0f * k);
@@ -323,9 +327,10 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
                     const float a1 = -__logf(e0), a2 = 0.5f * (1.0f - e0sq);
                     float eps, onecost, sint2, phi_u;
                     for (int tries = 0;; ++tries) {
-                        const float r1 = rng.next(), r2 = rng.next(),
-                                    r3 = rng.next();
-                        phi_u = rng.next();
+                        const u32x4 q = rng.draw();
+                        const float r1 = u01(q.x), r2 = u01(q.y),
+                                    r3 = u01(q.z);
+                        phi_u = u01(q.w);
                         float epssq;
                         if (r1 * (a1 + a2) < a1) {
                             eps = __expf(-a1 * r2);
@@ -569,15 +574,24 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 float th0 = 13.6f / pbc * sqrtf(qq) *
                             (1.0f + 0.038f * __logf(qq));
                 th0 = fmaxf(th0, 0.0f);
-                float th;
-                int tries = 0;
-                do {
-                    th = th0 * sqrtf(-2.0f * __logf(rng.next()));
-                } while (th > kPI && ++tries < 64);
-                if (th > kPI) th = kPI * rng.next();
+                // candidates x, z, w of the first block (y is the
+                // azimuth), then four per block, until one is <= pi
+                u32x4 q = rng.draw();
+                const float phi_u = u01(q.y);
+                float th = th0 * sqrtf(-2.0f * __logf(u01(q.x)));
+                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.z)));
+                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.w)));
+                for (int t = 0; t < 15 && th > kPI; ++t) {
+                    q = rng.draw();
+                    th = th0 * sqrtf(-2.0f * __logf(u01(q.x)));
+                    if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.y)));
+                    if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.z)));
+                    if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.w)));
+                }
+                if (th > kPI) th = kPI * u01(rng.draw().x);
                 float sth, cth, sp, cp;
                 __sincosf(th, &sth, &cth);
-                __sincosf(2.0f * kPI * rng.next(), &sp, &cp);
+                __sincosf(2.0f * kPI * phi_u, &sp, &cp);
                 rotate(u, v, w, cth, sth, cp, sp);
             }
         }
@@ -754,6 +768,9 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     PSL_REQUIRE(ph->dx > 0 && ph->dy > 0 && ph->dz > 0, "bad voxel size");
     PSL_REQUIRE(ph->rho_max > 0, "rho_max must be positive (and >= every "
                                  "voxel density)");
+    PSL_REQUIRE(ph->rho_min >= 0 && ph->rho_min <= ph->rho_max,
+                "rho_min must lie in [0, rho_max] (and be <= every voxel "
+                "density)");
     PSL_REQUIRE(acc->data, "NULL dose accumulator");
     PSL_REQUIRE(acc->mode == PSL_ACC_F64 ||
                     (acc->mode == PSL_ACC_FIXED64 && acc->frac_bits >= 16 &&
@@ -788,7 +805,7 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     PhDev P{ph->nx, ph->ny, ph->nz, (float)ph->x0, (float)ph->y0,
             (float)ph->z0, (float)ph->dx, (float)ph->dy, (float)ph->dz,
             (float)(1.0 / ph->dx), (float)(1.0 / ph->dy),
-            (float)(1.0 / ph->dz), ph->rho_max, ph->density};
+            (float)(1.0 / ph->dz), ph->rho_max, ph->rho_min, ph->density};
     PhysDev Y{(float)phys->step, (float)phys->p_cut, (float)phys->t_cut,
               (float)phys->X0, phys->flags};
     uint32_t *work_ph = w.words;

@@ -102,7 +102,8 @@ class Engine:
         self.density = torch.from_numpy(
             np.ascontiguousarray(ph.density, np.float32)).to(device)
         self.phantom = make_phantom(self.density, ph.voxel, ph.origin,
-                                    float(ph.density.max()))
+                                    float(ph.density.max()),
+                                    max(float(ph.density.min()), 0.0))
         e_max = float(max(6.0, float(ps.E.max()) if ps.n else 6.0))
         self.phys = make_physics(e_max=e_max, flags=phys_flags)
         self.tables = torch.zeros(PSL_TABLE_BYTES, dtype=torch.uint8,
@@ -165,6 +166,43 @@ class Engine:
             C.byref(self.queue)), device)
         self.n_kept = None
         self.folded = 0
+
+    # ------------------------------------------------- swapping inputs --
+    def set_phantom(self, ph):
+        """Replace the phantom by one with the same voxel count (new
+        densities, voxel size, origin); the tallies are cleared."""
+        nz, ny, nx = ph.density.shape
+        if nx * ny * nz != self.nvox:
+            raise ValueError("phantom has %d voxels, engine holds %d" %
+                             (nx * ny * nz, self.nvox))
+        d = self.torch.from_numpy(np.ascontiguousarray(ph.density,
+                                                       np.float32))
+        self.density = d.to(self.device)
+        self.phantom = make_phantom(self.density, ph.voxel, ph.origin,
+                                    float(ph.density.max()),
+                                    max(float(ph.density.min()), 0.0))
+        lo = np.array(ph.origin, np.float64)
+        hi = lo + np.array([nx, ny, nz], np.float64) * np.array(ph.voxel)
+        for a in range(3):
+            self.cfg.box_lo[a] = lo[a]
+            self.cfg.box_hi[a] = hi[a]
+        self.reset_tally()
+
+    def set_fields(self, fields):
+        """Replace the fields (same number); the tallies are cleared."""
+        if len(fields) != len(self.wl.fields):
+            raise ValueError("field count must stay %d" % len(self.wl.fields))
+        self.fluence = [None if f.fluence is None else
+                        self.torch.from_numpy(np.ascontiguousarray(
+                            f.fluence, np.float32)).to(self.device)
+                        for f in fields]
+        self.fields = make_fields(fields, self.fluence)
+        self.reset_tally()
+
+    def set_seed(self, seed):
+        """New random streams (start offsets and transport)."""
+        self.seed = int(seed)
+        self.cfg.seed = self.seed
 
     # -------------------------------------------------------------------
     def kept(self) -> int:

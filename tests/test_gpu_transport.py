@@ -188,6 +188,28 @@ def test_fixed_point_dose_independent_of_launch_shape():
         assert np.array_equal(o, out[0])
 
 
+def test_density_minorant_leaves_the_dose_unchanged():
+    """A tentative photon collision with xi*rho_max <= rho_min is real
+    whatever the voxel density: skipping the gather must give bit-identical
+    fixed-point dose (heterogeneous phantom, so both paths are taken)."""
+    import torch
+    wl = S.workload_heterogeneous(n_particles=500_000, shape=(96, 96, 64),
+                                  voxel=0.4)
+    out = []
+    for rho_min in (None, 0.0):
+        eng = _engine(wl, 400_000)
+        if rho_min is not None:
+            eng.phantom.rho_min = rho_min
+        assert eng.phantom.rho_min == (0.0 if rho_min is not None else
+                                       np.float32(wl.phantom.density.min()))
+        eng.sample(2)
+        eng.transport(2)
+        torch.cuda.synchronize()
+        out.append(eng.acc_t.cpu().numpy().copy())
+        _say("rho_min", eng.phantom.rho_min, "dose sum", int(out[-1].sum()))
+    assert out[0].any() and np.array_equal(out[0], out[1])
+
+
 # ------------------------------------------------ statistical parity -----
 def _parity(wl, hist, batches, threads=0, check_gamma=False):
     import torch
