@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical_10x10.json")
 
 
@@ -70,6 +71,76 @@ def _algorithmic_bytes(group, st, nvox):
     if group == "fold":
         return 48 * nvox
     return None
+
+
+def unet_forward_flops(shape, base=16, in_c=16):
+    """Multiply-add flops of the denoiser's 3x3x3 convolutions for one
+    forward pass over a volume of `shape` (4 levels, channels base * 2^l,
+    two convolutions per level and side, skip concatenation)."""
+    c = [base, 2 * base, 4 * base, 8 * base]
+    layers = [(0, in_c, c[0]), (0, c[0], c[0]), (1, c[0], c[1]),
+              (1, c[1], c[1]), (2, c[1], c[2]), (2, c[2], c[2]),
+              (3, c[2], c[3]), (3, c[3], c[3]), (2, c[3] + c[2], c[2]),
+              (2, c[2], c[2]), (1, c[2] + c[1], c[1]), (1, c[1], c[1]),
+              (0, c[1] + c[0], c[0]), (0, c[0], c[0])]
+    nz, ny, nx = shape
+    return sum(2 * 27 * ci * co * (nz >> l) * (ny >> l) * (nx >> l)
+               for l, ci, co in layers)
+
+
+def bench_imrt(P, S, torch, hpb, n_batches):
+    """The batched IMRT plan: 7 beams x 20 segments, MU-proportional
+    histories, autotuned, replayed from a hipGraph."""
+    wl = S.workload_imrt()
+    eng = P.Engine(wl, histories_per_batch=hpb)   # isocentre at SAD
+    plan = eng.make_plan()
+    r = plan.autotune(trials=1)
+    plan.run(0, 2, use_graph=True)
+    torch.cuda.synchronize()
+    eng.reset_tally()
+    t0 = time.perf_counter()
+    plan.run(0, n_batches, use_graph=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = eng.stats_dict()
+    plan.destroy()
+    return {"workload": "IMRT-like plan: 7 coplanar beams x 20 segments, "
+                        "MU-proportional, 128^3 water at 2.5 mm, "
+                        "%d batches of %d histories" % (n_batches, hpb),
+            "histories": n_batches * hpb, "seconds": dt,
+            "histories_per_s": n_batches * hpb / dt,
+            "ms_per_batch": 1e3 * dt / n_batches, "graph": True,
+            "tuned": {"blocks_per_cu": r.launch.blocks_per_cu,
+                      "rebucket": r.launch.rebucket,
+                      "n_ebuckets": r.n_ebuckets,
+                      "configs_tried": r.configs_tried,
+                      "tune_ms_per_batch": r.ms_per_batch},
+            "lost": st["lost"]}
+
+
+def bench_denoiser(P, torch, dose, density, shape, reps=5):
+    """Forward pass of the (untrained: timing does not depend on weights)
+    denoiser at the benchmark volume, timed with events on the current
+    stream, against the dense bf16 MFMA peak."""
+    net = P.Denoiser(seed=1)
+    d = dose.view(shape).contiguous()
+    r = density.view(shape).contiguous()
+    net.denoise(d, r)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), \
+        torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        net.denoise(d, r)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    fl = unet_forward_flops(shape)
+    tf = fl / (ms * 1e-3) / 1e12
+    return {"volume": list(shape), "forward_ms": ms,
+            "gflop_per_forward": fl / 1e9, "achieved": tf,
+            "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / MFMA_BF16_PEAK_TFLOPS}
 
 
 def cpu_baseline(wl, hist_target_s, threads):
@@ -120,6 +191,9 @@ def main():
     ap.add_argument("--histories-per-step", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the IMRT-plan and denoiser measurements")
+    ap.add_argument("--imrt-batches", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="device-to-device copy of this size before the "
                          "timed region (counter calibration)")
@@ -233,6 +307,13 @@ def main():
         "time_to_1pct_s": t1,
         "mean_rel_sigma_50pct": sbar,
     }
+    if not args.no_extras:
+        nz, ny, nx = wl.phantom.density.shape
+        out["denoiser"] = bench_denoiser(P, torch, eng.dose, eng.density,
+                                         (nz, ny, nx))
+        del eng
+        torch.cuda.empty_cache()
+        out["imrt_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches)
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or \
             min(16, os.cpu_count() or 1)

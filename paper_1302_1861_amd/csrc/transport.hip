@@ -255,6 +255,10 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
     double e_esc = 0.0, e_killed = 0.0;
     int part_i = wave % kParts, tried = 0;
     bool more = true;
+    // photons claimed by this wave but not yet given to a lane: the run
+    // [pend_b, pend_b + pend_n) (wave-uniform)
+    int64_t pend_b = 0;
+    int pend_n = 0;
     SecCursor cur;
     cur.part = wave % kParts;
     bool alive = false;
@@ -264,16 +268,33 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
     Rng rng;
     rng.init(seed, 0, 0u, 0u, 0u);
     for (;;) {
-        // refill the lanes whose photon is done
+        // refill the lanes whose photon is done: first from the pending
+        // run, then from a fresh claim of 64 (one atomic per several
+        // iterations instead of one per iteration)
         const uint64_t need = __ballot(!alive);
-        if (need && more) {
-            int64_t base = 0;
-            int got = 0;
-            more = claim_items(work, n, __popcll(need), part_i, tried, base,
-                               got);
+        if (need && (pend_n > 0 || more)) {
+            const int n_need = __popcll(need);
+            int64_t nb = 0;
+            int ng = 0;
+            if (pend_n < n_need && more) {
+                more = claim_items(work, n, 64, part_i, tried, nb, ng);
+                if (!more) ng = 0;
+            }
             const int rank = __popcll(need & lanemask_lt());
-            if (more && !alive && rank < got) {
-                const int64_t i = base + rank;
+            int64_t i = -1;
+            if (rank < pend_n)
+                i = pend_b + rank;
+            else if (rank - pend_n < ng)
+                i = nb + (rank - pend_n);
+            const int used = min(n_need, pend_n + ng);
+            if (used <= pend_n) {
+                pend_b += used;
+                pend_n -= used;
+            } else {
+                pend_b = nb + (used - pend_n);
+                pend_n = ng - (used - pend_n);
+            }
+            if (!alive && i >= 0) {
                 E = ph.E[i]; x = ph.x[i]; y = ph.y[i]; z = ph.z[i];
                 u = ph.u[i]; v = ph.v[i]; w = ph.w[i]; wt = ph.wt[i];
                 uid = ph.uid[i];
@@ -285,7 +306,7 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
             }
         }
         if (!__ballot(alive)) {
-            if (!more) break;
+            if (!more && pend_n == 0) break;
             continue;
         }
         bool push_e = false;
@@ -501,6 +522,10 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
         int64_t pv = vox;
         float pe = 0.0f;
         int segs = 0;
+        // density of the current voxel, reloaded only when a face crossing
+        // names the next voxel (the load then overlaps that segment's
+        // geometry)
+        float rho_v = P.rho[vox];
         bool done = false;
         while (!done) {
             // one step of Y.step cm, split at voxel faces
@@ -522,7 +547,7 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 if (sz < sb) { sb = sz; axis = 2; }
                 sb = fmaxf(sb, 0.0f);
                 const float seg = fminf(rem, sb);
-                const float dm = P.rho[vox] * seg;
+                const float dm = rho_v * seg;
                 ++c_seg;
                 if (vox != pv) {
                     tally<MODE>(acc, pv, pe, wt, scale, c_dep);
@@ -563,6 +588,7 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                         break;
                     }
                     vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
+                    rho_v = P.rho[vox];
                 }
             }
             if (!done && !(Y.flags & PSL_FLAG_NO_MSC) && tm > 0.0f) {

@@ -51,74 +51,88 @@ constexpr int kMaxCout = 128;
 
 // ------------------------------------------------------------ conv 3x3x3 --
 // y[v][co] = epilogue(sum_{o,ci} x[v + o][ci] W[co][o*Cin + ci]),
-// W rows padded to Kp = roundup(27 Cin, 32) with zeros.
-template <int NB>   // output channel blocks of 16
+// W rows padded to Kp = roundup(27 Cin, 32) with zeros.  A wave computes MT
+// tiles of 16 consecutive voxels x 16 NB output channels, so every weight
+// fragment it loads feeds MT matrix instructions and every input fragment
+// NB of them.
+template <int NB, int MT>   // output channel blocks of 16, voxel tiles of 16
 __global__ void __launch_bounds__(256)
 k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
         const bf16_t *__restrict__ W, int Kp, const float *__restrict__ bias,
         int relu, const bf16_t *__restrict__ mask, int mask_c,
         bf16_t *__restrict__ y, int Cout) {
     const int lane = __lane_id();
-    const int64_t tile = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    const int64_t tile0 =
+        ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * (16 * MT);
     const int64_t nvox = V.voxels();
-    if (tile >= nvox) return;
-    // the A row of this lane: voxel tile + lane % 16
-    const int64_t v = tile + (lane & 15);
-    const bool vok = v < nvox;
-    int vw = 0, vh = 0, vd = 0;
-    int64_t vn = 0;
-    if (vok) {
-        int64_t t = v;
-        vw = (int)(t % V.w); t /= V.w;
-        vh = (int)(t % V.h); t /= V.h;
-        vd = (int)(t % V.d); vn = t / V.d;
-    }
-    f32x4 acc[NB];
+    if (tile0 >= nvox) return;
+    // the A row of this lane in tile t: voxel tile0 + 16 t + lane % 16
+    int vw[MT], vh[MT], vd[MT];
+    int64_t vn[MT];
+    bool vok[MT];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = f32x4{0, 0, 0, 0};
+    for (int t = 0; t < MT; ++t) {
+        const int64_t v = tile0 + 16 * t + (lane & 15);
+        vok[t] = v < nvox;
+        int64_t q = vok[t] ? v : 0;
+        vw[t] = (int)(q % V.w); q /= V.w;
+        vh[t] = (int)(q % V.h); q /= V.h;
+        vd[t] = (int)(q % V.d); vn[t] = q / V.d;
+    }
+    f32x4 acc[MT][NB];
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) acc[t][b] = f32x4{0, 0, 0, 0};
     const int kq = 8 * (lane >> 4);
     for (int k0 = 0; k0 < Kp; k0 += 32) {
         const int k = k0 + kq;
-        bf16x8 a;
         const int o = k / Cin, ci = k - o * Cin;
-        bool ok = vok && o < 27;
-        int zz = 0, yy = 0, xx = 0;
-        if (ok) {
-            zz = vd + o / 9 - 1;
-            yy = vh + (o / 3) % 3 - 1;
-            xx = vw + o % 3 - 1;
-            ok = (unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
-                 (unsigned)xx < (unsigned)V.w;
-        }
-        if (ok) {
-            const int64_t nb = ((vn * V.d + zz) * V.h + yy) * V.w + xx;
-            a = *reinterpret_cast<const bf16x8 *>(x + nb * Cin + ci);
-        } else {
-            a = bf16x8{};
+        const int dz = o / 9 - 1, dy = (o / 3) % 3 - 1, dx = o % 3 - 1;
+        bf16x8 a[MT];
+#pragma unroll
+        for (int t = 0; t < MT; ++t) {
+            const int zz = vd[t] + dz, yy = vh[t] + dy, xx = vw[t] + dx;
+            const bool ok = vok[t] && o < 27 &&
+                            (unsigned)zz < (unsigned)V.d &&
+                            (unsigned)yy < (unsigned)V.h &&
+                            (unsigned)xx < (unsigned)V.w;
+            if (ok) {
+                const int64_t nb = ((vn[t] * V.d + zz) * V.h + yy) * V.w + xx;
+                a[t] = *reinterpret_cast<const bf16x8 *>(x + nb * Cin + ci);
+            } else {
+                a[t] = bf16x8{};
+            }
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int co = b * 16 + (lane & 15);
             const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
                 W + (int64_t)co * Kp + k);
-            acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wv, acc[b], 0,
-                                                            0, 0);
+#pragma unroll
+            for (int t = 0; t < MT; ++t)
+                acc[t][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a[t], wv, acc[t][b], 0, 0, 0);
         }
     }
-    // acc[b][r] is (voxel tile + 4 (lane/16) + r, channel 16 b + lane % 16)
+    // acc[t][b][r] is (voxel tile0 + 16 t + 4 (lane/16) + r,
+    //                  channel 16 b + lane % 16)
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-        const int co = b * 16 + (lane & 15);
+    for (int t = 0; t < MT; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t vv = tile + 4 * (lane >> 4) + r;
-            if (vv >= nvox || co >= Cout) continue;
-            float val = acc[b][r] + (bias ? bias[co] : 0.0f);
-            if (relu) val = fmaxf(val, 0.0f);
-            if (mask && !(bf2f(mask[vv * mask_c + co]) > 0.0f)) val = 0.0f;
-            y[vv * Cout + co] = f2bf(val);
+        for (int b = 0; b < NB; ++b) {
+            const int co = b * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t vv = tile0 + 16 * t + 4 * (lane >> 4) + r;
+                if (vv >= nvox || co >= Cout) continue;
+                float val = acc[t][b][r] + (bias ? bias[co] : 0.0f);
+                if (relu) val = fmaxf(val, 0.0f);
+                if (mask && !(bf2f(mask[vv * mask_c + co]) > 0.0f))
+                    val = 0.0f;
+                y[vv * Cout + co] = f2bf(val);
+            }
         }
-    }
 }
 
 // W'[ci][o'][co] = W[co][26 - o'][ci]: the weights of the transposed
@@ -612,26 +626,28 @@ Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
 
 unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-template <int NB>
+template <int NB, int MT>
 void launch_conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                  const float *bias, int relu, const bf16_t *mask, int mask_c,
                  bf16_t *y, int cout, hipStream_t st) {
-    hipLaunchKernelGGL(k_conv3<NB>, dim3(nblk(V.voxels(), 64)), dim3(256), 0,
-                       st, x, V, cin, W, kp, bias, relu, mask, mask_c, y,
-                       cout);
+    hipLaunchKernelGGL((k_conv3<NB, MT>), dim3(nblk(V.voxels(), 64 * MT)),
+                       dim3(256), 0, st, x, V, cin, W, kp, bias, relu, mask,
+                       mask_c, y, cout);
 }
 
+// Voxel tiles per wave: enough reuse of each weight fragment while the
+// accumulators (4 MT NB registers) stay at 64 or fewer.
 psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                 const float *bias, int relu, const bf16_t *mask, bf16_t *y,
                 int cout, hipStream_t st) {
     switch (cout / 16) {
-    case 1: launch_conv<1>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 2: launch_conv<2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 3: launch_conv<3>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 4: launch_conv<4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 6: launch_conv<6>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 8: launch_conv<8>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 12: launch_conv<12>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 1: launch_conv<1, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 2: launch_conv<2, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 3: launch_conv<3, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 4: launch_conv<4, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 6: launch_conv<6, 2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 8: launch_conv<8, 2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 12: launch_conv<12, 1>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
     default:
         set_error("unsupported channel count %d", cout);
         return PSL_EINVAL;

@@ -45,8 +45,13 @@ class PairMaker:
     and the draws of phantoms and fields."""
 
     def __init__(self, shape=(128, 128, 128), voxel=0.25, n_particles=None,
-                 device="cuda"):
+                 device="cuda", unsorted=False):
+        """unsorted=True: the plain-method analogue -- one PSL per particle
+        type holding the phase space in file order (one energy bin, one
+        position bin), no ROI cull, no electron re-bucketing."""
+        import dataclasses
         import psl_synth as S
+        from . import make_launch
         from .engine import Engine
         self.S = S
         self.shape = tuple(shape)
@@ -54,6 +59,14 @@ class PairMaker:
         kw = {} if n_particles is None else {"n_particles": n_particles}
         self.wl = S.workload_heterogeneous(shape=self.shape, voxel=self.voxel,
                                            **kw)
+        self.launch = None
+        if unsorted:
+            g = self.wl.grid
+            one = S.Grid(S.linear_edges(0.0, float(self.wl.phsp.E.max()), 1),
+                         g.x_edges[[0, -1]].copy(), g.y_edges[[0, -1]].copy(),
+                         g.z_plane)
+            self.wl = dataclasses.replace(self.wl, grid=one, cull=False)
+            self.launch = make_launch(rebucket=0)
         self.Engine = Engine
         self.device = device
         self.engines: Dict[int, object] = {}
@@ -61,7 +74,8 @@ class PairMaker:
     def engine(self, hpb):
         if hpb not in self.engines:
             self.engines[hpb] = self.Engine(self.wl, device=self.device,
-                                            histories_per_batch=hpb)
+                                            histories_per_batch=hpb,
+                                            launch=self.launch)
         return self.engines[hpb]
 
     def phantom(self, seed):
@@ -92,7 +106,7 @@ class PairMaker:
 
 
 def make_pairs(pm: PairMaker, n_draws, n_in, n_tgt, seed0=TRAIN_SEED0,
-               tgt_batches=10):
+               tgt_batches=None):
     """Stacks of (input dose, density, target dose) on the device."""
     import torch
     nx, ny, nz = pm.shape
@@ -104,7 +118,8 @@ def make_pairs(pm: PairMaker, n_draws, n_in, n_tgt, seed0=TRAIN_SEED0,
         s = seed0 + k
         ph, f = pm.phantom(s), pm.field(s)
         X[k], _, R[k] = pm.dose(ph, f, n_in, s)
-        T[k], _, _ = pm.dose(ph, f, n_tgt, s + MC_SEED_OFFSET, tgt_batches)
+        T[k], _, _ = pm.dose(ph, f, n_tgt, s + MC_SEED_OFFSET,
+                             tgt_batches or batches_for(n_tgt))
         if (k + 1) % max(1, n_draws // 10) == 0:
             _say("pairs %d/%d" % (k + 1, n_draws))
     return X, R, T
@@ -149,7 +164,7 @@ def _rms_rel(a, ref, sel, mx):
 
 
 def evaluate(pm: PairMaker, net, n_draws, n_in, n_ref, seed0=EVAL_SEED0,
-             ref_batches=10):
+             ref_batches=None):
     """Held-out draws: raw and denoised n_in doses against an independent
     n_ref reference.  Returns per-draw records and their means."""
     import torch
@@ -168,7 +183,7 @@ def evaluate(pm: PairMaker, net, n_draws, n_in, n_ref, seed0=EVAL_SEED0,
         torch.cuda.synchronize()
         t_den = time.perf_counter() - t0
         ref, sref, _ = pm.dose(ph, f, n_ref, s + 2 * MC_SEED_OFFSET,
-                               ref_batches)
+                               ref_batches or batches_for(n_ref))
         mx = float(ref.max().item())
         sel = ref >= 0.1 * mx
         sel50 = ref >= 0.5 * mx
@@ -200,6 +215,64 @@ def evaluate(pm: PairMaker, net, n_draws, n_in, n_ref, seed0=EVAL_SEED0,
     return recs, mean
 
 
+def batches_for(n, max_hpb=10_000_000):
+    """At least 10 batches and at most max_hpb histories per batch."""
+    return max(10, -(-int(n) // max_hpb))
+
+
+def time_to_gamma(pm: PairMaker, ph, field, ref, ladder, seed, target=0.99,
+                  voxel=None):
+    """Smallest history count of `ladder` whose dose passes gamma 2%/2mm
+    against `ref` at >= target, with its GPU seconds (sampling, transport,
+    tally), or None; and the pass rate at every rung tried."""
+    import torch
+    from . import dose_gamma
+    rungs = []
+    for n in ladder:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, _, _ = pm.dose(ph, field, n, seed, batches_for(n))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g, _ = dose_gamma(ref, d, voxel or pm.voxel)
+        rungs.append({"histories": n, "seconds": dt, "gamma": g})
+        if g >= target:
+            return rungs[-1], rungs
+    return None, rungs
+
+
+def compare_time_to_gamma(pm: PairMaker, pm_plain: PairMaker, net, n_draws,
+                          n_in, n_ref, ladder, seed0=EVAL_SEED0 + 500):
+    """Time to gamma 2%/2mm >= 99% against an independent n_ref plain run:
+    plain method (file order, no cull), PSL, and PSL + denoiser."""
+    import torch
+    from . import dose_gamma
+    out = []
+    for k in range(n_draws):
+        s = seed0 + k
+        ph, f = pm.phantom(s), pm.field(s)
+        ref, _, _ = pm.dose(ph, f, n_ref, s + 3 * MC_SEED_OFFSET,
+                            batches_for(n_ref))
+        hit_psl, r_psl = time_to_gamma(pm, ph, f, ref, ladder, s)
+        hit_pl, r_pl = time_to_gamma(pm_plain, ph, f, ref, ladder, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        raw, _, rho = pm.dose(ph, f, n_in, s + 4 * MC_SEED_OFFSET)
+        den = net.denoise(raw, rho)
+        torch.cuda.synchronize()
+        t_dn = time.perf_counter() - t0
+        g_dn, _ = dose_gamma(ref, den, pm.voxel)
+        rec = {"draw": s, "psl": hit_psl, "plain_unsorted": hit_pl,
+               "psl_denoise": {"histories": n_in, "seconds": t_dn,
+                               "gamma": g_dn},
+               "ladder_psl": r_psl, "ladder_plain": r_pl}
+        out.append(rec)
+        _say(json.dumps({k2: rec[k2] for k2 in ("draw", "psl",
+                                                "plain_unsorted",
+                                                "psl_denoise")}))
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--shape", type=int, nargs=3, default=(128, 128, 128))
@@ -214,6 +287,10 @@ def main(argv=None):
     ap.add_argument("--crop", type=int, nargs=3, default=(64, 64, 64))
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--gamma-draws", type=int, default=4,
+                    help="held-out draws for the time-to-gamma comparison")
+    ap.add_argument("--ladder", type=float, nargs="+",
+                    default=(1e7, 2e7, 5e7, 1e8, 2e8, 5e8, 1e9))
     ap.add_argument("--out", default=None, help="JSON report path")
     ap.add_argument("--save", default=None, help="fp32 weights (.npy)")
     a = ap.parse_args(argv)
@@ -233,12 +310,19 @@ def main(argv=None):
     t_train = time.perf_counter() - t0
     del X, R, T
     recs, mean = evaluate(pm, net, a.eval_draws, int(a.n_in), int(a.n_ref))
+    ttg = []
+    if a.gamma_draws:
+        pm_plain = PairMaker(tuple(a.shape), a.voxel, unsorted=True)
+        ttg = compare_time_to_gamma(pm, pm_plain, net, a.gamma_draws,
+                                    int(a.n_in), int(a.n_ref),
+                                    [int(n) for n in a.ladder])
     rep = {"shape": list(a.shape), "voxel_cm": a.voxel, "draws": a.draws,
            "n_in": a.n_in, "n_tgt": a.n_tgt, "n_ref": a.n_ref,
            "steps": a.steps, "batch": a.batch, "crop": list(a.crop),
            "pair_seconds": t_pairs, "train_seconds": t_train,
            "ms_per_train_step": 1e3 * t_train / max(1, a.steps),
            "losses": losses, "eval_mean": mean, "eval": recs,
+           "time_to_gamma": ttg,
            "total_seconds": time.perf_counter() - t_all}
     _say(json.dumps({"eval_mean": mean}))
     if a.out:
