@@ -152,15 +152,34 @@ __global__ void k_flip_weights(const bf16_t *__restrict__ W, int Cin,
 }
 
 // dW[co][o][ci] += sum over a voxel chunk of dy[v][co] x[v + o][ci].  One
-// block per (offset, voxel chunk); 32 voxels at a time are staged in LDS;
-// each wave owns 16x16 output tiles.
+// block per (offset, voxel chunk).  32 voxels at a time are staged in LDS
+// transposed (channel-major, 16-byte global loads), so that each lane reads
+// its 8 consecutive voxels of one channel -- an MFMA operand -- with one
+// 16-byte LDS read; the neighbour index of each voxel is computed once.
+// Each wave owns up to 16 of the (Cout/16) x (Cin/16) output tiles; the
+// partial sums go out with one fp32 atomic per weight per block.
 constexpr int kWgVox = 32;
+constexpr int kWgPitch = kWgVox + 8;   // LDS row pitch (elements)
+
+// The 8 bf16 values packed in q (channel c8 + j in bits 16 j of the 128)
+// written down a column of a row-pitch-kWgPitch LDS tile.  The halves are
+// split with 32-bit shifts: extracting elements of a bf16 vector type was
+// lowered incorrectly by this toolchain (every element read as element 0).
+__device__ __forceinline__ void put8_transposed(bf16_t *col, uint4 q) {
+    const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        col[(2 * m) * kWgPitch] = (bf16_t)(w[m] & 0xffffu);
+        col[(2 * m + 1) * kWgPitch] = (bf16_t)(w[m] >> 16);
+    }
+}
 __global__ void __launch_bounds__(256)
 k_conv3_wgrad(const bf16_t *__restrict__ x, Vol V, int Cin,
               const bf16_t *__restrict__ dy, int Cout, int64_t chunk,
               float *__restrict__ dW, int Kp) {
-    __shared__ bf16_t s_dy[kWgVox * kMaxCout];
-    __shared__ bf16_t s_x[kWgVox * 256];
+    __shared__ __attribute__((aligned(16))) bf16_t s_dy[kMaxCout * kWgPitch];
+    __shared__ __attribute__((aligned(16))) bf16_t s_x[2 * kMaxCout * kWgPitch];
+    __shared__ int64_t s_nb[kWgVox];
     const int o = blockIdx.y;
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int dz = o / 9 - 1, dyo = (o / 3) % 3 - 1, dx = o % 3 - 1;
@@ -169,21 +188,15 @@ k_conv3_wgrad(const bf16_t *__restrict__ x, Vol V, int Cin,
     const int64_t v1 = v0 + chunk < nvox ? v0 + chunk : nvox;
     const int mt = Cout / 16, nt = Cin / 16;
     const int n_tiles = mt * nt;
-    // up to 16 (co, ci) 16x16 tiles per wave
+    const int gy = Cout / 8, gx = Cin / 8;   // 16-byte groups per voxel
     f32x4 acc[16];
 #pragma unroll
     for (int t = 0; t < 16; ++t) acc[t] = f32x4{0, 0, 0, 0};
     for (int64_t vb = v0; vb < v1; vb += kWgVox) {
         __syncthreads();
-        for (int i = threadIdx.x; i < kWgVox * Cout; i += 256) {
-            const int vi = i / Cout, c = i % Cout;
-            const int64_t v = vb + vi;
-            s_dy[i] = v < v1 ? dy[v * Cout + c] : (bf16_t)0;
-        }
-        for (int i = threadIdx.x; i < kWgVox * Cin; i += 256) {
-            const int vi = i / Cin, c = i % Cin;
-            const int64_t v = vb + vi;
-            bf16_t val = 0;
+        if (threadIdx.x < kWgVox) {
+            const int64_t v = vb + threadIdx.x;
+            int64_t nb = -1;
             if (v < v1) {
                 int64_t t = v;
                 const int w = (int)(t % V.w); t /= V.w;
@@ -194,9 +207,28 @@ k_conv3_wgrad(const bf16_t *__restrict__ x, Vol V, int Cin,
                 if ((unsigned)zz < (unsigned)V.d &&
                     (unsigned)yy < (unsigned)V.h &&
                     (unsigned)xx < (unsigned)V.w)
-                    val = x[(((n * V.d + zz) * V.h + yy) * V.w + xx) * Cin + c];
+                    nb = ((n * V.d + zz) * V.h + yy) * V.w + xx;
             }
-            s_x[i] = val;
+            s_nb[threadIdx.x] = nb;
+        }
+        // dy rows of the 32 voxels (contiguous in memory), transposed
+        // (consecutive threads take consecutive voxels: the transposed LDS
+        // writes of a wave then fall on consecutive addresses)
+        for (int i = threadIdx.x; i < kWgVox * gy; i += 256) {
+            const int vi = i % kWgVox, c8 = (i / kWgVox) * 8;
+            const int64_t v = vb + vi;
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if (v < v1) q = *reinterpret_cast<const uint4 *>(dy + v * Cout + c8);
+            put8_transposed(s_dy + c8 * kWgPitch + vi, q);
+        }
+        __syncthreads();
+        // shifted x rows, transposed
+        for (int i = threadIdx.x; i < kWgVox * gx; i += 256) {
+            const int vi = i % kWgVox, c8 = (i / kWgVox) * 8;
+            const int64_t nb = s_nb[vi];
+            uint4 q = make_uint4(0, 0, 0, 0);
+            if (nb >= 0) q = *reinterpret_cast<const uint4 *>(x + nb * Cin + c8);
+            put8_transposed(s_x + c8 * kWgPitch + vi, q);
         }
         __syncthreads();
         // A[i = co][k = voxel], B[k = voxel][j = ci]
@@ -206,15 +238,12 @@ k_conv3_wgrad(const bf16_t *__restrict__ x, Vol V, int Cin,
             const int t = wid + 4 * slot;
             if (t >= n_tiles) break;
             const int cb = t / nt, ib = t % nt;
-            bf16x8 a, b;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int co = cb * 16 + (lane & 15);
-                const int ci = ib * 16 + (lane & 15);
-                a[j] = __builtin_bit_cast(__bf16,
-                                          s_dy[(kk + j) * Cout + co]);
-                b[j] = __builtin_bit_cast(__bf16, s_x[(kk + j) * Cin + ci]);
-            }
+            const int co = cb * 16 + (lane & 15);
+            const int ci = ib * 16 + (lane & 15);
+            const bf16x8 a =
+                *reinterpret_cast<const bf16x8 *>(&s_dy[co * kWgPitch + kk]);
+            const bf16x8 b =
+                *reinterpret_cast<const bf16x8 *>(&s_x[ci * kWgPitch + kk]);
             acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                 a, b, acc[slot], 0, 0, 0);
         }
@@ -730,7 +759,9 @@ psl_status layer_back(const Ctx &c, const Acts &a, int i, const bf16_t *x,
                       const bf16_t *dx_mask) {
     const ConvL &l = c.net.L[i];
     const int64_t nv = V.voxels();
-    int64_t chunk = std::max<int64_t>(1024, (nv / 256 + 31) / 32 * 32);
+    // about 64 chunks per offset (27 x 64 blocks): enough blocks to fill
+    // the chip, few enough that the per-block atomics stay small
+    int64_t chunk = std::max<int64_t>(256, (nv / 64 + 31) / 32 * 32);
     const unsigned nch = (unsigned)((nv + chunk - 1) / chunk);
     hipLaunchKernelGGL(k_conv3_wgrad, dim3(nch, 27), dim3(256), 0, c.st, x, V,
                        l.cin, dy, l.cout, chunk, grads + l.w_off, l.kp);

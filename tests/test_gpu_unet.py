@@ -78,18 +78,21 @@ def test_gradients_match_reference():
     _say("loss", float(net.loss.item()), L)
     assert float(net.loss.item()) == pytest.approx(L, rel=2e-2)
     cos = g @ want / (np.linalg.norm(g) * np.linalg.norm(want))
-    _say("gradient cosine", cos)
-    assert cos >= 0.999
-    # per layer
-    off = 0
+    # per layer, weights and biases apart (all reported before asserting)
+    off, bad = 0, []
     for name, (ci, co) in U.layer_shapes().items():
         kp = (27 * ci + 31) // 32 * 32
-        a, b = off, off + co * kp + co
-        off = b
-        c = g[a:b] @ want[a:b] / (np.linalg.norm(g[a:b]) *
-                                  np.linalg.norm(want[a:b]) + 1e-300)
-        _say(name, "cosine", c)
-        assert c >= 0.99, name
+        for part, n in (("W", co * kp), ("b", co)):
+            a, b = off, off + n
+            off = b
+            c = g[a:b] @ want[a:b] / (np.linalg.norm(g[a:b]) *
+                                      np.linalg.norm(want[a:b]) + 1e-300)
+            r = np.linalg.norm(g[a:b]) / (np.linalg.norm(want[a:b]) + 1e-300)
+            _say(name, part, "cosine %.5f norm ratio %.4f" % (c, r))
+            if c < 0.99:
+                bad.append(name + part)
+    _say("gradient cosine", cos)
+    assert cos >= 0.999 and not bad, bad
 
 
 def test_adam_reduces_loss():
