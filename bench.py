@@ -32,33 +32,41 @@ MFMA_BF16_PEAK_TFLOPS = 2500.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_clinical_10x10.json")
 
 
-def _source_hash():
+KERNEL_OF_GROUP = {"photons": "k_photons<1>", "electrons": "k_electrons<1>",
+                   "sample": "k_sample", "fold": "k_fold<1>"}
+# the sources each kernel is compiled from
+SOURCES_OF_KERNEL = {
+    "k_photons<1>": ("transport.hip", "common.hpp", "compact.hpp"),
+    "k_electrons<1>": ("transport.hip", "common.hpp", "compact.hpp"),
+    "k_sample": ("sample.hip", "sample.hpp", "common.hpp", "compact.hpp"),
+    "k_fold<1>": ("tally.hip", "common.hpp"),
+}
+
+
+def source_hash(kernel):
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1302_1861_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in SOURCES_OF_KERNEL[kernel]:
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "psl.h"), "rb").read())
     return h.hexdigest()[:16]
-
-
-KERNEL_OF_GROUP = {"photons": "k_photons<1>", "electrons": "k_electrons<1>",
-                   "sample": "k_sample", "fold": "k_fold<1>"}
 
 
 def _traffic(group):
     """HBM bytes per launch of the group's kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter reads
-    for a plain copy of known size), or None when the kernel sources changed
-    since the counters were taken."""
+    for a plain copy of known size), or None when that kernel's sources
+    changed since the counters were taken."""
     try:
         t = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     k = KERNEL_OF_GROUP.get(group)
-    if t.get("source_hash") != _source_hash() or k not in t["kernels"]:
+    rec = t.get("kernels", {}).get(k)
+    if rec is None or rec.get("source_hash") != source_hash(k):
         return None
-    return t["kernels"][k]["bytes_per_launch"]
+    return rec["bytes_per_launch"]
 
 
 def _algorithmic_bytes(group, st, nvox):
@@ -178,9 +186,9 @@ def cpu_baseline(wl, hist_target_s, threads):
         oracle.fold(acc, s1, s2)
 
     t0 = time.perf_counter()
-    batch(0, 20_000)
+    batch(0, 300_000)
     dt = time.perf_counter() - t0
-    rate0 = 20_000 / max(dt, 1e-6)
+    rate0 = 300_000 / max(dt, 1e-6)
     H = int(min(max(rate0 * hist_target_s, 20_000), 50_000_000))
     t0 = time.perf_counter()
     batch(1, H)
@@ -203,6 +211,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the IMRT-plan and denoiser measurements")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="only the IMRT-plan and denoiser measurements (for "
+                         "profiling them apart from the main workload)")
     ap.add_argument("--imrt-batches", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="device-to-device copy of this size before the "
@@ -223,6 +234,18 @@ def main():
     wl = S.workload_clinical(side=args.field)
     H = args.histories_per_step
     eng = P.Engine(wl, histories_per_batch=H)
+    if args.extras_only:
+        eng.step(0)
+        eng.step(1)
+        d, _ = eng.finalize()
+        nz, ny, nx = wl.phantom.density.shape
+        out = {"denoiser": bench_denoiser(P, torch, d, eng.density,
+                                          (nz, ny, nx))}
+        del eng
+        torch.cuda.empty_cache()
+        out["imrt_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches)
+        print(json.dumps(out))
+        return
     torch.cuda.synchronize()
     if args.copy_probe_mib:
         nbytes = args.copy_probe_mib << 20
@@ -255,7 +278,9 @@ def main():
     ms = 1000.0 * elapsed / args.steps
     # dominant kernel and its HBM roofline
     groups = {g: v for g, v in prof.items() if v[1] > 0}
-    dom = max(groups, key=lambda g: groups[g][0])
+    # the dominant kernel among those with algorithmic bytes defined
+    dom = max((g for g in groups if g in KERNEL_OF_GROUP),
+              key=lambda g: groups[g][0])
     avg_ms = groups[dom][0] / groups[dom][1]
     nbytes = _algorithmic_bytes(dom, st, eng.nvox)
     achieved = nbytes / (avg_ms * 1e-3) / 1e9

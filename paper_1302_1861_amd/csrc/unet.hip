@@ -397,14 +397,19 @@ __global__ void k_add_mask(const bf16_t *__restrict__ a,
 
 constexpr int kInC = 16;   // input channels: dose, density, 14 zeros
 
-// per-sample normalisation: scale[n] = 1 / max(dose of sample n)
+// per-sample normalisation: scale[n] = 1 / max(dose of sample n), or 1 when
+// that maximum is not positive.  kMaxBlocks blocks per sample each reduce a
+// slice and merge with an integer atomicMax on the bits of max(m, 0): for
+// non-negative floats the bit patterns order like the values.
+constexpr int kMaxBlocks = 256;
 __global__ void __launch_bounds__(256)
-k_sample_scale(const float *__restrict__ dose, int64_t per_sample,
-               float *__restrict__ scale) {
+k_sample_max(const float *__restrict__ dose, int64_t per_sample,
+             unsigned int *__restrict__ mbits) {
     __shared__ float s[256];
-    const float *d = dose + (int64_t)blockIdx.x * per_sample;
+    const float *d = dose + (int64_t)blockIdx.y * per_sample;
     float m = 0.0f;
-    for (int64_t i = threadIdx.x; i < per_sample; i += 256)
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_sample;
+         i += (int64_t)gridDim.x * 256)
         m = fmaxf(m, d[i]);
     s[threadIdx.x] = m;
     __syncthreads();
@@ -413,7 +418,20 @@ k_sample_scale(const float *__restrict__ dose, int64_t per_sample,
                                                     s[threadIdx.x + h]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) scale[blockIdx.x] = s[0] > 0.0f ? 1.0f / s[0] : 1.0f;
+    if (threadIdx.x == 0) atomicMax(&mbits[blockIdx.y], __float_as_uint(s[0]));
+}
+
+__global__ void k_scale_from_max(const unsigned int *__restrict__ mbits,
+                                 int n, float *__restrict__ scale) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float m = __uint_as_float(mbits[i]);
+    scale[i] = m > 0.0f ? 1.0f / m : 1.0f;
+}
+
+__global__ void k_fill_u32(unsigned int *p, int64_t n, unsigned int v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 // input tensor: channels (dose * scale, density, 0 ...)
@@ -602,6 +620,7 @@ struct Acts {
     bf16_t *xin, *e0a, *e0b, *p1, *e1a, *e1b, *p2, *e2a, *e2b, *p3, *e3a,
         *e3b, *cat2, *d2a, *d2b, *cat1, *d1a, *d1b, *cat0, *d0a, *d0b;
     float *out, *scale;
+    unsigned int *maxbits;
     // backward
     bf16_t *gA, *gB, *gC, *sk0, *sk1, *sk2, *wt;
     size_t bytes;
@@ -637,6 +656,7 @@ Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
     a.d0b = c.take<bf16_t>(v0 * c0);
     a.out = c.take<float>(v0);
     a.scale = c.take<float>(n);
+    a.maxbits = c.take<unsigned int>(n);
     a.gA = a.gB = a.gC = a.sk0 = a.sk1 = a.sk2 = a.wt = nullptr;
     if (train) {
         const int64_t big = std::max({v0 * (c1 + c0), v1 * (c2 + c1),
@@ -700,8 +720,15 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
     auto B = [&](int i) { return c.p + L[i].b_off; };
     const Vol *V = a.V;
     const int64_t per = V[0].voxels() / V[0].n;
-    hipLaunchKernelGGL(k_sample_scale, dim3(V[0].n), dim3(256), 0, c.st, dose,
-                       per, a.scale);
+    hipLaunchKernelGGL(k_fill_u32, dim3(nblk(V[0].n)), dim3(256), 0, c.st,
+                       a.maxbits, (int64_t)V[0].n, 0u);
+    hipLaunchKernelGGL(k_sample_max,
+                       dim3((unsigned)std::min<int64_t>(kMaxBlocks,
+                                                        nblk(per)),
+                            V[0].n),
+                       dim3(256), 0, c.st, dose, per, a.maxbits);
+    hipLaunchKernelGGL(k_scale_from_max, dim3(nblk(V[0].n)), dim3(256), 0,
+                       c.st, a.maxbits, V[0].n, a.scale);
     hipLaunchKernelGGL(k_pack_input, dim3(nblk(V[0].voxels() * kInC)),
                        dim3(256), 0, c.st, dose, rho, V[0].voxels(), per,
                        a.scale, a.xin);
