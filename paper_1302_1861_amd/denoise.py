@@ -170,6 +170,7 @@ def evaluate(pm: PairMaker, net, n_draws, n_in, n_ref, seed0=EVAL_SEED0,
     import torch
     from . import dose_gamma
     recs = []
+    pm.engine(int(n_in // 10))
     for k in range(n_draws):
         s = seed0 + k
         ph, f = pm.phantom(s), pm.field(s)
@@ -227,6 +228,8 @@ def time_to_gamma(pm: PairMaker, ph, field, ref, ladder, seed, target=0.99,
     tally), or None; and the pass rate at every rung tried."""
     import torch
     from . import dose_gamma
+    for n in ladder:        # engines (PSL build, buffers) outside the timing
+        pm.engine(int(n // batches_for(n)))
     rungs = []
     for n in ladder:
         torch.cuda.synchronize()
