@@ -211,6 +211,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the IMRT-plan and denoiser measurements")
+    ap.add_argument("--rebucket", type=int, default=None, choices=(0, 1),
+                    help="re-bucket secondary electrons (default: library)")
+    ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--extras-only", action="store_true",
                     help="only the IMRT-plan and denoiser measurements (for "
                          "profiling them apart from the main workload)")
@@ -233,7 +236,15 @@ def main():
 
     wl = S.workload_clinical(side=args.field)
     H = args.histories_per_step
-    eng = P.Engine(wl, histories_per_batch=H)
+    launch = None
+    if args.rebucket is not None or args.blocks_per_cu is not None:
+        kw = {}
+        if args.rebucket is not None:
+            kw["rebucket"] = args.rebucket
+        if args.blocks_per_cu is not None:
+            kw["blocks_per_cu"] = args.blocks_per_cu
+        launch = P.make_launch(**kw)
+    eng = P.Engine(wl, histories_per_batch=H, launch=launch)
     if args.extras_only:
         eng.step(0)
         eng.step(1)

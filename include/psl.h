@@ -269,7 +269,7 @@ typedef struct psl_dose_acc {
     void *data;                 /* device [nz*ny*nx]                         */
 } psl_dose_acc;
 
-/* Launch shape.  NULL selects defaults (256, 8, 0, 1); the autotuner
+/* Launch shape.  NULL selects defaults (256, 4, 0, 1); the autotuner
  * chooses values. */
 typedef struct psl_launch {
     int32_t block;              /* threads per block (256 in this build)     */

@@ -148,7 +148,7 @@ class psl_unet(C.Structure):
                 ("params_bf16", C.c_void_p)]
 
 
-def make_launch(blocks_per_cu=8, rebucket=1, n_cu=0, block=256):
+def make_launch(blocks_per_cu=4, rebucket=1, n_cu=0, block=256):
     L = psl_launch()
     L.block, L.blocks_per_cu, L.n_cu, L.rebucket = block, blocks_per_cu, \
         n_cu, rebucket

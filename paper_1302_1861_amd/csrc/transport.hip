@@ -234,6 +234,14 @@ __device__ __forceinline__ void sec_close(const SecStream &S,
 }
 
 // ---------------------------------------------------------------- photons -
+// Lanes are refilled once at least this many are idle.  Vector-memory
+// operations retire in issue order, so the wait for refill loads is also a
+// wait for the wave's earlier dose atomics and stores; refilling in bursts
+// pays that wait on fewer iterations.
+#ifndef PSL_PHOTON_REFILL_MIN
+#define PSL_PHOTON_REFILL_MIN 24
+#endif
+constexpr int kRefillMin = PSL_PHOTON_REFILL_MIN;
 template <int MODE>
 __global__ void __launch_bounds__(kBlock, 5)
 k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
@@ -272,7 +280,8 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
         // run, then from a fresh claim of 64 (one atomic per several
         // iterations instead of one per iteration)
         const uint64_t need = __ballot(!alive);
-        if (need && (pend_n > 0 || more)) {
+        if (need && (pend_n > 0 || more) &&
+            (__popcll(need) >= kRefillMin || need == ~0ull)) {
             const int n_need = __popcll(need);
             int64_t nb = 0;
             int ng = 0;
@@ -298,7 +307,14 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
                 E = ph.E[i]; x = ph.x[i]; y = ph.y[i]; z = ph.z[i];
                 u = ph.u[i]; v = ph.v[i]; w = ph.w[i]; wt = ph.wt[i];
                 uid = ph.uid[i];
-                rng.init(seed, uid, 0u, 0u, ph.ctr[i]);
+                const uint32_t c0 = ph.ctr[i];
+                // retire the refill loads here (vmcnt 0; expcnt and lgkmcnt
+                // left at their maxima), so that no load into the lane's
+                // state is outstanding at the loop's back edge, where a
+                // conservative wait would also wait for every store and
+                // atomic of the iteration
+                __builtin_amdgcn_s_waitcnt(0x0F70);
+                rng.init(seed, uid, 0u, 0u, c0);
                 mu1 = lerp_tab(s_mu, kTabMu,
                                (__logf(E) - H.mu_lnE0) * H.mu_inv_dlnE);
                 flights = 0;
@@ -442,7 +458,7 @@ struct ElWork {
 };
 
 template <int MODE>
-__global__ void __launch_bounds__(kBlock, 6)
+__global__ void __launch_bounds__(kBlock, 5)
 k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
             uint64_t seed, void *acc, double scale, uint32_t *work,
             uint64_t *part) {
@@ -474,63 +490,108 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
     uint32_t c_seg = 0, c_run = 0, c_dep = 0;
     double e_esc = 0.0;
     int part_i = wave % kParts, tried = 0;
-    // one electron per lane, followed to its end: the buckets keep the
-    // electrons of a wave at similar ranges
+    bool more = true;
+    int64_t pend_b = 0;   // claimed, not yet given to a lane (wave-uniform)
+    int pend_n = 0;
+    // the lane's electron
+    bool alive = false;
+    float T = 0, x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, wt = 0;
+    float r = 0;        // residual CSDA range, g/cm^2
+    float pe = 0;       // energy deposited in voxel pv, not yet tallied
+    float rho_v = 0;    // density of voxel vox
+    int ix = 0, iy = 0, iz = 0, segs = 0;
+    uint32_t vox = 0, pv = 0;   // voxel indices (< 2^32)
+    Rng rng;
+    rng.init(seed, 0, 0u, 0u, 0u);
+    // Lanes whose electron has ended take a new one between steps, so a
+    // wave is not held by its longest track while the deflection code
+    // still runs for all live lanes together.
     for (;;) {
-        int64_t base = 0;
-        int got = 0;
-        if (!claim_items(work, total, 64, part_i, tried, base, got)) break;
-        if ((int)__lane_id() >= got) continue;
-        int64_t t = base + __lane_id();
-        int sgi = 0;
-        while (t >= s_cnt[sgi]) { t -= s_cnt[sgi]; ++sgi; }
-        const psl_particles *src;
-        int64_t i;
-        if (sgi < W.n_b) {
-            src = &W.el;
-            i = (int64_t)(W.n_b - 1 - sgi) * W.cap_b + t;
-        } else {
-            src = &W.raw.p;
-            i = t;
-            if (W.raw.code[i] == kEmpty) continue;
+        const uint64_t need = __ballot(!alive);
+        if (need && (pend_n > 0 || more)) {
+            const int n_need = __popcll(need);
+            int64_t nb = 0;
+            int ng = 0;
+            if (pend_n < n_need && more) {
+                more = claim_items(work, total, 64, part_i, tried, nb, ng);
+                if (!more) ng = 0;
+            }
+            const int rank = __popcll(need & lanemask_lt());
+            int64_t it = -1;
+            if (rank < pend_n)
+                it = pend_b + rank;
+            else if (rank - pend_n < ng)
+                it = nb + (rank - pend_n);
+            const int used = min(n_need, pend_n + ng);
+            if (used <= pend_n) {
+                pend_b += used;
+                pend_n -= used;
+            } else {
+                pend_b = nb + (used - pend_n);
+                pend_n = ng - (used - pend_n);
+            }
+            if (!alive && it >= 0) {
+                int64_t t = it;
+                int sgi = 0;
+                while (t >= s_cnt[sgi]) { t -= s_cnt[sgi]; ++sgi; }
+                const psl_particles *src;
+                int64_t i;
+                bool ok = true;
+                if (sgi < W.n_b) {
+                    src = &W.el;
+                    i = (int64_t)(W.n_b - 1 - sgi) * W.cap_b + t;
+                } else {
+                    src = &W.raw.p;
+                    i = t;
+                    ok = W.raw.code[i] != kEmpty;
+                }
+                if (ok) {
+                    T = src->E[i];
+                    x = src->x[i]; y = src->y[i]; z = src->z[i];
+                    u = src->u[i]; v = src->v[i]; w = src->w[i];
+                    wt = src->wt[i];
+                    // entry voxel; a point on the box surface belongs to
+                    // the voxel inside
+                    ix = (int)floorf((x - P.x0) * P.ix_);
+                    iy = (int)floorf((y - P.y0) * P.iy_);
+                    iz = (int)floorf((z - P.z0) * P.iz_);
+                    if (ix < -1 || iy < -1 || iz < -1 || ix > P.nx ||
+                        iy > P.ny || iz > P.nz) {
+                        e_esc += (double)T * wt;
+                    } else {
+                        ix = min(max(ix, 0), P.nx - 1);
+                        iy = min(max(iy, 0), P.ny - 1);
+                        iz = min(max(iz, 0), P.nz - 1);
+                        vox = (uint32_t)(((int64_t)iz * P.ny + iy) * P.nx +
+                                         ix);
+                        if (T <= Y.t_cut) {
+                            tally<MODE>(acc, vox, T, wt, scale, c_dep);
+                        } else {
+                            rng.init(seed, src->uid[i], src->ctr[i],
+                                     kElectronTag, 0u);
+                            r = lerp_tab(s_rng, kTabRange,
+                                         (__logf(T) - H.rng_lnT0) *
+                                             H.rng_inv_dlnT);
+                            pv = vox;
+                            pe = 0.0f;
+                            segs = 0;
+                            rho_v = P.rho[vox];
+                            alive = true;
+                        }
+                    }
+                }
+            }
         }
-        float T = src->E[i];
-        float x = src->x[i], y = src->y[i], z = src->z[i];
-        float u = src->u[i], v = src->v[i], w = src->w[i], wt = src->wt[i];
-        // entry voxel; a point on the box surface belongs to the voxel
-        // inside
-        int ix = (int)floorf((x - P.x0) * P.ix_);
-        int iy = (int)floorf((y - P.y0) * P.iy_);
-        int iz = (int)floorf((z - P.z0) * P.iz_);
-        if (ix < -1 || iy < -1 || iz < -1 || ix > P.nx || iy > P.ny ||
-            iz > P.nz) {
-            e_esc += (double)T * wt;
+        if (!__ballot(alive)) {
+            if (!more && pend_n == 0) break;
             continue;
         }
-        ix = min(max(ix, 0), P.nx - 1);
-        iy = min(max(iy, 0), P.ny - 1);
-        iz = min(max(iz, 0), P.nz - 1);
-        int64_t vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
-        if (T <= Y.t_cut) {
-            tally<MODE>(acc, vox, T, wt, scale, c_dep);
-            continue;
-        }
-        Rng rng;
-        rng.init(seed, src->uid[i], src->ctr[i], kElectronTag, 0u);
-        float r = lerp_tab(s_rng, kTabRange,
-                           (__logf(T) - H.rng_lnT0) * H.rng_inv_dlnT);
-        int64_t pv = vox;
-        float pe = 0.0f;
-        int segs = 0;
-        // density of the current voxel, reloaded only when a face crossing
-        // names the next voxel (the load then overlaps that segment's
-        // geometry)
-        float rho_v = P.rho[vox];
+        // one step of Y.step cm for every live lane, split at voxel faces
         bool done = false;
-        while (!done) {
-            // one step of Y.step cm, split at voxel faces
-            float rem = Y.step, tm = 0.0f;
-            const float T0 = T;
+        float tm = 0.0f;
+        const float T0 = T;
+        if (alive) {
+            float rem = Y.step;
             while (rem > 0.0f) {
                 const float sx = u > 0.0f ? (P.x0 + (ix + 1) * P.dx - x) / u
                                : u < 0.0f ? (P.x0 + ix * P.dx - x) / u
@@ -549,11 +610,6 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 const float seg = fminf(rem, sb);
                 const float dm = rho_v * seg;
                 ++c_seg;
-                if (vox != pv) {
-                    tally<MODE>(acc, pv, pe, wt, scale, c_dep);
-                    pv = vox;
-                    pe = 0.0f;
-                }
                 if (dm >= r || ++segs > kMaxSegments) {
                     if (segs > kMaxSegments) ++c_run;
                     pe += T;
@@ -587,41 +643,48 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                         done = true;
                         break;
                     }
-                    vox = ((int64_t)iz * P.ny + iy) * P.nx + ix;
+                    vox = (uint32_t)(((int64_t)iz * P.ny + iy) * P.nx + ix);
+                    // the next density is requested before the deposit of
+                    // the voxel just left is sent
                     rho_v = P.rho[vox];
+                    if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale, c_dep);
+                    pv = vox;
+                    pe = 0.0f;
                 }
-            }
-            if (!done && !(Y.flags & PSL_FLAG_NO_MSC) && tm > 0.0f) {
-                // Highland angle from the pre-step energy and the step's
-                // mass thickness; space angle Rayleigh-distributed with
-                // scale theta0, truncated at pi
-                const float pbc = T0 * (T0 + 2.0f * kME) / (T0 + kME);
-                const float qq = tm / Y.X0;
-                float th0 = 13.6f / pbc * sqrtf(qq) *
-                            (1.0f + 0.038f * __logf(qq));
-                th0 = fmaxf(th0, 0.0f);
-                // candidates x, z, w of the first block (y is the
-                // azimuth), then four per block, until one is <= pi
-                u32x4 q = rng.draw();
-                const float phi_u = u01(q.y);
-                float th = th0 * sqrtf(-2.0f * __logf(u01(q.x)));
-                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.z)));
-                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.w)));
-                for (int t = 0; t < 15 && th > kPI; ++t) {
-                    q = rng.draw();
-                    th = th0 * sqrtf(-2.0f * __logf(u01(q.x)));
-                    if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.y)));
-                    if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.z)));
-                    if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.w)));
-                }
-                if (th > kPI) th = kPI * u01(rng.draw().x);
-                float sth, cth, sp, cp;
-                __sincosf(th, &sth, &cth);
-                __sincosf(2.0f * kPI * phi_u, &sp, &cp);
-                rotate(u, v, w, cth, sth, cp, sp);
             }
         }
-        if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale, c_dep);
+        if (alive && !done && !(Y.flags & PSL_FLAG_NO_MSC) && tm > 0.0f) {
+            // Highland angle from the pre-step energy and the step's mass
+            // thickness; space angle Rayleigh-distributed with scale
+            // theta0, truncated at pi
+            const float pbc = T0 * (T0 + 2.0f * kME) / (T0 + kME);
+            const float qq = tm / Y.X0;
+            float th0 = 13.6f / pbc * sqrtf(qq) * (1.0f + 0.038f * __logf(qq));
+            th0 = fmaxf(th0, 0.0f);
+            // candidates x, z, w of the first block (y is the azimuth),
+            // then four per block, until one is <= pi
+            u32x4 q = rng.draw();
+            const float phi_u = u01(q.y);
+            float th = th0 * sqrtf(-2.0f * __logf(u01(q.x)));
+            if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.z)));
+            if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.w)));
+            for (int t = 0; t < 15 && th > kPI; ++t) {
+                q = rng.draw();
+                th = th0 * sqrtf(-2.0f * __logf(u01(q.x)));
+                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.y)));
+                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.z)));
+                if (th > kPI) th = th0 * sqrtf(-2.0f * __logf(u01(q.w)));
+            }
+            if (th > kPI) th = kPI * u01(rng.draw().x);
+            float sth, cth, sp, cp;
+            __sincosf(th, &sth, &cth);
+            __sincosf(2.0f * kPI * phi_u, &sp, &cp);
+            rotate(u, v, w, cth, sth, cp, sp);
+        }
+        if (alive && done) {
+            if (pe > 0.0f) tally<MODE>(acc, pv, pe, wt, scale, c_dep);
+            alive = false;
+        }
     }
     StatAcc st;
     st.zero();
@@ -789,8 +852,8 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     if (s) return s;
     PSL_REQUIRE(ph->nx > 0 && ph->ny > 0 && ph->nz > 0 && ph->density,
                 "bad phantom");
-    PSL_REQUIRE((int64_t)ph->nx * ph->ny * ph->nz < ((int64_t)1 << 40),
-                "phantom too large");
+    PSL_REQUIRE((int64_t)ph->nx * ph->ny * ph->nz < ((int64_t)1 << 32),
+                "phantom too large (at most 2^32 - 1 voxels)");
     PSL_REQUIRE(ph->dx > 0 && ph->dy > 0 && ph->dz > 0, "bad voxel size");
     PSL_REQUIRE(ph->rho_max > 0, "rho_max must be positive (and >= every "
                                  "voxel density)");
@@ -806,7 +869,7 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     PSL_REQUIRE(phys->t_cut > 0 && phys->p_cut > 0 && phys->step > 0 &&
                     phys->X0 > 0,
                 "bad physics constants");
-    psl_launch L{kBlock, 8, 0, 1};
+    psl_launch L{kBlock, 4, 0, 1};
     if (launch) {
         PSL_REQUIRE(launch->block == kBlock,
                     "block must be %d in this build", kBlock);
