@@ -58,6 +58,11 @@ k_compact_offsets(uint32_t *__restrict__ tile_counts, int64_t n_tiles,
     if (threadIdx.x == 0) counts[q] = (uint32_t)carry;
 }
 
+// One wave per tile of kCompactRounds x 64 slots: all codes of the tile are
+// loaded first (independent loads, one wait), every destination is then
+// ranked with ballots, and the payload moves in groups of kMoveGroup rounds
+// whose loads are issued together.
+constexpr int kMoveGroup = 4;
 __global__ void __launch_bounds__(kCompactBlock)
 k_compact_scatter(Slots s, int64_t n_host, const uint32_t *n_dev,
                   int64_t mult, int64_t add, QueueRegions q,
@@ -69,40 +74,64 @@ k_compact_scatter(Slots s, int64_t n_host, const uint32_t *n_dev,
     const int64_t n = slot_count(n_host, n_dev, mult, add);
     const int64_t base = tile * kCompactTile;
     if (base >= n) return;
-    uint32_t run = lane < q.nq ? tile_off[(int64_t)lane * n_tiles + tile] : 0;
-    uint32_t lost = 0;
+    uint32_t code[kCompactRounds];
+#pragma unroll
     for (int r = 0; r < kCompactRounds; ++r) {
         const int64_t i = base + r * 64 + lane;
-        const uint32_t c = i < n ? (uint32_t)s.code[i] : (uint32_t)kEmpty;
+        code[r] = i < n ? (uint32_t)s.code[i] : (uint32_t)kEmpty;
+    }
+    uint32_t run = lane < q.nq ? tile_off[(int64_t)lane * n_tiles + tile] : 0;
+    int64_t dst[kCompactRounds];   // queue index, or -1 (empty or lost)
+    uint32_t lost = 0;
+#pragma unroll
+    for (int r = 0; r < kCompactRounds; ++r) {
+        const uint32_t c = code[r];
         uint64_t my = 0;
         uint32_t add_c = 0;
         for (int qq = 0; qq < q.nq; ++qq) {
-            uint64_t m = __ballot(c == (uint32_t)qq);
+            const uint64_t m = __ballot(c == (uint32_t)qq);
             if (c == (uint32_t)qq) my = m;
             if (lane == qq) add_c = (uint32_t)__popcll(m);
         }
         const bool valid = c < (uint32_t)q.nq;
         const uint32_t cb = __shfl(run, valid ? (int)c : 0);
         run += add_c;
+        dst[r] = -1;
         if (valid) {
-            const uint32_t dst = cb + (uint32_t)__popcll(my & lanemask_lt());
-            const psl_particles &P = c == 0 ? q.ph : q.el;
+            const uint32_t k = cb + (uint32_t)__popcll(my & lanemask_lt());
             const int64_t cap = c == 0 ? q.ph.capacity : q.cap_b;
-            if ((int64_t)dst < cap) {
-                const int64_t d = c == 0 ? (int64_t)dst
-                                         : (int64_t)(c - 1) * q.cap_b + dst;
-                P.E[d] = s.p.E[i];
-                P.x[d] = s.p.x[i];
-                P.y[d] = s.p.y[i];
-                P.z[d] = s.p.z[i];
-                P.u[d] = s.p.u[i];
-                P.v[d] = s.p.v[i];
-                P.w[d] = s.p.w[i];
-                P.wt[d] = s.p.wt[i];
-                P.uid[d] = s.p.uid[i];
-                P.ctr[d] = s.p.ctr[i];
-            } else {
+            if ((int64_t)k < cap)
+                dst[r] = c == 0 ? (int64_t)k : (int64_t)(c - 1) * q.cap_b + k;
+            else
                 ++lost;
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kCompactRounds; g += kMoveGroup) {
+        // masked loads of the group (only lanes with a destination touch
+        // memory), then the stores
+        float E[kMoveGroup], x[kMoveGroup], y[kMoveGroup], z[kMoveGroup];
+        float u[kMoveGroup], v[kMoveGroup], w[kMoveGroup], wt[kMoveGroup];
+        uint64_t uid[kMoveGroup];
+        uint32_t ctr[kMoveGroup];
+#pragma unroll
+        for (int j = 0; j < kMoveGroup; ++j) {
+            const int64_t i = base + (g + j) * 64 + lane;
+            if (dst[g + j] >= 0) {
+                E[j] = s.p.E[i]; x[j] = s.p.x[i]; y[j] = s.p.y[i];
+                z[j] = s.p.z[i]; u[j] = s.p.u[i]; v[j] = s.p.v[i];
+                w[j] = s.p.w[i]; wt[j] = s.p.wt[i]; uid[j] = s.p.uid[i];
+                ctr[j] = s.p.ctr[i];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kMoveGroup; ++j) {
+            const int64_t d = dst[g + j];
+            if (d >= 0) {
+                const psl_particles &P = code[g + j] == 0 ? q.ph : q.el;
+                P.E[d] = E[j]; P.x[d] = x[j]; P.y[d] = y[j]; P.z[d] = z[j];
+                P.u[d] = u[j]; P.v[d] = v[j]; P.w[d] = w[j];
+                P.wt[d] = wt[j]; P.uid[d] = uid[j]; P.ctr[d] = ctr[j];
             }
         }
     }

@@ -181,6 +181,27 @@ __global__ void k_cursor(const int64_t *__restrict__ N, int n_fields,
 constexpr uint32_t kSourceElectronCtr = 0xFFFFFFFFu;
 constexpr int kSampleBlock = 256;
 
+// The last index idx >= from with H[idx] <= h, given H[from] <= h and
+// H[n] > h (H non-decreasing, n + 1 entries): a galloping search, short
+// when the answer is near `from`.
+__device__ __forceinline__ int64_t range_at(const int64_t *__restrict__ H,
+                                            int64_t n, int64_t from,
+                                            int64_t h) {
+    if (H[from + 1] > h) return from;
+    int64_t a = from + 1, step = 1, b = a + 1;   // H[a] <= h
+    while (b < n && H[b] <= h) {
+        a = b;
+        step *= 2;
+        b = a + step;
+    }
+    if (b > n) b = n;                             // H[b] > h
+    while (b - a > 1) {
+        const int64_t mid = (a + b) >> 1;
+        if (H[mid] <= h) a = mid; else b = mid;
+    }
+    return a;
+}
+
 // One thread per history: read the particle from its PSL, apply the jaw
 // model, the fluence weight and g_ik, rotate by the gantry and move it to
 // the phantom; write the result into slot h with its queue code.
@@ -203,19 +224,41 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
     StatAcc st;
     st.zero();
     const int64_t h_total = (int64_t)*h_total_p;
-    const int64_t stride = (int64_t)gridDim.x * kSampleBlock;
-    for (int64_t h0 = (int64_t)blockIdx.x * kSampleBlock + threadIdx.x;
-         h0 < n_slots; h0 += stride) {
+    // Each wave takes a contiguous run of 64-history chunks.  The range of
+    // a chunk's first and last history is found by a wave-uniform search
+    // that starts from the previous chunk's range (ranges are sorted), so
+    // lanes search on their own only where a chunk straddles ranges.
+    const int lane = __lane_id();
+    const int64_t n_waves = (int64_t)gridDim.x * (kSampleBlock / 64);
+    const int64_t wave_g = (int64_t)blockIdx.x * (kSampleBlock / 64) +
+                           (threadIdx.x >> 6);
+    const int64_t n_chunks = (n_slots + 63) / 64;
+    const int64_t per_wave = (n_chunks + n_waves - 1) / n_waves;
+    const int64_t ch_end = min(n_chunks, (wave_g + 1) * per_wave);
+    int64_t lo = 0;   // wave-uniform, H[lo] <= first history of the chunk
+    for (int64_t ch = wave_g * per_wave; ch < ch_end; ++ch) {
+        const int64_t h0 = ch * 64 + lane;
+        const int64_t hf = ch * 64;
+        int64_t hi = lo;
+        if (hf < h_total) {
+            const int64_t hl = min(hf + 63, h_total - 1);
+            lo = range_at(H, n_ranges, lo, hf);
+            hi = range_at(H, n_ranges, lo, hl);
+        }
+        if (h0 >= n_slots) continue;
         uint8_t code = kEmpty;
         if (h0 < h_total) {
             st.add(PSL_STAT(histories), 1);
-            // range containing h: last idx with H[idx] <= h
-            int64_t lo = 0, hi = n_ranges;  // H[lo] <= h < H[hi]
-            while (hi - lo > 1) {
-                int64_t mid = (lo + hi) >> 1;
-                if (H[mid] <= h0) lo = mid; else hi = mid;
+            // range containing h0: last idx with H[idx] <= h0
+            int64_t idx = lo;
+            if (hi != lo) {
+                int64_t a0 = lo, b0 = hi + 1;   // H[a0] <= h0 < H[b0]
+                while (b0 - a0 > 1) {
+                    const int64_t mid = (a0 + b0) >> 1;
+                    if (H[mid] <= h0) a0 = mid; else b0 = mid;
+                }
+                idx = a0;
             }
-            const int64_t idx = lo;
             const int f = (int)(idx / n_keys);
             const int64_t k = idx % n_keys;
             const int64_t r = h0 - H[idx];
