@@ -179,12 +179,16 @@ struct TableHeader {
     float rng_lnT0, rng_inv_dlnT;   // residual range on ln T
     float inv_r0, inv_inv_dr;       // energy on residual range
     float t_cut, p_cut, r_max, e_max;
+    float kn_lnE0, kn_inv_dlnE;     // Compton fraction table on ln E
 };
 constexpr int kTabMu = 2048;
 constexpr int kTabRange = 2048;
 constexpr int kTabInv = 4096;
+constexpr int kKnE = 64;    // energies of the Compton fraction table
+constexpr int kKnQ = 96;    // quantiles per energy
 constexpr size_t kTabHeaderBytes = 256;
-// floats after the header: mu[kTabMu], range[kTabRange], inv[kTabInv]
+// floats after the header: mu[kTabMu], range[kTabRange], inv[kTabInv],
+// kn[kKnE][kKnQ]
 
 }  // namespace psl
 

@@ -7,8 +7,10 @@
 // atomic per wave on one of 64 counters that split the queue, so waves stay
 // full however unequal particle lifetimes are.
 //
-//   k_photons    Woodcock free flights against rho_max; Compton scattering
-//                sampled by Butcher and Messel's mixture-rejection method;
+//   k_photons    Woodcock free flights against rho_max; the Compton energy
+//                fraction from an inverse-CDF table of the Klein-Nishina
+//                distribution (normalised to its support, in LDS), so one
+//                random block drives a whole flight-and-scatter step;
 //                recoil electrons above the cut-off go into a dense stream
 //                of 64-slot chunks that each wave claims from partitioned
 //                counters (holes only at the end of a wave's last chunk);
@@ -47,6 +49,41 @@ double kn_sigma_cm2(double E) {
     double s = (1.0 + k) / (k * k) * (2.0 * (1.0 + k) / a - L / k) +
                L / (2.0 * k) - (1.0 + 3.0 * k) / (a * a);
     return 2.0 * M_PI * re * re * s;
+}
+
+// Klein-Nishina density of the energy fraction eps = E'/E on [eps0, 1],
+// unnormalised: eps + 1/eps - sin^2(theta), with 1 - cos(theta) =
+// (1 - eps) / (eps k), k = E / m_e c^2.
+double kn_eps_density(double eps, double k) {
+    const double s = (1.0 - eps) / (eps * k);
+    return eps + 1.0 / eps - s * (2.0 - s);
+}
+
+// Row of the inverse CDF at energy E, in the normalised variable
+// t = (eps - eps0) / (1 - eps0) at quantiles u_m = m / (kKnQ - 1): the CDF
+// on a fine grid by Simpson's rule per cell, inverted by linear
+// interpolation within the cell.
+void kn_inverse_cdf_row(double E, float *row) {
+    const double me = 0.51099895, k = E / me, e0 = 1.0 / (1.0 + 2.0 * k);
+    constexpr int n = 1 << 14;
+    std::vector<double> C(n + 1, 0.0);
+    const double h = (1.0 - e0) / n;
+    for (int i = 0; i < n; ++i) {
+        const double a = e0 + i * h, b = a + h;
+        C[i + 1] = C[i] + h / 6.0 *
+                              (kn_eps_density(a, k) +
+                               4.0 * kn_eps_density(0.5 * (a + b), k) +
+                               kn_eps_density(b, k));
+    }
+    int j = 0;
+    for (int m = 0; m < kKnQ; ++m) {
+        const double target = C[n] * m / (kKnQ - 1);
+        while (j < n - 1 && C[j + 1] < target) ++j;
+        const double f = C[j + 1] > C[j] ? (target - C[j]) / (C[j + 1] - C[j])
+                                         : 0.0;
+        const double t = (j + std::min(std::max(f, 0.0), 1.0)) / n;
+        row[m] = (float)(m == 0 ? 0.0 : (m == kKnQ - 1 ? 1.0 : t));
+    }
 }
 
 double bethe_mass_stopping(double T, double n_e, double I_eV) {
@@ -173,7 +210,8 @@ struct SecStream {
     Slots s;
     int64_t n_chunks;
     uint32_t *chunk_ctr;     // kParts counters, kPartStride apart
-    uint32_t *chunks_used;   // number of chunks claimed (max index + 1)
+    uint32_t *chunks_used;   // number of chunks claimed (max index + 1),
+                             // set by k_chunks_used after the photons
 };
 
 // Wave-uniform cursor into the wave's current chunk.
@@ -195,7 +233,6 @@ __device__ __forceinline__ int64_t new_chunk(const SecStream &S,
         old = __shfl(old, 0);
         if (p0 + (int64_t)old < p1) {
             const int64_t ch = p0 + old;
-            if (__lane_id() == 0) atomicMax(S.chunks_used, (uint32_t)(ch + 1));
             return ch * 64;
         }
         c.part = (c.part + 1) % kParts;
@@ -249,11 +286,14 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
           const float *__restrict__ tables, uint64_t seed, void *acc,
           double scale, uint32_t *work, uint64_t *part) {
     __shared__ float s_mu[kTabMu];
+    __shared__ float s_kn[kKnE * kKnQ];
     __shared__ float s_bk[PSL_MAX_QBUCKETS + 1];
     __shared__ uint64_t s_red[(kBlock / 64) * kStatWords];
     const TableHeader H = *reinterpret_cast<const TableHeader *>(tables);
     const float *gmu = tables + kTabHeaderBytes / 4;
     for (int i = threadIdx.x; i < kTabMu; i += kBlock) s_mu[i] = gmu[i];
+    const float *gkn = gmu + kTabMu + kTabRange + kTabInv;
+    for (int i = threadIdx.x; i < kKnE * kKnQ; i += kBlock) s_kn[i] = gkn[i];
     if (threadIdx.x <= PSL_MAX_QBUCKETS)
         s_bk[threadIdx.x] = qcfg.e_bucket_edges[threadIdx.x];
     __syncthreads();
@@ -357,30 +397,26 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
                            xi <= P.rho_min || xi <= P.rho[vox]) {
                     // (rho_min <= every density: the first test implies
                     // the second and spares the gather)
-                    // Compton: Butcher-Messel sampling of eps = E'/E
+                    // Compton: eps = E'/E from the inverse CDF (bilinear
+                    // in ln E and the quantile), then the exact kinematics
                     const float k = E / kME;
                     const float e0 = 1.0f / (1.0f + 2.0f * k);
-                    const float e0sq = e0 * e0;
-                    const float a1 = -__logf(e0), a2 = 0.5f * (1.0f - e0sq);
-                    float eps, onecost, sint2, phi_u;
-                    for (int tries = 0;; ++tries) {
-                        const u32x4 q = rng.draw();
-                        const float r1 = u01(q.x), r2 = u01(q.y),
-                                    r3 = u01(q.z);
-                        phi_u = u01(q.w);
-                        float epssq;
-                        if (r1 * (a1 + a2) < a1) {
-                            eps = __expf(-a1 * r2);
-                            epssq = eps * eps;
-                        } else {
-                            epssq = e0sq + (1.0f - e0sq) * r2;
-                            eps = sqrtf(epssq);
-                        }
-                        onecost = (1.0f - eps) / (eps * k);
-                        sint2 = onecost * (2.0f - onecost);
-                        const float gr = 1.0f - eps * sint2 / (1.0f + epssq);
-                        if (gr >= r3 || tries > 1000) break;
-                    }
+                    float fe = (__logf(E) - H.kn_lnE0) * H.kn_inv_dlnE;
+                    fe = fminf(fmaxf(fe, 0.0f), (float)(kKnE - 1) - 1e-3f);
+                    const int ie = (int)fe;
+                    const float we = fe - (float)ie;
+                    const float fq = u01(rf.z) * (float)(kKnQ - 1);
+                    const int iq = min((int)fq, kKnQ - 2);
+                    const float wq = fq - (float)iq;
+                    const float *r0 = s_kn + ie * kKnQ + iq;
+                    const float *r1 = r0 + kKnQ;
+                    const float t0 = r0[0] + wq * (r0[1] - r0[0]);
+                    const float t1 = r1[0] + wq * (r1[1] - r1[0]);
+                    const float t = t0 + we * (t1 - t0);
+                    const float eps = e0 + t * (1.0f - e0);
+                    const float onecost = (1.0f - eps) / (eps * k);
+                    const float sint2 = onecost * (2.0f - onecost);
+                    const float phi_u = u01(rf.w);
                     ++c_int;
                     const float cost = 1.0f - onecost;
                     const float sint = sqrtf(fmaxf(sint2, 0.0f));
@@ -695,6 +731,30 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
     block_stats_write(st, s_red, part);
 }
 
+// chunks_used = 1 + the highest chunk index claimed: partition p (chunks
+// [p len, min((p + 1) len, n))) handed out its first min(ctr[p], its size)
+// chunks.  One small kernel instead of a same-address atomic per chunk.
+__global__ void k_chunks_used(const uint32_t *__restrict__ ctr,
+                              int64_t n_chunks, uint32_t *__restrict__ used) {
+    __shared__ uint32_t s[kParts];
+    const int p = threadIdx.x;
+    const int64_t len = (n_chunks + kParts - 1) / kParts;
+    const int64_t p0 = (int64_t)p * len;
+    const int64_t p1 = p0 + len < n_chunks ? p0 + len : n_chunks;
+    uint32_t top = 0;
+    if (p0 < p1) {
+        const int64_t got = min((int64_t)ctr[p * kPartStride], p1 - p0);
+        if (got > 0) top = (uint32_t)(p0 + got);
+    }
+    s[p] = top;
+    __syncthreads();
+    if (p == 0) {
+        uint32_t m = 0;
+        for (int i = 0; i < kParts; ++i) m = max(m, s[i]);
+        *used = m;
+    }
+}
+
 __global__ void k_transport_init(uint32_t *words, int n_words,
                                  uint32_t *codes, int64_t n_code_words) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -821,6 +881,14 @@ extern "C" psl_status psl_physics_init(const psl_physics *phys,
         }
         inv[i] = (float)(i == 0 ? phys->t_cut : T);
     }
+    // Compton energy fraction: inverse CDF on ln E over [p_cut, emax]
+    float *kn = inv + kTabInv;
+    const double klo = std::log(phys->p_cut), khi = std::log(emax);
+    const double kd = (khi - klo) / (kKnE - 1);
+    for (int i = 0; i < kKnE; ++i)
+        kn_inverse_cdf_row(std::exp(klo + i * kd), kn + i * kKnQ);
+    H->kn_lnE0 = (float)klo;
+    H->kn_inv_dlnE = (float)(1.0 / kd);
     H->n_inv = kTabInv;
     H->inv_r0 = 0.0f;
     H->inv_inv_dr = (float)(1.0 / dr);
@@ -923,6 +991,8 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
                                q->ph, q->d_counts, w.sec, *q, P, Y, tab, seed,
                                acc->data, scale, work_ph, w.part);
     }
+    hipLaunchKernelGGL(k_chunks_used, dim3(1), dim3(kParts), 0, st,
+                       w.sec.chunk_ctr, w.sec.n_chunks, w.sec.chunks_used);
     ElWork ew{q->el, q->n_ebuckets, cap_b, q->d_counts, Slots{}, nullptr};
     if (L.rebucket) {
         ProfScope prof(PSL_PROF_REBUCKET, st);

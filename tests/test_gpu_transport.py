@@ -123,6 +123,48 @@ def test_first_collision_dose_closed_form():
     assert tot == pytest.approx(n * E, rel=1e-5)
 
 
+@pytest.mark.parametrize("E", [0.03, 0.1, 1.0, 6.0])
+def test_compton_mean_energy_transfer(E):
+    """First collisions of a monoenergetic beam: deposited recoil energy
+    over deposited + scattered photon energy is the mean energy-transfer
+    fraction T/E of the Klein-Nishina distribution (quadrature here),
+    within 4 standard errors from its exact variance."""
+    from scipy import integrate
+    n = 4_000_000
+    rng = np.random.default_rng(7)
+    x = rng.uniform(-4, 4, n)
+    y = rng.uniform(-4, 4, n)
+    ps = phase_space_arrays(np.zeros(n), np.full(n, E), x, y, np.zeros(n),
+                            np.zeros(n), np.ones(n), 100.0)
+    ph = S.water_phantom((8, 8, 40), 2.0, (-8.0, -8.0, 100.0))
+    f = S.Field(-4, 4, -4, 4, jaws=False)
+    wl = _wl(ps, _single_bin_grid(ps, 4.0), ph, [f], n * 2, 2, fixed=False)
+    import paper_1302_1861_amd as P
+    eng = _engine(wl, n, phys_flags=P.PSL_FLAG_FIRST_COLLISION)
+    eng.sample(0)
+    eng.transport(0)
+    import torch
+    torch.cuda.synchronize()
+    st = eng.stats_dict()
+    dep = float(eng.acc_t.cpu().numpy().sum())
+    got = dep / (dep + st["e_killed"])
+    k = E / ME
+
+    def dsig(c):
+        Pr = 1.0 / (1.0 + k * (1.0 - c))
+        return Pr * Pr * (Pr + 1.0 / Pr - (1.0 - c * c))
+    norm = integrate.quad(dsig, -1, 1, epsabs=0, epsrel=1e-12)[0]
+    m1 = integrate.quad(lambda c: dsig(c) * (1 - 1 / (1 + k * (1 - c))), -1,
+                        1, epsabs=0, epsrel=1e-12)[0] / norm
+    m2 = integrate.quad(lambda c: dsig(c) * (1 - 1 / (1 + k * (1 - c))) ** 2,
+                        -1, 1, epsabs=0, epsrel=1e-12)[0] / norm
+    se = np.sqrt((m2 - m1 * m1) / st["interactions"])
+    _say("E", E, "T/E", got, "exact", m1, "z", (got - m1) / se,
+         "interactions", st["interactions"])
+    assert st["interactions"] > n // 4
+    assert abs(got - m1) < 4 * se
+
+
 def test_electron_pencil_depth_staircase_no_scattering():
     """A 2 MeV electron pencil beam without scattering deposits the
     deterministic CSDA staircase of the oracle."""
