@@ -297,11 +297,15 @@ def main():
     achieved = nbytes / (avg_ms * 1e-3) / 1e9
     kernel_ms = {g: round(v[0] / v[1], 4) for g, v in groups.items()}
     # dose atomics of the transport kernels against the measured roof
-    t_tr = (groups.get("photons", (0, 1))[0] / groups.get("photons", (0, 1))[1]
-            + groups.get("electrons", (0, 1))[0]
-            / groups.get("electrons", (0, 1))[1]) * 1e-3
+    def _avg(g):
+        v = groups.get(g)
+        return v[0] / v[1] * 1e-3 if v else 0.0
+    t_ph, t_el = _avg("photons"), _avg("electrons")
     n_atom = st["deposits"] + st["photon_deposits"]
-    atomic_rate = n_atom / t_tr if t_tr > 0 else 0.0
+    atomic_rate = n_atom / (t_ph + t_el) if t_ph + t_el > 0 else 0.0
+    per_kernel_atomics = {
+        "photons": st["photon_deposits"] / t_ph if t_ph else 0.0,
+        "electrons": st["deposits"] / t_el if t_el else 0.0}
 
     # time to 1% uncertainty from the timed steps (batches)
     d, s = eng.finalize()
@@ -344,6 +348,9 @@ def main():
                             "achieved": atomic_rate, "peak": atom_scatter,
                             "unit": "u64 atomic adds/s",
                             "frac": atomic_rate / atom_scatter,
+                            "per_kernel_frac": {
+                                k: v / atom_scatter
+                                for k, v in per_kernel_atomics.items()},
                             "same_address_peak": atom_same,
                             "atomics_per_step": n_atom},
         "batch_stats": {k: st[k] for k in (
