@@ -252,10 +252,12 @@ typedef struct psl_physics {
 /*
  * psl_physics_init - builds the transport tables for `phys` into d_tables
  * (device, PSL_TABLE_BYTES): Compton attenuation per unit density
- * n_e sigma_KN(E) on a log energy grid, and the CSDA residual range above
- * t_cut of the Bethe collision stopping power with its inverse.  The host
- * computes them in double and enqueues one copy; phys->e_max must cover the
- * highest particle energy.
+ * n_e sigma_KN(E) on a log energy grid, the CSDA residual range above
+ * t_cut of the Bethe collision stopping power with its inverse, and the
+ * inverse cumulative distribution of the Klein-Nishina energy fraction
+ * (64 log-spaced energies from p_cut x 96 quantiles, in the fraction
+ * normalised to its support).  The host computes them in double and
+ * enqueues one copy; phys->e_max must cover the highest particle energy.
  */
 psl_status psl_physics_init(const psl_physics *phys, void *d_tables,
                             void *stream);
@@ -284,8 +286,11 @@ typedef struct psl_launch {
  * transport_batch - transports every queued particle to exhaustion and adds
  * energy x weight per voxel to acc.  Physics (the paper defers to gDPM;
  * this is the model of the workloads): photons undergo Compton scattering
- * only (Klein-Nishina, free electrons at rest), tracked by Woodcock delta
- * tracking with majorant rho_max; a recoil electron above t_cut is queued in
+ * only (Klein-Nishina, free electrons at rest, energy fraction drawn from
+ * the tabulated inverse distribution), tracked by Woodcock delta tracking
+ * with majorant rho_max (and minorant rho_min: a tentative collision below
+ * it is real without a density read); a recoil electron above t_cut is
+ * queued in
  * its energy bucket, otherwise deposited on the spot; photons below p_cut
  * deposit on the spot.  Electrons slow down continuously (CSDA, Bethe
  * collision stopping power, I = I_eV, no density effect) in steps of
