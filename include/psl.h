@@ -134,10 +134,11 @@ typedef struct psl_particles {
     uint32_t *ctr;              /* random-number identity (see transport)    */
 } psl_particles;
 
-/* Transport queues.  Electrons are kept in n_ebuckets regions of
+/* Transport queues.  Source electrons are kept in n_ebuckets regions of
  * el.capacity / n_ebuckets entries each, one per kinetic-energy bucket
- * [e_bucket_edges[b], e_bucket_edges[b+1]).  d_counts (device uint32,
- * PSL_QCOUNTS entries): [0] photons queued, [1 + b] electrons in bucket b,
+ * [e_bucket_edges[b], e_bucket_edges[b+1]); secondary electrons live in
+ * the transport workspace.  d_counts (device uint32, PSL_QCOUNTS
+ * entries): [0] photons queued, [1 + b] electrons in bucket b,
  * [PSL_QCOUNTS - 1] entries lost because a region was full (a batch with a
  * non-zero value here is invalid and must be re-run with more capacity). */
 #define PSL_QCOUNTS (PSL_MAX_QBUCKETS + 2)
@@ -277,9 +278,10 @@ typedef struct psl_launch {
     int32_t block;              /* threads per block (256 in this build)     */
     int32_t blocks_per_cu;      /* transport blocks launched per CU, 1..64   */
     int32_t n_cu;               /* CUs to assume (0 = query the device)      */
-    int32_t rebucket;           /* 1: compact secondary electrons into the   */
-                                /* energy buckets before electron transport; */
-                                /* 0: transport them from the raw stream     */
+    int32_t rebucket;           /* 1: transport electrons bucket by bucket,  */
+                                /* highest energy first (secondary chunks    */
+                                /* listed by bucket); 0: all source          */
+                                /* electrons, then the pool in claim order   */
 } psl_launch;
 
 /*
@@ -302,8 +304,9 @@ typedef struct psl_launch {
  * results do not depend on scheduling.  Photons are processed first, then
  * electron buckets from the highest energy down.  Queues are consumed
  * (counts zeroed).
- * Secondary electrons are first written to a stream of at most
- * 2 x ph.capacity entries (beyond that they are counted in stats.lost).
+ * Secondary electrons go to a workspace pool of 64-slot chunks (room for
+ * 2 x ph.capacity of them; beyond that they are counted in stats.lost),
+ * each chunk holding one energy bucket.
  * Errors: PSL_EINVAL (sizes, null pointers, bad acc mode), PSL_ENOSPC
  * (workspace too small).
  */

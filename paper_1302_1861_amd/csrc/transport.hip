@@ -11,18 +11,19 @@
 //                fraction from an inverse-CDF table of the Klein-Nishina
 //                distribution (normalised to its support, in LDS), so one
 //                random block drives a whole flight-and-scatter step;
-//                recoil electrons above the cut-off go into a dense stream
-//                of 64-slot chunks that each wave claims from partitioned
-//                counters (holes only at the end of a wave's last chunk);
-//                the attenuation table is staged in LDS.
-//   rebucket     (optional) ballot-ranked compaction of that stream into the
-//                electron energy buckets, after the source electrons.
+//                recoil electrons above the cut-off go into 64-slot chunks
+//                of a pool; each wave keeps one open chunk per energy
+//                bucket and tags the chunks it claims (from partitioned
+//                counters) with their bucket; the attenuation and Compton
+//                tables are staged in LDS.
+//   rebucket     (optional) lists the pool's chunks by bucket (one block).
 //   k_electrons  CSDA steps split at voxel faces; the energy after each
 //                piece comes from the residual-range table and its inverse
 //                in LDS; deposits into one voxel are merged before the
 //                atomic; Highland deflection after each step.  Work is the
-//                electron buckets from the highest energy down, then (when
-//                not re-bucketed) the secondary stream.
+//                per bucket from the highest energy down: the source
+//                electrons of the bucket, then its listed chunks (or, when
+//                not re-bucketed, all source electrons, then the pool).
 #include "common.hpp"
 #include "compact.hpp"
 
@@ -204,70 +205,78 @@ __device__ __forceinline__ bool claim_items(uint32_t *ctr, int64_t n,
     return false;
 }
 
-// Dense output stream of secondary electrons: 64-slot chunks claimed per
-// wave from kParts partitions of the chunk space.
+// Secondary electrons: a pool of 64-slot chunks claimed per wave from kParts
+// partitions of the chunk space.  A wave keeps one open chunk per electron
+// energy bucket and tags each chunk it claims with that bucket, so the
+// secondaries arrive already bucketed: listing the chunks of each bucket
+// replaces moving the particles.
 struct SecStream {
     Slots s;
     int64_t n_chunks;
     uint32_t *chunk_ctr;     // kParts counters, kPartStride apart
     uint32_t *chunks_used;   // number of chunks claimed (max index + 1),
                              // set by k_chunks_used after the photons
+    uint8_t *chunk_bucket;   // bucket of each claimed chunk (kEmpty: none)
 };
 
-// Wave-uniform cursor into the wave's current chunk.
-struct SecCursor {
-    int64_t base = -1;   // first slot of the current chunk (-1: none)
-    int fill = 64;       // slots used in it
-    int part, tried = 0;
-};
-
-__device__ __forceinline__ int64_t new_chunk(const SecStream &S,
-                                             SecCursor &c) {
+// A fresh chunk index for the wave, or -1 once the pool is exhausted.
+// Wave-uniform; `part` and `tried` are the wave's partition cursor.
+__device__ __forceinline__ int64_t new_chunk(const SecStream &S, int &part,
+                                             int &tried) {
     const int64_t len = (S.n_chunks + kParts - 1) / kParts;
-    while (c.tried < kParts) {
-        const int64_t p0 = (int64_t)c.part * len;
+    while (tried < kParts) {
+        const int64_t p0 = (int64_t)part * len;
         const int64_t p1 = p0 + len < S.n_chunks ? p0 + len : S.n_chunks;
         uint32_t old = 0;
         if (__lane_id() == 0 && p0 < p1)
-            old = atomicAdd(&S.chunk_ctr[c.part * kPartStride], 1u);
+            old = atomicAdd(&S.chunk_ctr[part * kPartStride], 1u);
         old = __shfl(old, 0);
-        if (p0 + (int64_t)old < p1) {
-            const int64_t ch = p0 + old;
-            return ch * 64;
-        }
-        c.part = (c.part + 1) % kParts;
-        ++c.tried;
+        if (p0 + (int64_t)old < p1) return p0 + old;
+        part = (part + 1) % kParts;
+        ++tried;
     }
     return -1;
 }
 
-// Reserve one slot for each lane with `want`; -1 if the stream is full.
+// Reserves one slot for each lane with `want` in the wave's open chunk of
+// its bucket b (cursors cb[b], cf[b] in LDS: chunk index or -1, slots
+// used); -1 when the pool is full.  Lanes of one bucket are served together,
+// one bucket per pass.
 __device__ __forceinline__ int64_t sec_reserve(const SecStream &S,
-                                               SecCursor &c, bool want) {
-    const uint64_t m = __ballot(want);
-    if (!m) return -1;
-    const int cnt = __popcll(m);
-    const int rank = __popcll(m & lanemask_lt());
-    const int left = 64 - c.fill;
+                                               int32_t *cb, int32_t *cf,
+                                               int &part, int &tried,
+                                               bool want, int b) {
+    const int lane = __lane_id();
+    uint64_t pend = __ballot(want);
     int64_t slot = -1;
-    if (cnt <= left) {
-        if (want && c.base >= 0) slot = c.base + c.fill + rank;
-        c.fill += cnt;
-    } else {
-        if (want && rank < left && c.base >= 0) slot = c.base + c.fill + rank;
-        const int64_t nb = new_chunk(S, c);
-        if (want && rank >= left && nb >= 0) slot = nb + (rank - left);
-        c.base = nb;
-        c.fill = cnt - left;
+    while (pend) {
+        const int bb = __shfl(b, __ffsll((unsigned long long)pend) - 1);
+        const uint64_t grp = __ballot(want && b == bb) & pend;
+        const int cnt = __popcll(grp);
+        const int rank = __popcll(grp & lanemask_lt());
+        const bool mine = (grp >> lane) & 1ull;
+        int32_t base = cb[bb], fill = cf[bb];
+        const int left = base >= 0 ? 64 - fill : 0;
+        if (cnt <= left) {
+            if (mine) slot = (int64_t)base * 64 + fill + rank;
+            fill += cnt;
+        } else {
+            if (mine && rank < left) slot = (int64_t)base * 64 + fill + rank;
+            const int64_t nc = new_chunk(S, part, tried);
+            if (nc >= 0) {
+                if (lane == 0) S.chunk_bucket[nc] = (uint8_t)bb;
+                if (mine && rank >= left) slot = nc * 64 + (rank - left);
+            }
+            base = (int32_t)nc;
+            fill = cnt - left;
+        }
+        if (lane == 0) {
+            cb[bb] = base;
+            cf[bb] = fill;
+        }
+        pend &= ~grp;
     }
     return slot;
-}
-
-// Marks the unused tail of the wave's last chunk empty.
-__device__ __forceinline__ void sec_close(const SecStream &S,
-                                          const SecCursor &c) {
-    if (c.base >= 0 && (int)__lane_id() >= c.fill)
-        S.s.code[c.base + __lane_id()] = kEmpty;
 }
 
 // ---------------------------------------------------------------- photons -
@@ -289,6 +298,8 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
     __shared__ float s_kn[kKnE * kKnQ];
     __shared__ float s_bk[PSL_MAX_QBUCKETS + 1];
     __shared__ uint64_t s_red[(kBlock / 64) * kStatWords];
+    __shared__ int32_t s_cb[kBlock / 64][PSL_MAX_QBUCKETS];   // open chunks
+    __shared__ int32_t s_cf[kBlock / 64][PSL_MAX_QBUCKETS];
     const TableHeader H = *reinterpret_cast<const TableHeader *>(tables);
     const float *gmu = tables + kTabHeaderBytes / 4;
     for (int i = threadIdx.x; i < kTabMu; i += kBlock) s_mu[i] = gmu[i];
@@ -296,6 +307,10 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
     for (int i = threadIdx.x; i < kKnE * kKnQ; i += kBlock) s_kn[i] = gkn[i];
     if (threadIdx.x <= PSL_MAX_QBUCKETS)
         s_bk[threadIdx.x] = qcfg.e_bucket_edges[threadIdx.x];
+    if (threadIdx.x < (kBlock / 64) * PSL_MAX_QBUCKETS) {
+        (&s_cb[0][0])[threadIdx.x] = -1;
+        (&s_cf[0][0])[threadIdx.x] = 0;
+    }
     __syncthreads();
     const int64_t n = (int64_t)counts[0];
     const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
@@ -307,8 +322,8 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
     // [pend_b, pend_b + pend_n) (wave-uniform)
     int64_t pend_b = 0;
     int pend_n = 0;
-    SecCursor cur;
-    cur.part = wave % kParts;
+    int32_t *cb = s_cb[threadIdx.x >> 6], *cf = s_cf[threadIdx.x >> 6];
+    int sec_part = wave % kParts, sec_tried = 0;
     bool alive = false;
     float E = 0, x = 0, y = 0, z = 0, u = 0, v = 0, w = 0, wt = 0, mu1 = 0;
     uint64_t uid = 0;
@@ -448,13 +463,15 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
                 }
             }
         }
-        // recoil electrons into the dense secondary stream
-        const int64_t slot = sec_reserve(sec, cur, push_e);
+        // recoil electrons into the wave's open chunk of their bucket
+        int b = 0;
+        if (push_e)
+            for (int j = 1; j < qcfg.n_ebuckets; ++j)
+                if (Te >= s_bk[j]) b = j;
+        const int64_t slot =
+            sec_reserve(sec, cb, cf, sec_part, sec_tried, push_e, b);
         if (push_e) {
             if (slot >= 0) {
-                int b = 0;
-                for (int j = 1; j < qcfg.n_ebuckets; ++j)
-                    if (Te >= s_bk[j]) b = j;
                 const Slots &S = sec.s;
                 S.p.E[slot] = Te; S.p.x[slot] = x; S.p.y[slot] = y;
                 S.p.z[slot] = z; S.p.u[slot] = eu; S.p.v[slot] = ev;
@@ -467,7 +484,6 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
             }
         }
     }
-    sec_close(sec, cur);
     StatAcc st;
     st.zero();
     st.add(PSL_STAT(interactions), c_int);
@@ -489,8 +505,13 @@ struct ElWork {
     int32_t n_b;
     int64_t cap_b;
     const uint32_t *counts;
-    Slots raw;                  // raw.code == nullptr: no raw stream
-    const uint32_t *raw_chunks; // chunks used in the raw stream
+    Slots sec;                  // secondary chunk pool (code kEmpty: hole)
+    const uint32_t *sec_chunks; // chunks used in the pool
+    // bucketed: per bucket, the pool chunks tagged with it (list_off[b],
+    // list_cnt[b] into list); otherwise the pool in claim order
+    int bucketed;
+    const int32_t *list;
+    const uint32_t *list_off, *list_cnt;
 };
 
 template <int MODE>
@@ -501,27 +522,39 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
     __shared__ float s_rng[kTabRange];
     __shared__ float s_inv[kTabInv];
     __shared__ uint64_t s_red[(kBlock / 64) * kStatWords];
-    __shared__ int64_t s_cnt[PSL_MAX_QBUCKETS + 1];
+    // work segments in processing order, buckets from high to low energy:
+    // bucketed -- (source electrons of b, secondary chunks of b) per bucket;
+    // otherwise -- source electrons of every bucket, then the whole pool
+    __shared__ int64_t s_cnt[2 * PSL_MAX_QBUCKETS + 1];
     const TableHeader H = *reinterpret_cast<const TableHeader *>(tables);
     const float *g = tables + kTabHeaderBytes / 4 + kTabMu;
     for (int i = threadIdx.x; i < kTabRange; i += kBlock) s_rng[i] = g[i];
     for (int i = threadIdx.x; i < kTabInv; i += kBlock)
         s_inv[i] = g[kTabRange + i];
-    // segment sizes in processing order: buckets high to low, then raw
-    if (threadIdx.x <= PSL_MAX_QBUCKETS) {
+    const int n_seg = W.bucketed ? 2 * W.n_b : W.n_b + 1;
+    if (threadIdx.x < n_seg) {
+        const int sg = threadIdx.x;
         int64_t c = 0;
-        if (threadIdx.x < W.n_b) {
-            const int b = W.n_b - 1 - threadIdx.x;
+        if (W.bucketed) {
+            const int b = W.n_b - 1 - sg / 2;
+            if (sg % 2 == 0) {
+                c = (int64_t)W.counts[1 + b];
+                c = c < W.cap_b ? c : W.cap_b;
+            } else {
+                c = (int64_t)W.list_cnt[b] * 64;
+            }
+        } else if (sg < W.n_b) {
+            const int b = W.n_b - 1 - sg;
             c = (int64_t)W.counts[1 + b];
             c = c < W.cap_b ? c : W.cap_b;
-        } else if (threadIdx.x == W.n_b && W.raw.code) {
-            c = (int64_t)(*W.raw_chunks) * 64;
+        } else {
+            c = (int64_t)(*W.sec_chunks) * 64;
         }
-        s_cnt[threadIdx.x] = c;
+        s_cnt[sg] = c;
     }
     __syncthreads();
     int64_t total = 0;
-    for (int b = 0; b <= W.n_b; ++b) total += s_cnt[b];
+    for (int sg = 0; sg < n_seg; ++sg) total += s_cnt[sg];
     const int wave = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     uint32_t c_seg = 0, c_run = 0, c_dep = 0;
     double e_esc = 0.0;
@@ -573,13 +606,21 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 const psl_particles *src;
                 int64_t i;
                 bool ok = true;
-                if (sgi < W.n_b) {
+                const bool dense = W.bucketed ? sgi % 2 == 0 : sgi < W.n_b;
+                if (dense) {
+                    const int b = W.n_b - 1 - (W.bucketed ? sgi / 2 : sgi);
                     src = &W.el;
-                    i = (int64_t)(W.n_b - 1 - sgi) * W.cap_b + t;
+                    i = (int64_t)b * W.cap_b + t;
                 } else {
-                    src = &W.raw.p;
-                    i = t;
-                    ok = W.raw.code[i] != kEmpty;
+                    src = &W.sec.p;
+                    if (W.bucketed) {
+                        const int b = W.n_b - 1 - sgi / 2;
+                        i = (int64_t)W.list[W.list_off[b] + t / 64] * 64 +
+                            t % 64;
+                    } else {
+                        i = t;
+                    }
+                    ok = W.sec.code[i] != kEmpty;
                 }
                 if (ok) {
                     T = src->E[i];
@@ -755,17 +796,68 @@ __global__ void k_chunks_used(const uint32_t *__restrict__ ctr,
     }
 }
 
+// Lists the pool chunks of each bucket (one block): counts by wave ballots
+// and LDS atomics, offsets by a scan over buckets, then positions.  The
+// order within a bucket is irrelevant: every electron's result depends only
+// on its own state and random stream.
+constexpr int kListBlock = 1024;
+__global__ void __launch_bounds__(kListBlock)
+k_bucket_chunks(const uint8_t *__restrict__ tag,
+                const uint32_t *__restrict__ chunks_used, int n_b,
+                int32_t *__restrict__ list, uint32_t *__restrict__ off,
+                uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t s_cnt[PSL_MAX_QBUCKETS], s_cur[PSL_MAX_QBUCKETS];
+    const int lane = __lane_id();
+    if (threadIdx.x < PSL_MAX_QBUCKETS) s_cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t n = *chunks_used;
+    const int64_t n_pad = (n + kListBlock - 1) / kListBlock * kListBlock;
+    for (int64_t i = threadIdx.x; i < n_pad; i += kListBlock) {
+        const uint32_t b = i < n ? (uint32_t)tag[i] : (uint32_t)kEmpty;
+        for (int q = 0; q < n_b; ++q) {
+            const uint64_t m = __ballot(b == (uint32_t)q);
+            if (lane == 0 && m) atomicAdd(&s_cnt[q], (uint32_t)__popcll(m));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int q = 0; q < n_b; ++q) {
+            off[q] = acc;
+            cnt[q] = s_cnt[q];
+            s_cur[q] = acc;
+            acc += s_cnt[q];
+        }
+    }
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n_pad; i += kListBlock) {
+        const uint32_t b = i < n ? (uint32_t)tag[i] : (uint32_t)kEmpty;
+        for (int q = 0; q < n_b; ++q) {
+            const uint64_t m = __ballot(b == (uint32_t)q);
+            uint32_t base = 0;
+            if (lane == 0 && m) base = atomicAdd(&s_cur[q], (uint32_t)__popcll(m));
+            base = __shfl(base, 0);
+            if (b == (uint32_t)q)
+                list[base + __popcll(m & lanemask_lt())] = (int32_t)i;
+        }
+    }
+}
+
 __global__ void k_transport_init(uint32_t *words, int n_words,
-                                 uint32_t *codes, int64_t n_code_words) {
+                                 uint32_t *codes, int64_t n_code_words,
+                                 uint8_t *tags, int64_t n_tags) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
          i < n_words; i += stride)
         words[i] = 0;
-    // every slot of the secondary stream starts empty
+    // every slot of the secondary pool starts empty, every chunk untagged
     const uint32_t e4 = 0x01010101u * kEmpty;
     for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
          i < n_code_words; i += stride)
         codes[i] = e4;
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x;
+         i < n_tags; i += stride)
+        tags[i] = kEmpty;
 }
 
 __global__ void k_consume(uint32_t *counts, int n_b, psl_stats *stats) {
@@ -783,7 +875,8 @@ struct TransportWs {
                          // chunks used
     int n_words;
     SecStream sec;
-    uint32_t *tiles;
+    int32_t *list;       // pool chunks listed by bucket
+    uint32_t *list_off, *list_cnt;
     uint64_t *part;
     size_t bytes;
 };
@@ -814,7 +907,10 @@ TransportWs carve_transport(void *base, int64_t ph_cap) {
     w.sec.s.p.uid = c.take<uint64_t>(n);
     w.sec.s.p.ctr = c.take<uint32_t>(n);
     w.sec.s.code = c.take<uint8_t>(n);   // n is a multiple of 64
-    w.tiles = c.take<uint32_t>((int64_t)kMaxQ * compact_tiles(n));
+    w.sec.chunk_bucket = c.take<uint8_t>(chunks);
+    w.list = c.take<int32_t>(chunks);
+    w.list_off = c.take<uint32_t>(PSL_MAX_QBUCKETS);
+    w.list_cnt = c.take<uint32_t>(PSL_MAX_QBUCKETS);
     w.part = c.take<uint64_t>((int64_t)2 * kMaxGridBlocks * kStatWords);
     w.bytes = c.used;
     return w;
@@ -970,7 +1066,6 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     w.sec.chunk_ctr = w.words + 2 * kParts * kPartStride;
     w.sec.chunks_used = w.words + 3 * kParts * kPartStride;
     const int64_t cap_b = q->el.capacity / q->n_ebuckets;
-    QueueRegions qr{q->ph, q->el, 1 + q->n_ebuckets, cap_b, q->d_counts};
     const float *tab = static_cast<const float *>(d_tables);
     const double scale =
         acc->mode == PSL_ACC_FIXED64 ? std::ldexp(1.0, acc->frac_bits) : 1.0;
@@ -979,7 +1074,8 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     hipLaunchKernelGGL(k_transport_init, dim3(1024), dim3(256), 0, st,
                        w.words, w.n_words,
                        reinterpret_cast<uint32_t *>(w.sec.s.code),
-                       w.sec.s.p.capacity / 4);
+                       w.sec.s.p.capacity / 4, w.sec.chunk_bucket,
+                       w.sec.n_chunks);
     {
         ProfScope prof(PSL_PROF_PHOTONS, st);
         if (fixed)
@@ -993,15 +1089,14 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     }
     hipLaunchKernelGGL(k_chunks_used, dim3(1), dim3(kParts), 0, st,
                        w.sec.chunk_ctr, w.sec.n_chunks, w.sec.chunks_used);
-    ElWork ew{q->el, q->n_ebuckets, cap_b, q->d_counts, Slots{}, nullptr};
+    ElWork ew{q->el,   q->n_ebuckets, cap_b,      q->d_counts, w.sec.s,
+              w.sec.chunks_used, L.rebucket, w.list, w.list_off,
+              w.list_cnt};
     if (L.rebucket) {
         ProfScope prof(PSL_PROF_REBUCKET, st);
-        if ((s = compact_slots(w.sec.s, w.sec.s.p.capacity, w.sec.chunks_used,
-                               64, 0, qr, w.tiles, st)))
-            return s;
-    } else {
-        ew.raw = w.sec.s;
-        ew.raw_chunks = w.sec.chunks_used;
+        hipLaunchKernelGGL(k_bucket_chunks, dim3(1), dim3(kListBlock), 0, st,
+                           w.sec.chunk_bucket, w.sec.chunks_used,
+                           q->n_ebuckets, w.list, w.list_off, w.list_cnt);
     }
     {
         ProfScope prof(PSL_PROF_ELECTRONS, st);
