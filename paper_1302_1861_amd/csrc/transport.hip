@@ -16,7 +16,8 @@
 //                bucket and tags the chunks it claims (from partitioned
 //                counters) with their bucket; the attenuation and Compton
 //                tables are staged in LDS.
-//   rebucket     (optional) lists the pool's chunks by bucket (one block).
+//   rebucket     (optional) lists the pool's chunks by bucket (one block per
+//                claim partition).
 //   k_electrons  CSDA steps split at voxel faces; the energy after each
 //                piece comes from the residual-range table and its inverse
 //                in LDS; deposits into one voxel are merged before the
@@ -796,48 +797,92 @@ __global__ void k_chunks_used(const uint32_t *__restrict__ ctr,
     }
 }
 
-// Lists the pool chunks of each bucket (one block): counts by wave ballots
-// and LDS atomics, offsets by a scan over buckets, then positions.  The
-// order within a bucket is irrelevant: every electron's result depends only
-// on its own state and random stream.
-constexpr int kListBlock = 1024;
-__global__ void __launch_bounds__(kListBlock)
-k_bucket_chunks(const uint8_t *__restrict__ tag,
-                const uint32_t *__restrict__ chunks_used, int n_b,
-                int32_t *__restrict__ list, uint32_t *__restrict__ off,
-                uint32_t *__restrict__ cnt) {
-    __shared__ uint32_t s_cnt[PSL_MAX_QBUCKETS], s_cur[PSL_MAX_QBUCKETS];
+// Lists the pool chunks of each bucket.  Block p takes the chunks handed
+// out by partition p (the first min(ctr[p], size) of its range).  First
+// pass: counts per (partition, bucket).  Second pass: every block derives
+// its offsets from the whole count table (bucket-major, partition-minor)
+// and places its chunks with wave ballots.  The order within a bucket is
+// irrelevant: every electron's result depends only on its own state and
+// random stream.
+__device__ __forceinline__ void partition_range(int64_t n_chunks, int p,
+                                                const uint32_t *ctr,
+                                                int64_t &a, int64_t &b) {
+    const int64_t len = (n_chunks + kParts - 1) / kParts;
+    a = (int64_t)p * len;
+    const int64_t e = a + len < n_chunks ? a + len : n_chunks;
+    b = a;
+    if (a < e) b = a + min((int64_t)ctr[p * kPartStride], e - a);
+}
+
+__global__ void __launch_bounds__(256)
+k_bucket_count(const uint8_t *__restrict__ tag, const uint32_t *ctr,
+               int64_t n_chunks, int n_b, uint32_t *__restrict__ pcnt) {
+    __shared__ uint32_t s_cnt[PSL_MAX_QBUCKETS];
     const int lane = __lane_id();
     if (threadIdx.x < PSL_MAX_QBUCKETS) s_cnt[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t n = *chunks_used;
-    const int64_t n_pad = (n + kListBlock - 1) / kListBlock * kListBlock;
-    for (int64_t i = threadIdx.x; i < n_pad; i += kListBlock) {
-        const uint32_t b = i < n ? (uint32_t)tag[i] : (uint32_t)kEmpty;
+    int64_t a, b;
+    partition_range(n_chunks, blockIdx.x, ctr, a, b);
+    for (int64_t i0 = a; i0 < b; i0 += 256) {
+        const int64_t i = i0 + threadIdx.x;
+        const uint32_t t = i < b ? (uint32_t)tag[i] : (uint32_t)kEmpty;
         for (int q = 0; q < n_b; ++q) {
-            const uint64_t m = __ballot(b == (uint32_t)q);
+            const uint64_t m = __ballot(t == (uint32_t)q);
             if (lane == 0 && m) atomicAdd(&s_cnt[q], (uint32_t)__popcll(m));
         }
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t acc = 0;
-        for (int q = 0; q < n_b; ++q) {
-            off[q] = acc;
-            cnt[q] = s_cnt[q];
-            s_cur[q] = acc;
-            acc += s_cnt[q];
+    if (threadIdx.x < PSL_MAX_QBUCKETS)
+        pcnt[blockIdx.x * PSL_MAX_QBUCKETS + threadIdx.x] = s_cnt[threadIdx.x];
+}
+
+__global__ void __launch_bounds__(256)
+k_bucket_list(const uint8_t *__restrict__ tag, const uint32_t *ctr,
+              int64_t n_chunks, int n_b,
+              const uint32_t *__restrict__ pcnt, int32_t *__restrict__ list,
+              uint32_t *__restrict__ off, uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t s_cur[PSL_MAX_QBUCKETS];
+    __shared__ uint32_t s_p[kParts * PSL_MAX_QBUCKETS];
+    const int lane = __lane_id();
+    const int p = blockIdx.x;
+    for (int i = threadIdx.x; i < kParts * PSL_MAX_QBUCKETS; i += 256)
+        s_p[i] = pcnt[i];
+    __syncthreads();
+    if (threadIdx.x < PSL_MAX_QBUCKETS) {
+        const int q = threadIdx.x;
+        uint32_t before = 0, total_q = 0;   // earlier buckets; bucket q
+        for (int pp = 0; pp < kParts; ++pp)
+            for (int qq = 0; qq < n_b; ++qq) {
+                const uint32_t c = s_p[pp * PSL_MAX_QBUCKETS + qq];
+                if (qq < q) before += c;
+                if (qq == q) {
+                    total_q += c;
+                    if (pp < p) before += c;
+                }
+            }
+        s_cur[q] = before;
+        if (p == 0 && q < n_b) {
+            cnt[q] = total_q;
+            uint32_t o = 0;
+            for (int pp = 0; pp < kParts; ++pp)
+                for (int qq = 0; qq < q; ++qq)
+                    o += s_p[pp * PSL_MAX_QBUCKETS + qq];
+            off[q] = o;
         }
     }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n_pad; i += kListBlock) {
-        const uint32_t b = i < n ? (uint32_t)tag[i] : (uint32_t)kEmpty;
+    int64_t a, b;
+    partition_range(n_chunks, p, ctr, a, b);
+    for (int64_t i0 = a; i0 < b; i0 += 256) {
+        const int64_t i = i0 + threadIdx.x;
+        const uint32_t t = i < b ? (uint32_t)tag[i] : (uint32_t)kEmpty;
         for (int q = 0; q < n_b; ++q) {
-            const uint64_t m = __ballot(b == (uint32_t)q);
+            const uint64_t m = __ballot(t == (uint32_t)q);
             uint32_t base = 0;
-            if (lane == 0 && m) base = atomicAdd(&s_cur[q], (uint32_t)__popcll(m));
+            if (lane == 0 && m)
+                base = atomicAdd(&s_cur[q], (uint32_t)__popcll(m));
             base = __shfl(base, 0);
-            if (b == (uint32_t)q)
+            if (t == (uint32_t)q)
                 list[base + __popcll(m & lanemask_lt())] = (int32_t)i;
         }
     }
@@ -877,6 +922,7 @@ struct TransportWs {
     SecStream sec;
     int32_t *list;       // pool chunks listed by bucket
     uint32_t *list_off, *list_cnt;
+    uint32_t *list_pcnt; // chunks per (partition, bucket)
     uint64_t *part;
     size_t bytes;
 };
@@ -911,6 +957,7 @@ TransportWs carve_transport(void *base, int64_t ph_cap) {
     w.list = c.take<int32_t>(chunks);
     w.list_off = c.take<uint32_t>(PSL_MAX_QBUCKETS);
     w.list_cnt = c.take<uint32_t>(PSL_MAX_QBUCKETS);
+    w.list_pcnt = c.take<uint32_t>((int64_t)kParts * PSL_MAX_QBUCKETS);
     w.part = c.take<uint64_t>((int64_t)2 * kMaxGridBlocks * kStatWords);
     w.bytes = c.used;
     return w;
@@ -1094,9 +1141,13 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
               w.list_cnt};
     if (L.rebucket) {
         ProfScope prof(PSL_PROF_REBUCKET, st);
-        hipLaunchKernelGGL(k_bucket_chunks, dim3(1), dim3(kListBlock), 0, st,
-                           w.sec.chunk_bucket, w.sec.chunks_used,
-                           q->n_ebuckets, w.list, w.list_off, w.list_cnt);
+        hipLaunchKernelGGL(k_bucket_count, dim3(kParts), dim3(256), 0, st,
+                           w.sec.chunk_bucket, w.sec.chunk_ctr,
+                           w.sec.n_chunks, q->n_ebuckets, w.list_pcnt);
+        hipLaunchKernelGGL(k_bucket_list, dim3(kParts), dim3(256), 0, st,
+                           w.sec.chunk_bucket, w.sec.chunk_ctr,
+                           w.sec.n_chunks, q->n_ebuckets, w.list_pcnt, w.list,
+                           w.list_off, w.list_cnt);
     }
     {
         ProfScope prof(PSL_PROF_ELECTRONS, st);
