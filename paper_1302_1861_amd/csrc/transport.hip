@@ -669,17 +669,22 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
         float tm = 0.0f;
         const float T0 = T;
         if (alive) {
+            // direction constants of the step: reciprocals, the side of the
+            // voxel whose face comes next, the index step across it
+            const float iu = u != 0.0f ? 1.0f / u : 0.0f;
+            const float iv = v != 0.0f ? 1.0f / v : 0.0f;
+            const float iw = w != 0.0f ? 1.0f / w : 0.0f;
+            const int fu = u > 0.0f, fv = v > 0.0f, fw = w > 0.0f;
+            const int su = u > 0.0f ? 1 : -1, sv = v > 0.0f ? 1 : -1,
+                      sw = w > 0.0f ? 1 : -1;
             float rem = Y.step;
             while (rem > 0.0f) {
-                const float sx = u > 0.0f ? (P.x0 + (ix + 1) * P.dx - x) / u
-                               : u < 0.0f ? (P.x0 + ix * P.dx - x) / u
-                                          : INFINITY;
-                const float sy = v > 0.0f ? (P.y0 + (iy + 1) * P.dy - y) / v
-                               : v < 0.0f ? (P.y0 + iy * P.dy - y) / v
-                                          : INFINITY;
-                const float sz = w > 0.0f ? (P.z0 + (iz + 1) * P.dz - z) / w
-                               : w < 0.0f ? (P.z0 + iz * P.dz - z) / w
-                                          : INFINITY;
+                const float sx = u != 0.0f
+                    ? (P.x0 + (float)(ix + fu) * P.dx - x) * iu : INFINITY;
+                const float sy = v != 0.0f
+                    ? (P.y0 + (float)(iy + fv) * P.dy - y) * iv : INFINITY;
+                const float sz = w != 0.0f
+                    ? (P.z0 + (float)(iz + fw) * P.dz - z) * iw : INFINITY;
                 int axis = 0;
                 float sb = sx;
                 if (sy < sb) { sb = sy; axis = 1; }
@@ -704,18 +709,12 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 x += seg * u; y += seg * v; z += seg * w;
                 rem -= seg;
                 if (seg == sb) {
-                    bool in;
-                    if (axis == 0) {
-                        ix += u > 0.0f ? 1 : -1;
-                        in = (unsigned)ix < (unsigned)P.nx;
-                    } else if (axis == 1) {
-                        iy += v > 0.0f ? 1 : -1;
-                        in = (unsigned)iy < (unsigned)P.ny;
-                    } else {
-                        iz += w > 0.0f ? 1 : -1;
-                        in = (unsigned)iz < (unsigned)P.nz;
-                    }
-                    if (!in) {
+                    ix += axis == 0 ? su : 0;
+                    iy += axis == 1 ? sv : 0;
+                    iz += axis == 2 ? sw : 0;
+                    if (!((unsigned)ix < (unsigned)P.nx &&
+                          (unsigned)iy < (unsigned)P.ny &&
+                          (unsigned)iz < (unsigned)P.nz)) {
                         e_esc += (double)T * wt;
                         T = 0.0f;
                         done = true;
