@@ -81,40 +81,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
-// Wave-aggregated reservation of `want` (0 or 1) slots in one of several
-// counters: lanes choosing the same counter share one atomic.  Returns the
-// slot index for lanes with want != 0.  Must be reached by all lanes that
-// may want a slot (divergent lanes simply do not take part).
-__device__ __forceinline__ uint32_t wave_reserve(uint32_t *counters, int which,
-                                                 bool want) {
-    uint64_t pending = __ballot(want);
-    uint32_t slot = 0;
-    while (pending) {
-        int leader = __ffsll((unsigned long long)pending) - 1;
-        int w = __shfl(which, leader);
-        uint64_t grp = __ballot(want && which == w) & pending;
-        uint32_t base = 0;
-        if ((int)__lane_id() == leader)
-            base = atomicAdd(&counters[w], (uint32_t)__popcll(grp));
-        base = __shfl(base, leader);
-        if (want && which == w)
-            slot = base + (uint32_t)__popcll(grp & lanemask_lt());
-        pending &= ~grp;
-    }
-    return slot;
-}
-
-// Wave sum then one atomic (for statistics).
-__device__ __forceinline__ void wave_add_u64(uint64_t *dst, uint64_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (__lane_id() == 0 && v) atomicAdd((unsigned long long *)dst,
-                                         (unsigned long long)v);
-}
-__device__ __forceinline__ void wave_add_f64(double *dst, double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if (__lane_id() == 0 && v != 0.0) unsafeAtomicAdd(dst, v);
-}
-
 // --------------------------------------------------------------- Philox --
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
 struct u32x4 { uint32_t x, y, z, w; };
@@ -253,23 +219,10 @@ psl_status stats_reduce(const uint64_t *part, int n_blocks, psl_stats *out,
                         hipStream_t st);
 
 // --------------------------------------------------- work distribution ----
-// Chunks of 64 items are claimed from kParts counters on separate cache
-// lines; a wave starts at its own partition and moves on when it is empty.
+// Work items are claimed from kParts counters on separate cache lines, each
+// owning a contiguous partition of the items; a wave starts at its own
+// partition and moves on when it is drained.
 constexpr int kParts = 64;
 constexpr int kPartStride = 32;   // uint32 per counter (128 bytes)
-
-__device__ __forceinline__ int64_t claim_chunk(uint32_t *ctr, int64_t n_chunks,
-                                               int &part, int &tried) {
-    while (tried < kParts) {
-        uint32_t k = 0;
-        if (__lane_id() == 0) k = atomicAdd(&ctr[part * kPartStride], 1u);
-        k = __shfl(k, 0);
-        int64_t chunk = part + (int64_t)k * kParts;
-        if (chunk < n_chunks) return chunk;
-        part = (part + 1) % kParts;
-        ++tried;
-    }
-    return -1;
-}
 
 }  // namespace psl

@@ -52,9 +52,9 @@ constexpr int kMaxCout = 128;
 // ------------------------------------------------------------ conv 3x3x3 --
 // y[v][co] = epilogue(sum_{o,ci} x[v + o][ci] W[co][o*Cin + ci]),
 // W rows padded to Kp = roundup(27 Cin, 32) with zeros.  A wave computes MT
-// tiles of 16 consecutive voxels x 16 NB output channels, so every weight
-// fragment it loads feeds MT matrix instructions and every input fragment
-// NB of them.
+// tiles of 16 consecutive voxels x 16 NB output channels (channel blocks
+// blockIdx.y NB .. blockIdx.y NB + NB - 1), so every weight fragment it
+// loads feeds MT matrix instructions and every input fragment NB of them.
 template <int NB, int MT>   // output channel blocks of 16, voxel tiles of 16
 __global__ void __launch_bounds__(256)
 k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
@@ -85,6 +85,7 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
 #pragma unroll
         for (int b = 0; b < NB; ++b) acc[t][b] = f32x4{0, 0, 0, 0};
     const int kq = 8 * (lane >> 4);
+    const int cb0 = blockIdx.y * NB;   // first channel block of the wave
     for (int k0 = 0; k0 < Kp; k0 += 32) {
         const int k = k0 + kq;
         const int o = k / Cin, ci = k - o * Cin;
@@ -106,7 +107,7 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
         }
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int co = b * 16 + (lane & 15);
+            const int co = (cb0 + b) * 16 + (lane & 15);
             const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
                 W + (int64_t)co * Kp + k);
 #pragma unroll
@@ -121,7 +122,7 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
     for (int t = 0; t < MT; ++t)
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int co = b * 16 + (lane & 15);
+            const int co = (cb0 + b) * 16 + (lane & 15);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t vv = tile0 + 16 * t + 4 * (lane >> 4) + r;
@@ -326,26 +327,30 @@ __global__ void k_pool_back(const bf16_t *__restrict__ dy, Vol V, int C,
 
 // out = concat(nearest-upsampled a [coarse, Ca], b [fine, Cb]) on the fine
 // grid V
+// One thread per voxel and 8-channel group (16 bytes); Ca, Cb multiples
+// of 8.
 __global__ void k_up_concat(const bf16_t *__restrict__ a, int Ca,
                             const bf16_t *__restrict__ b, int Cb, Vol V,
                             bf16_t *__restrict__ out) {
-    const int C = Ca + Cb;
+    const int G = (Ca + Cb) / 8;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= V.voxels() * C) return;
-    const int c = (int)(i % C);
-    const int64_t v = i / C;
-    if (c >= Ca) {
-        out[i] = b[v * Cb + (c - Ca)];
-        return;
+    if (i >= V.voxels() * G) return;
+    const int g = (int)(i % G);
+    const int64_t v = i / G;
+    uint4 val;
+    if (g * 8 >= Ca) {
+        val = *reinterpret_cast<const uint4 *>(b + v * Cb + (g * 8 - Ca));
+    } else {
+        int64_t t = v;
+        const int w = (int)(t % V.w); t /= V.w;
+        const int h = (int)(t % V.h); t /= V.h;
+        const int d = (int)(t % V.d);
+        const int64_t n = t / V.d;
+        const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
+        const int64_t u = ((n * U.d + d / 2) * U.h + h / 2) * U.w + w / 2;
+        val = *reinterpret_cast<const uint4 *>(a + u * Ca + g * 8);
     }
-    int64_t t = v;
-    const int w = (int)(t % V.w); t /= V.w;
-    const int h = (int)(t % V.h); t /= V.h;
-    const int d = (int)(t % V.d);
-    const int64_t n = t / V.d;
-    const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
-    const int64_t u = ((n * U.d + d / 2) * U.h + h / 2) * U.w + w / 2;
-    out[i] = a[u * Ca + c];
+    *reinterpret_cast<uint4 *>(out + v * (Ca + Cb) + g * 8) = val;
 }
 
 // split the gradient of concat: the up-sampling part summed over the 8
@@ -435,17 +440,18 @@ __global__ void k_fill_u32(unsigned int *p, int64_t n, unsigned int v) {
 }
 
 // input tensor: channels (dose * scale, density, 0 ...)
+// One thread per voxel: its 16 channels as two 16-byte stores.
 __global__ void k_pack_input(const float *__restrict__ dose,
                              const float *__restrict__ rho, int64_t nvox,
                              int64_t per_sample, const float *__restrict__ scale,
                              bf16_t *__restrict__ x) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nvox * kInC) return;
-    const int c = (int)(i % kInC);
-    const int64_t v = i / kInC;
-    float val = c == 0 ? dose[v] * scale[v / per_sample]
-                       : (c == 1 ? rho[v] : 0.0f);
-    x[i] = f2bf(val);
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    const uint32_t d = f2bf(dose[v] * scale[v / per_sample]);
+    const uint32_t r = f2bf(rho[v]);
+    uint4 *o = reinterpret_cast<uint4 *>(x + v * kInC);
+    o[0] = make_uint4(d | (r << 16), 0u, 0u, 0u);
+    o[1] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // out[v] = dose[v] * scale + sum_c f[v][c] wh[c] + bh  (normalised units)
@@ -457,7 +463,17 @@ __global__ void k_head(const bf16_t *__restrict__ f, int C,
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= nvox) return;
     float s = bh[0];
-    for (int c = 0; c < C; ++c) s += bf2f(f[v * C + c]) * wh[c];
+    // 16-byte loads; bf16 halves split by shifts
+    const uint4 *fv = reinterpret_cast<const uint4 *>(f + v * C);
+    for (int g = 0; g < C / 8; ++g) {
+        const uint4 q = fv[g];
+        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            s += __uint_as_float(w4[m] << 16) * wh[8 * g + 2 * m];
+            s += __uint_as_float(w4[m] & 0xffff0000u) * wh[8 * g + 2 * m + 1];
+        }
+    }
     out[v] = dose[v] * scale[v / per_sample] + s;
 }
 
@@ -679,27 +695,49 @@ template <int NB, int MT>
 void launch_conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                  const float *bias, int relu, const bf16_t *mask, int mask_c,
                  bf16_t *y, int cout, hipStream_t st) {
-    hipLaunchKernelGGL((k_conv3<NB, MT>), dim3(nblk(V.voxels(), 64 * MT)),
+    hipLaunchKernelGGL((k_conv3<NB, MT>),
+                       dim3(nblk(V.voxels(), 64 * MT),
+                            (unsigned)(cout / (16 * NB))),
                        dim3(256), 0, st, x, V, cin, W, kp, bias, relu, mask,
                        mask_c, y, cout);
 }
 
-// Voxel tiles per wave: enough reuse of each weight fragment while the
-// accumulators (4 MT NB registers) stay at 64 or fewer.
+// Tile shape per layer: the most output channels per wave (reuse of each
+// input fragment) that still gives kConvWaves waves, with voxel tiles per
+// wave such that the accumulators (4 MT NB registers) stay at 64 or fewer.
+// Small volumes (the coarse levels) thus split the output channels across
+// waves instead of leaving most of the chip idle.
+constexpr int64_t kConvWaves = 2048;
+
 psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                 const float *bias, int relu, const bf16_t *mask, bf16_t *y,
                 int cout, hipStream_t st) {
-    switch (cout / 16) {
-    case 1: launch_conv<1, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 2: launch_conv<2, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 3: launch_conv<3, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 4: launch_conv<4, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 6: launch_conv<6, 2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 8: launch_conv<8, 2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    case 12: launch_conv<12, 1>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
-    default:
+    if (cout % 16 != 0 || cout > 16 * 12) {
         set_error("unsupported channel count %d", cout);
         return PSL_EINVAL;
+    }
+    const int nc = cout / 16;
+    const int64_t nv = V.voxels();
+    auto waves = [&](int nb, int mt) {
+        return (nv + 16 * mt - 1) / (16 * mt) * (nc / nb);
+    };
+    static const int kNB[] = {12, 8, 6, 4, 3, 2, 1};
+    int nb = 1, mt = 1;
+    for (int cand : kNB) {
+        if (nc % cand) continue;
+        const int m = cand <= 4 ? 4 : (cand <= 8 ? 2 : 1);
+        if (waves(cand, m) >= kConvWaves) { nb = cand; mt = m; break; }
+    }
+    if (nb == 1 && waves(1, 4) >= kConvWaves) mt = 4;
+    switch (nb * 8 + mt) {
+    case 12 * 8 + 1: launch_conv<12, 1>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 8 * 8 + 2: launch_conv<8, 2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 6 * 8 + 2: launch_conv<6, 2>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 4 * 8 + 4: launch_conv<4, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 3 * 8 + 4: launch_conv<3, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 2 * 8 + 4: launch_conv<2, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    case 1 * 8 + 4: launch_conv<1, 4>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
+    default: launch_conv<1, 1>(x, V, cin, W, kp, bias, relu, mask, cout, y, cout, st); break;
     }
     PSL_LAUNCHED();
     return PSL_OK;
@@ -729,7 +767,7 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
                        dim3(256), 0, c.st, dose, per, a.maxbits);
     hipLaunchKernelGGL(k_scale_from_max, dim3(nblk(V[0].n)), dim3(256), 0,
                        c.st, a.maxbits, V[0].n, a.scale);
-    hipLaunchKernelGGL(k_pack_input, dim3(nblk(V[0].voxels() * kInC)),
+    hipLaunchKernelGGL(k_pack_input, dim3(nblk(V[0].voxels())),
                        dim3(256), 0, c.st, dose, rho, V[0].voxels(), per,
                        a.scale, a.xin);
     // encoder
@@ -760,7 +798,8 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
         const int ia = (l == 2) ? D2A : (l == 1 ? D1A : D0A);
         const ConvL &la = L[ia], &lb = L[ia + 1];
         const int cf = L[2 * l + 1].cout;
-        hipLaunchKernelGGL(k_up_concat, dim3(nblk(V[l].voxels() * (cc + cf))),
+        hipLaunchKernelGGL(k_up_concat,
+                           dim3(nblk(V[l].voxels() * ((cc + cf) / 8))),
                            dim3(256), 0, c.st, coarse, cc, eb[l], cf, V[l],
                            cats[l]);
         if ((s = conv(cats[l], V[l], la.cin, W(ia), la.kp, B(ia), 1, nullptr,
