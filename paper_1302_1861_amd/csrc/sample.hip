@@ -181,30 +181,28 @@ __global__ void k_cursor(const int64_t *__restrict__ N, int n_fields,
 constexpr uint32_t kSourceElectronCtr = 0xFFFFFFFFu;
 constexpr int kSampleBlock = 256;
 
-// The last index idx >= from with H[idx] <= h, given H[from] <= h and
-// H[n] > h (H non-decreasing, n + 1 entries): a galloping search, short
-// when the answer is near `from`.
+// The last index idx >= from with H[idx] <= h, given H[from] <= h < total
+// (H non-decreasing with n entries; entry n, which is not stored, is the
+// total): a galloping search, short when the answer is near `from`.
 __device__ __forceinline__ int64_t range_at(const int64_t *__restrict__ H,
-                                            int64_t n, int64_t from,
-                                            int64_t h) {
-    if (H[from + 1] > h) return from;
+                                            int64_t n, int64_t total,
+                                            int64_t from, int64_t h) {
+    auto at = [&](int64_t i) { return i < n ? H[i] : total; };
+    if (at(from + 1) > h) return from;
     int64_t a = from + 1, step = 1, b = a + 1;   // H[a] <= h
     while (b < n && H[b] <= h) {
         a = b;
         step *= 2;
         b = a + step;
     }
-    if (b > n) b = n;                             // H[b] > h
+    if (b > n) b = n;                             // at(b) > h
     while (b - a > 1) {
-        const int64_t mid = (a + b) >> 1;
+        const int64_t mid = (a + b) >> 1;        // a < mid < b <= n
         if (H[mid] <= h) a = mid; else b = mid;
     }
     return a;
 }
 
-// One thread per history: read the particle from its PSL, apply the jaw
-// model, the fluence weight and g_ik, rotate by the gantry and move it to
-// the phantom; write the result into slot h with its queue code.
 __global__ void __launch_bounds__(kSampleBlock)
 k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
          const FieldDev *__restrict__ fields, Geo geo,
@@ -242,8 +240,8 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
         int64_t hi = lo;
         if (hf < h_total) {
             const int64_t hl = min(hf + 63, h_total - 1);
-            lo = range_at(H, n_ranges, lo, hf);
-            hi = range_at(H, n_ranges, lo, hl);
+            lo = range_at(H, n_ranges, h_total, lo, hf);
+            hi = range_at(H, n_ranges, h_total, lo, hl);
         }
         if (h0 >= n_slots) continue;
         uint8_t code = kEmpty;
@@ -252,7 +250,9 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
             // range containing h0: last idx with H[idx] <= h0
             int64_t idx = lo;
             if (hi != lo) {
-                int64_t a0 = lo, b0 = hi + 1;   // H[a0] <= h0 < H[b0]
+                // H[a0] <= h0 < H[b0] (b0 <= n_ranges; only H[mid], mid <
+                // b0, is read)
+                int64_t a0 = lo, b0 = hi + 1;
                 while (b0 - a0 > 1) {
                     const int64_t mid = (a0 + b0) >> 1;
                     if (H[mid] <= h0) a0 = mid; else b0 = mid;

@@ -89,8 +89,11 @@ def _engine(wl, hpb, **kw):
 
 
 def _check_sample(wl, hpb, batches=(0,), iso=(0.0, 0.0, 100.0)):
+    _check_sample_engine(_engine(wl, hpb, iso=iso), wl, hpb, batches, iso)
+
+
+def _check_sample_engine(eng, wl, hpb, batches=(0,), iso=(0.0, 0.0, 100.0)):
     import torch
-    eng = _engine(wl, hpb, iso=iso)
     perm, off, _ = oracle.build_psl(wl.phsp, wl.grid)
     sps = wl.phsp.subset(perm)
     geom = oracle.geometry(wl.phantom, iso=iso, z_psl=wl.grid.z_plane)
@@ -170,6 +173,27 @@ def test_sample_imrt_plan_mu_allocation_and_rotation():
 def test_sample_ragged_history_counts(hpb):
     wl = S.workload_clinical(side=10.0, n_particles=200_000)
     _check_sample(wl, hpb, batches=(0, 1))
+
+
+@pytest.mark.parametrize("fill", [0x00, 0xFF])
+def test_sample_empty_first_range_with_dirty_workspace(fill):
+    """All-electron source (the photon PSL is empty, so the first history
+    range is empty) with the sampling workspace filled beforehand: no read
+    may depend on workspace bytes the allocation does not write."""
+    n = 1000
+    ps = phase_space_arrays(np.ones(n), np.full(n, 2.0), np.full(n, 1e-4),
+                            np.full(n, 1e-4), np.zeros(n), np.zeros(n),
+                            np.ones(n), 100.0)
+    grid = S.Grid(S.linear_edges(0.0, 2.5, 1), S.linear_edges(-1.0, 1.0, 1),
+                  S.linear_edges(-1.0, 1.0, 1), 100.0)
+    ph = S.water_phantom((3, 3, 40), 0.5, (-0.75, -0.75, 100.0))
+    wl = S.Workload("dirty-ws", ps, grid, ph,
+                    [S.Field(-1, 1, -1, 1, jaws=False)], 2 * n, 2, False,
+                    False, 0, 77)
+    import paper_1302_1861_amd as P
+    eng = P.Engine(wl, histories_per_batch=n)
+    eng.ws_sample.fill_(fill)
+    _check_sample_engine(eng, wl, n, (0, 1))
 
 
 def test_sample_full_clinical_batch():
