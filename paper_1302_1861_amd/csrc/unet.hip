@@ -136,6 +136,103 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
         }
 }
 
+// The same convolution with the input staged in LDS: a block computes a
+// brick of kBZ x kBY rows of 16 consecutive x-voxels; the zero-padded halo
+// of the brick ((kBZ+2) x (kBY+2) x 18 voxels x CIN channels) is loaded
+// once with 16-byte loads, and each wave reads its A fragments from LDS
+// (one 16-byte read per lane) instead of gathering every neighbour from
+// global memory.  Each wave computes kBZ*kBY/4 rows x 16 NB channels.
+// Requires W % 16 == 0, H % kBY == 0, D % kBZ == 0.
+constexpr int kBZ = 4, kBY = 4;
+template <int CIN, int NB>
+__global__ void __launch_bounds__(256)
+k_conv3_lds(const bf16_t *__restrict__ x, Vol V,
+            const bf16_t *__restrict__ W, int Kp,
+            const float *__restrict__ bias, int relu,
+            const bf16_t *__restrict__ mask, int mask_c,
+            bf16_t *__restrict__ y, int Cout) {
+    constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
+    constexpr int HVOX = HZ * HY * HX;
+    constexpr int G = CIN / 8;                 // 16-byte groups per voxel
+    constexpr int ROWS = kBZ * kBY / 4;        // rows (tiles) per wave
+    __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * CIN];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    // brick coordinates
+    const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
+    int64_t b = blockIdx.x;
+    const int bx = (int)(b % nxb); b /= nxb;
+    const int by = (int)(b % nyb); b /= nyb;
+    const int bz = (int)(b % nzb);
+    const int64_t bn = b / nzb;
+    const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
+    // halo: voxel (hz, hy, hx) = input (z0 + hz - 1, y0 + hy - 1, x0 + hx - 1)
+    for (int i = threadIdx.x; i < HVOX * G; i += 256) {
+        const int g = i % G, hv = i / G;
+        const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+        const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+        uint4 val = make_uint4(0, 0, 0, 0);
+        if ((unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
+            (unsigned)xx < (unsigned)V.w)
+            val = *reinterpret_cast<const uint4 *>(
+                x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * CIN + g * 8);
+        *reinterpret_cast<uint4 *>(s_in + hv * CIN + g * 8) = val;
+    }
+    __syncthreads();
+    f32x4 acc[ROWS][NB];
+#pragma unroll
+    for (int t = 0; t < ROWS; ++t)
+#pragma unroll
+        for (int c = 0; c < NB; ++c) acc[t][c] = f32x4{0, 0, 0, 0};
+    const int kq = 8 * (lane >> 4);
+    const int vx = lane & 15;
+    for (int k0 = 0; k0 < Kp; k0 += 32) {
+        const int k = k0 + kq;
+        const int o = k / CIN, ci = k - o * CIN;
+        const bool ok = o < 27;
+        const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;   // halo offsets
+        bf16x8 wv[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            wv[c] = *reinterpret_cast<const bf16x8 *>(
+                W + (int64_t)(c * 16 + vx) * Kp + k);
+#pragma unroll
+        for (int t = 0; t < ROWS; ++t) {
+            const int row = wid * ROWS + t;        // row of the brick
+            const int rz = row / kBY, ry = row % kBY;
+            bf16x8 a = bf16x8{};
+            if (ok)
+                a = *reinterpret_cast<const bf16x8 *>(
+                    s_in + (((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)) *
+                               CIN + ci);
+#pragma unroll
+            for (int c = 0; c < NB; ++c)
+                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a, wv[c], acc[t][c], 0, 0, 0);
+        }
+    }
+    // acc[t][c][r]: voxel (row, x = 4 (lane/16) + r), channel 16 c + lane%16
+#pragma unroll
+    for (int t = 0; t < ROWS; ++t) {
+        const int row = wid * ROWS + t;
+        const int rz = row / kBY, ry = row % kBY;
+        const int64_t vrow =
+            ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            const int co = c * 16 + (lane & 15);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t vv = vrow + 4 * (lane >> 4) + r;
+                float val = acc[t][c][r] + (bias ? bias[co] : 0.0f);
+                if (relu) val = fmaxf(val, 0.0f);
+                if (mask && !(bf2f(mask[vv * mask_c + co]) > 0.0f))
+                    val = 0.0f;
+                y[vv * Cout + co] = f2bf(val);
+            }
+        }
+    }
+}
+
 // W'[ci][o'][co] = W[co][26 - o'][ci]: the weights of the transposed
 // convolution (data gradient), padded to Kp2 = roundup(27 Cout, 32).
 __global__ void k_flip_weights(const bf16_t *__restrict__ W, int Cin,
@@ -718,6 +815,27 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
     }
     const int nc = cout / 16;
     const int64_t nv = V.voxels();
+    // LDS-staged bricks for the large volumes with few channels
+    if ((cout == 16 || cout == 32) && (cin == 16 || cin == 32 || cin == 48) &&
+        V.w % 16 == 0 && V.h % kBY == 0 && V.d % kBZ == 0 &&
+        nv / (16 * kBY * kBZ) >= 128) {
+        const unsigned blocks = (unsigned)(nv / (16 * kBY * kBZ));
+#define PSL_CONV_LDS(CI, NBV)                                                 \
+    hipLaunchKernelGGL((k_conv3_lds<CI, NBV>), dim3(blocks), dim3(256), 0,   \
+                       st, x, V, W, kp, bias, relu, mask, cout, y, cout)
+        if (cout == 16) {
+            if (cin == 16) PSL_CONV_LDS(16, 1);
+            else if (cin == 32) PSL_CONV_LDS(32, 1);
+            else PSL_CONV_LDS(48, 1);
+        } else {
+            if (cin == 16) PSL_CONV_LDS(16, 2);
+            else if (cin == 32) PSL_CONV_LDS(32, 2);
+            else PSL_CONV_LDS(48, 2);
+        }
+#undef PSL_CONV_LDS
+        PSL_LAUNCHED();
+        return PSL_OK;
+    }
     auto waves = [&](int nb, int mt) {
         return (nv + 16 * mt - 1) / (16 * mt) * (nc / nb);
     };

@@ -46,9 +46,12 @@ def _setup(n=2, size=16, seed=5):
     return net, ref, dose, rho, tgt, T
 
 
-def test_forward_matches_reference():
+# 16^3 runs the direct-gather convolution at every level; at 32^3 (n = 2)
+# the finest level runs the LDS-staged brick kernel
+@pytest.mark.parametrize("size", [16, 32])
+def test_forward_matches_reference(size):
     import torch
-    net, ref, dose, rho, tgt, T = _setup()
+    net, ref, dose, rho, tgt, T = _setup(size=size)
     out = net.forward(T(dose), T(rho))
     torch.cuda.synchronize()
     got = out.cpu().numpy().astype(np.float64)
@@ -64,9 +67,10 @@ def test_forward_matches_reference():
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-2
 
 
-def test_gradients_match_reference():
+@pytest.mark.parametrize("size", [16, 32])
+def test_gradients_match_reference(size):
     import torch
-    net, ref, dose, rho, tgt, T = _setup()
+    net, ref, dose, rho, tgt, T = _setup(size=size)
     net.loss.zero_()
     net.grads.zero_()
     net.backward(T(dose), T(rho), T(tgt))
