@@ -136,28 +136,34 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
         }
 }
 
-// The same convolution with the input staged in LDS: a block computes a
-// brick of kBZ x kBY rows of 16 consecutive x-voxels; the zero-padded halo
-// of the brick ((kBZ+2) x (kBY+2) x 18 voxels x CIN channels) is loaded
-// once with 16-byte loads, and each wave reads its A fragments from LDS
-// (one 16-byte read per lane) instead of gathering every neighbour from
-// global memory.  Each wave computes kBZ*kBY/4 rows x 16 NB channels.
-// Requires W % 16 == 0, H % kBY == 0, D % kBZ == 0.
+// The same convolution with the input staged in LDS.  A block computes a
+// brick of kBZ x kBY rows of 16 consecutive x-voxels for NB blocks of 16
+// output channels (channel group blockIdx.y); each wave owns kBZ*kBY/4 rows.
+// The zero-padded halo of the brick ((kBZ+2) x (kBY+2) x 18 voxels) is
+// staged CC input channels at a time with 16-byte loads, at a voxel pitch of
+// CC + 8 elements so that the 16 lanes reading one A fragment row hit
+// distinct LDS banks.  Within a chunk the reduction runs over slots
+// (tap o, 8-channel group g), four per matrix instruction (one per lane
+// quarter); A and B take the same slot, so any slot order sums the same
+// products.  Requires W % 16 == 0, H % kBY == 0, D % kBZ == 0 and
+// Cin % CC == 0.
 constexpr int kBZ = 4, kBY = 4;
-template <int CIN, int NB>
+template <int CC, int NB>
 __global__ void __launch_bounds__(256)
-k_conv3_lds(const bf16_t *__restrict__ x, Vol V,
-            const bf16_t *__restrict__ W, int Kp,
-            const float *__restrict__ bias, int relu,
-            const bf16_t *__restrict__ mask, int mask_c,
-            bf16_t *__restrict__ y, int Cout) {
+k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
+           const bf16_t *W, int Kp,
+           const float *__restrict__ bias, int relu,
+           const bf16_t *__restrict__ mask, bf16_t *__restrict__ y,
+           int Cout) {
     constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
     constexpr int HVOX = HZ * HY * HX;
-    constexpr int G = CIN / 8;                 // 16-byte groups per voxel
+    constexpr int G = CC / 8;                  // 16-byte groups per voxel
+    constexpr int PITCH = CC + 8;              // LDS voxel pitch (elements)
+    constexpr int SLOTS = 27 * G;
+    constexpr int STEPS = (SLOTS + 3) / 4;
     constexpr int ROWS = kBZ * kBY / 4;        // rows (tiles) per wave
-    __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * CIN];
+    __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * PITCH];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
-    // brick coordinates
     const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
     int64_t b = blockIdx.x;
     const int bx = (int)(b % nxb); b /= nxb;
@@ -165,52 +171,81 @@ k_conv3_lds(const bf16_t *__restrict__ x, Vol V,
     const int bz = (int)(b % nzb);
     const int64_t bn = b / nzb;
     const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
-    // halo: voxel (hz, hy, hx) = input (z0 + hz - 1, y0 + hy - 1, x0 + hx - 1)
-    for (int i = threadIdx.x; i < HVOX * G; i += 256) {
-        const int g = i % G, hv = i / G;
-        const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
-        const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
-        uint4 val = make_uint4(0, 0, 0, 0);
-        if ((unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
-            (unsigned)xx < (unsigned)V.w)
-            val = *reinterpret_cast<const uint4 *>(
-                x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * CIN + g * 8);
-        *reinterpret_cast<uint4 *>(s_in + hv * CIN + g * 8) = val;
-    }
-    __syncthreads();
+    const int cb0 = blockIdx.y * NB;
+    const int q = lane >> 4, vx = lane & 15;
     f32x4 acc[ROWS][NB];
 #pragma unroll
     for (int t = 0; t < ROWS; ++t)
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[t][c] = f32x4{0, 0, 0, 0};
-    const int kq = 8 * (lane >> 4);
-    const int vx = lane & 15;
-    for (int k0 = 0; k0 < Kp; k0 += 32) {
-        const int k = k0 + kq;
-        const int o = k / CIN, ci = k - o * CIN;
-        const bool ok = o < 27;
-        const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;   // halo offsets
-        bf16x8 wv[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-            wv[c] = *reinterpret_cast<const bf16x8 *>(
-                W + (int64_t)(c * 16 + vx) * Kp + k);
-#pragma unroll
-        for (int t = 0; t < ROWS; ++t) {
-            const int row = wid * ROWS + t;        // row of the brick
-            const int rz = row / kBY, ry = row % kBY;
-            bf16x8 a = bf16x8{};
-            if (ok)
-                a = *reinterpret_cast<const bf16x8 *>(
-                    s_in + (((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)) *
-                               CIN + ci);
+    for (int c0 = 0; c0 < Cin; c0 += CC) {
+        if (c0) __syncthreads();               // the last chunk's reads
+        // halo: voxel (hz, hy, hx) = input (z0+hz-1, y0+hy-1, x0+hx-1)
+        for (int i = threadIdx.x; i < HVOX * G; i += 256) {
+            const int g = i % G, hv = i / G;
+            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+            const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if ((unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
+                (unsigned)xx < (unsigned)V.w)
+                val = *reinterpret_cast<const uint4 *>(
+                    x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * Cin + c0 +
+                    g * 8);
+            *reinterpret_cast<uint4 *>(s_in + hv * PITCH + g * 8) = val;
+        }
+        __syncthreads();
+        // Weights of step j + 1 are loaded while step j computes.  Slots
+        // past the last tap (only when 27 G is not a multiple of 4) read
+        // tap 0 and get a zero A fragment, so no load is conditional.
+        auto wload = [&](int j, bf16x8 *wv) {
+            const int sl = 4 * j + q;
+            const bool ok = (SLOTS % 4 == 0) || sl < SLOTS;
+            const int o = ok ? sl / G : 0, g = ok ? sl % G : 0;
 #pragma unroll
             for (int c = 0; c < NB; ++c)
-                acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                    a, wv[c], acc[t][c], 0, 0, 0);
+                wv[c] = *reinterpret_cast<const bf16x8 *>(
+                    W + (int64_t)((cb0 + c) * 16 + vx) * Kp + o * Cin + c0 +
+                    8 * g);
+        };
+        auto step = [&](int j, const bf16x8 *wv) {
+            const int sl = 4 * j + q;
+            const bool ok = (SLOTS % 4 == 0) || sl < SLOTS;
+            const int o = ok ? sl / G : 0, g = ok ? sl % G : 0;
+            const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;
+            bf16x8 a[ROWS];
+#pragma unroll
+            for (int t = 0; t < ROWS; ++t) {
+                const int row = wid * ROWS + t;
+                const int rz = row / kBY, ry = row % kBY;
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
+                    s_in + (((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)) *
+                               PITCH + 8 * g);
+                a[t] = ok ? v : bf16x8{};
+            }
+#pragma unroll
+            for (int t = 0; t < ROWS; ++t)
+#pragma unroll
+                for (int c = 0; c < NB; ++c)
+                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[t], wv[c], acc[t][c], 0, 0, 0);
+        };
+        // two weight buffers in turn; the empty asm statements keep each
+        // prefetch ahead of the step that does not use it (the compiler
+        // otherwise moves the loads next to their use)
+        bf16x8 wa[NB], wb[NB];
+        wload(0, wa);
+#pragma unroll 1
+        for (int j = 0; j + 1 < STEPS; j += 2) {
+            wload(j + 1, wb);
+            asm volatile("" ::: "memory");
+            step(j, wa);
+            wload(j + 2 < STEPS ? j + 2 : j + 1, wa);
+            asm volatile("" ::: "memory");
+            step(j + 1, wb);
         }
+        if (STEPS % 2) step(STEPS - 1, wa);
     }
-    // acc[t][c][r]: voxel (row, x = 4 (lane/16) + r), channel 16 c + lane%16
+    // acc[t][c][r]: voxel (row, x = 4 (lane/16) + r), channel of block c
 #pragma unroll
     for (int t = 0; t < ROWS; ++t) {
         const int row = wid * ROWS + t;
@@ -219,13 +254,13 @@ k_conv3_lds(const bf16_t *__restrict__ x, Vol V,
             ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0;
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
-            const int co = c * 16 + (lane & 15);
+            const int co = (cb0 + c) * 16 + vx;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t vv = vrow + 4 * (lane >> 4) + r;
+                const int64_t vv = vrow + 4 * q + r;
                 float val = acc[t][c][r] + (bias ? bias[co] : 0.0f);
                 if (relu) val = fmaxf(val, 0.0f);
-                if (mask && !(bf2f(mask[vv * mask_c + co]) > 0.0f))
+                if (mask && !(bf2f(mask[vv * Cout + co]) > 0.0f))
                     val = 0.0f;
                 y[vv * Cout + co] = f2bf(val);
             }
@@ -815,24 +850,26 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
     }
     const int nc = cout / 16;
     const int64_t nv = V.voxels();
-    // LDS-staged bricks for the large volumes with few channels
-    if ((cout == 16 || cout == 32) && (cin == 16 || cin == 32 || cin == 48) &&
-        V.w % 16 == 0 && V.h % kBY == 0 && V.d % kBZ == 0 &&
-        nv / (16 * kBY * kBZ) >= 128) {
-        const unsigned blocks = (unsigned)(nv / (16 * kBY * kBZ));
-#define PSL_CONV_LDS(CI, NBV)                                                 \
-    hipLaunchKernelGGL((k_conv3_lds<CI, NBV>), dim3(blocks), dim3(256), 0,   \
-                       st, x, V, W, kp, bias, relu, mask, cout, y, cout)
-        if (cout == 16) {
-            if (cin == 16) PSL_CONV_LDS(16, 1);
-            else if (cin == 32) PSL_CONV_LDS(32, 1);
-            else PSL_CONV_LDS(48, 1);
+    // LDS-staged bricks wherever the volume tiles into them: two output
+    // channel blocks per wave up to 32 channels (the fine levels, where the
+    // volume gives blocks enough), one above (the coarse levels, small
+    // volumes: more blocks)
+    if (cin % 16 == 0 && V.w % 16 == 0 && V.h % kBY == 0 &&
+        V.d % kBZ == 0) {
+        const unsigned bricks = (unsigned)(nv / (16 * kBY * kBZ));
+        const int nbk = (cout == 32) ? 2 : 1;
+        const dim3 grid(bricks, (unsigned)(nc / nbk));
+#define PSL_CONV_BK(CC, NBV)                                                  \
+    hipLaunchKernelGGL((k_conv3_bk<CC, NBV>), grid, dim3(256), 0, st, x, V,  \
+                       cin, W, kp, bias, relu, mask, y, cout)
+        if (cin % 32 == 0) {
+            if (nbk == 2) PSL_CONV_BK(32, 2);
+            else PSL_CONV_BK(32, 1);
         } else {
-            if (cin == 16) PSL_CONV_LDS(16, 2);
-            else if (cin == 32) PSL_CONV_LDS(32, 2);
-            else PSL_CONV_LDS(48, 2);
+            if (nbk == 2) PSL_CONV_BK(16, 2);
+            else PSL_CONV_BK(16, 1);
         }
-#undef PSL_CONV_LDS
+#undef PSL_CONV_BK
         PSL_LAUNCHED();
         return PSL_OK;
     }

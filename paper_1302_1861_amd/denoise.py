@@ -18,13 +18,21 @@ denoised version are compared with an independent plain run of ``n_ref``
 histories, using the RMS error above the 10% isodose and the global
 gamma 2%/2mm pass rate from dose_gamma.
 
-Run as ``python -m paper_1302_1861_amd.denoise --help``.
+Run as ``python -m paper_1302_1861_amd.denoise --help``.  The weights the
+package ships (data/denoiser_128.npy) were written by
+
+    python -m paper_1302_1861_amd.denoise --draws 2000 --steps 30000 \
+        --batch 2 --crop 64 64 64 --save denoiser_128.npy
+
+at the defaults below: 128^3 phantoms at 2.5 mm, 1e7-history inputs and
+1e9-history targets.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import math
+import os
 import sys
 import time
 from typing import Dict, List
@@ -34,6 +42,8 @@ import numpy as np
 TRAIN_SEED0 = 50_000      # draw k of the training set uses TRAIN_SEED0 + k
 EVAL_SEED0 = 90_000       # held-out draws
 MC_SEED_OFFSET = 7_919    # transport seeds of input / target / reference
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data",
+                       "denoiser_128.npy")
 
 
 def _say(*a):
@@ -163,6 +173,18 @@ def _rms_rel(a, ref, sel, mx):
     return float(((a - ref)[sel].double().pow(2).mean().sqrt() / mx).item())
 
 
+def load_trained(path=WEIGHTS, device="cuda"):
+    """A Denoiser holding fp32 weights saved by main() (``--save``)."""
+    from . import Denoiser
+    net = Denoiser(device=device)
+    blob = np.load(path)
+    if blob.dtype != np.float32 or blob.shape != (net.n,):
+        raise ValueError("%s: expected float32[%d], found %s%s"
+                         % (path, net.n, blob.dtype, blob.shape))
+    net.set_params(blob)
+    return net
+
+
 def evaluate(pm: PairMaker, net, n_draws, n_in, n_ref, seed0=EVAL_SEED0,
              ref_batches=None):
     """Held-out draws: raw and denoised n_in doses against an independent
@@ -244,6 +266,102 @@ def time_to_gamma(pm: PairMaker, ph, field, ref, ladder, seed, target=0.99,
     return None, rungs
 
 
+class _Judge:
+    """Error of a dose against an independent plain reference run: the RMS
+    difference over voxels at or above 10% of the reference maximum, over
+    that maximum, with the reference's own noise (its batch sigma, same
+    region) taken out in quadrature; and the gamma 2%/2mm pass rate."""
+
+    def __init__(self, ref, sref, voxel):
+        self.ref, self.voxel = ref, voxel
+        self.mx = float(ref.max().item())
+        self.sel = ref >= 0.1 * self.mx
+        self.s_ref = float(sref[self.sel].double().pow(2).mean().sqrt()
+                           .item() / self.mx)
+
+    def __call__(self, d):
+        from . import dose_gamma
+        e = _rms_rel(d, self.ref, self.sel, self.mx)
+        g, _ = dose_gamma(self.ref, d, self.voxel)
+        return math.sqrt(max(e * e - self.s_ref ** 2, 0.0)), g
+
+
+def denoise_vs_plain(pm: PairMaker, net, draw=EVAL_SEED0 + 900,
+                     n_ref=int(1e9), target=0.01, gamma_target=0.99,
+                     in_ladder=(int(1e7), int(2e7), int(5e7)),
+                     plain_ladder=(int(1e7), int(2e7), int(5e7), int(1e8),
+                                   int(2e8))):
+    """Time to a dose accuracy, PSL + denoiser against plain MC (the same
+    PSL engine without the network), on one held-out draw.
+
+    Accuracy is judged against an independent n_ref run (_Judge): RMS error
+    <= `target` of the maximum, and gamma 2%/2mm >= `gamma_target`.  Every
+    rung is a live, timed run (sampling, transport, tally and, for the
+    denoised rungs, the network) with engines built beforehand.  For plain
+    MC the time to `target` is also measured directly: the history count
+    that the 1/sqrt(N) law predicts from the first rung is run and judged
+    (and raised again if it falls short)."""
+    import torch
+
+    def timed(n, seed, den):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        d, _, rho = pm.dose(ph, f, n, seed, batches_for(n))
+        if den:
+            d = net.denoise(d, rho)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        err, g = judge(d)
+        return {"histories": int(n), "seconds": dt, "rms_error": err,
+                "gamma": g}
+
+    ph, f = pm.phantom(draw), pm.field(draw)
+    ref, sref, _ = pm.dose(ph, f, n_ref, draw + 3 * MC_SEED_OFFSET,
+                           batches_for(n_ref))
+    judge = _Judge(ref, sref, pm.voxel)
+    for n in set(in_ladder) | set(plain_ladder):
+        pm.engine(int(n // batches_for(n)))
+    timed(in_ladder[0], draw + 5 * MC_SEED_OFFSET, True)       # warm-up
+    seed = draw + 4 * MC_SEED_OFFSET
+    den = [timed(n, seed, True) for n in in_ladder]
+    plain = [timed(n, seed, False) for n in plain_ladder]
+    direct = []
+    c, n = plain[0]["rms_error"], plain[0]["histories"]
+    for k in range(3):
+        # aim at the target itself first, then 10% past it
+        n = int(math.ceil(n * (c / target) ** 2 * (1.0 if k == 0 else 1.1)
+                          / 1e6)) * int(1e6)
+        pm.engine(int(n // batches_for(n)))
+        direct.append(timed(n, seed, False))
+        c = direct[-1]["rms_error"]
+        if c <= target:
+            break
+
+    def first(rungs, key, ok):
+        hit = [r for r in rungs if ok(r[key])]
+        return min(hit, key=lambda r: r["seconds"]) if hit else None
+
+    def ratio(a, b):
+        return a["seconds"] / b["seconds"] if a and b else None
+
+    err_ok = (lambda v: v <= target)
+    gam_ok = (lambda v: v >= gamma_target)
+    t1_plain = first(plain + direct, "rms_error", err_ok)
+    t1_den = first(den, "rms_error", err_ok)
+    g_plain = first(plain + direct, "gamma", gam_ok)
+    g_den = first(den, "gamma", gam_ok)
+    return {"draw": draw, "voxel_cm": pm.voxel, "shape": list(pm.shape),
+            "reference_histories": int(n_ref),
+            "reference_noise": judge.s_ref,
+            "criterion": {"rms_error_of_max": target,
+                          "gamma_2pct_2mm": gamma_target},
+            "time_to_error": {"plain": t1_plain, "psl_denoise": t1_den,
+                              "speedup": ratio(t1_plain, t1_den)},
+            "time_to_gamma": {"plain": g_plain, "psl_denoise": g_den,
+                              "speedup": ratio(g_plain, g_den)},
+            "rungs_denoised": den, "rungs_plain": plain + direct}
+
+
 def compare_time_to_gamma(pm: PairMaker, pm_plain: PairMaker, net, n_draws,
                           n_in, n_ref, ladder, seed0=EVAL_SEED0 + 500):
     """Time to gamma 2%/2mm >= 99% against an independent n_ref plain run:
@@ -282,7 +400,7 @@ def main(argv=None):
     ap.add_argument("--voxel", type=float, default=0.25)
     ap.add_argument("--draws", type=int, default=2000)
     ap.add_argument("--n-in", type=float, default=1e7)
-    ap.add_argument("--n-tgt", type=float, default=1e8)
+    ap.add_argument("--n-tgt", type=float, default=1e9)
     ap.add_argument("--n-ref", type=float, default=1e9)
     ap.add_argument("--eval-draws", type=int, default=8)
     ap.add_argument("--steps", type=int, default=3000)
@@ -312,6 +430,9 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     del X, R, T
+    if a.save:
+        np.save(a.save, net.params.cpu().numpy())
+        _say("saved", a.save)
     recs, mean = evaluate(pm, net, a.eval_draws, int(a.n_in), int(a.n_ref))
     ttg = []
     if a.gamma_draws:
@@ -331,8 +452,6 @@ def main(argv=None):
     if a.out:
         with open(a.out, "w") as f:
             json.dump(rep, f, indent=1)
-    if a.save:
-        np.save(a.save, net.params.cpu().numpy())
     return rep
 
 

@@ -46,12 +46,15 @@ def _setup(n=2, size=16, seed=5):
     return net, ref, dose, rho, tgt, T
 
 
-# 16^3 runs the direct-gather convolution at every level; at 32^3 (n = 2)
-# the finest level runs the LDS-staged brick kernel
-@pytest.mark.parametrize("size", [16, 32])
-def test_forward_matches_reference(size):
+# The LDS-staged brick kernel runs on every level whose volume tiles into
+# 16 x 4 x 4 bricks, the direct-gather kernel elsewhere: 16^3 runs both,
+# 32^3 adds the 32-channel level on bricks (two channel blocks per wave,
+# 32-channel staging), 64^3 (one volume) the 64-channel level (one block
+# per wave, several 32-channel stages).
+@pytest.mark.parametrize("size,n", [(16, 2), (32, 2), (64, 1)])
+def test_forward_matches_reference(size, n):
     import torch
-    net, ref, dose, rho, tgt, T = _setup(size=size)
+    net, ref, dose, rho, tgt, T = _setup(n=n, size=size)
     out = net.forward(T(dose), T(rho))
     torch.cuda.synchronize()
     got = out.cpu().numpy().astype(np.float64)
