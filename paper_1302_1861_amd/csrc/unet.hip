@@ -397,25 +397,224 @@ k_conv3_wgrad(const bf16_t *__restrict__ x, Vol V, int Cin,
     }
 }
 
-// dbias[co] += sum_v dy[v][co]
+// The weight gradient on LDS-staged bricks.  A block runs over bricks of
+// 16 x kBY x kBZ voxels (grid-stride over blockIdx.x) for one chunk of 16
+// input channels (blockIdx.y) and 16 MTP output channels (blockIdx.z).  Per
+// brick, dy is staged transposed (channel rows of the brick's 256 voxels)
+// and x likewise, one x-shift dx at a time ((kBZ+2) x (kBY+2) rows of 16
+// voxels, zero outside the volume), so that the 8 consecutive voxels of an
+// MFMA operand are one aligned 16-byte LDS read for every offset.  The
+// transposes pair two channels per 32-bit load.  The reduction dimension
+// of the matrix instruction is the voxel: K step s covers brick rows 2s and
+// 2s + 1.  Wave w accumulates all 27 offsets of output tile w % MTP over
+// the K steps congruent to w / MTP; the waves of a tile are summed through
+// LDS at the end and the block writes its partial sums (no atomics) to
+// part[blockIdx.x][o][co][ci], which k_wgrad_reduce adds into dW in a fixed
+// order.
+constexpr int kWgDyPitch = 16 * kBY * kBZ + 8;          // 264
+constexpr int kWgXRows = (kBZ + 2) * (kBY + 2);          // 36
+constexpr int kWgXPitch = kWgXRows * 16 + 8;             // 584
+constexpr int64_t kWgPartFloats = int64_t(8) << 20;      // 32 MB
+__device__ __forceinline__ void put_pair_rows(bf16_t *row0, bf16_t *row1,
+                                              const uint32_t p[8]) {
+    uint4 lo, hi;
+    lo.x = (p[0] & 0xffffu) | (p[1] << 16);
+    lo.y = (p[2] & 0xffffu) | (p[3] << 16);
+    lo.z = (p[4] & 0xffffu) | (p[5] << 16);
+    lo.w = (p[6] & 0xffffu) | (p[7] << 16);
+    hi.x = (p[0] >> 16) | (p[1] & 0xffff0000u);
+    hi.y = (p[2] >> 16) | (p[3] & 0xffff0000u);
+    hi.z = (p[4] >> 16) | (p[5] & 0xffff0000u);
+    hi.w = (p[6] >> 16) | (p[7] & 0xffff0000u);
+    *reinterpret_cast<uint4 *>(row0) = lo;
+    *reinterpret_cast<uint4 *>(row1) = hi;
+}
+template <int MTP>
+__global__ void __launch_bounds__(256)
+k_conv3_wgrad_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
+                 const bf16_t *__restrict__ dy, int Cout,
+                 float *__restrict__ part) {
+    constexpr int NKG = 4 / MTP;               // waves per output tile
+    constexpr int NKS = 8 / NKG;               // K steps per wave and brick
+    __shared__ __attribute__((aligned(16))) bf16_t s_dy[16 * MTP * kWgDyPitch];
+    __shared__ __attribute__((aligned(16))) bf16_t s_x[16 * kWgXPitch];
+    __shared__ __attribute__((aligned(16))) f32x4 s_red[(NKG - 1) * MTP * 64 + 1];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int tw = wid % MTP, kg = wid / MTP;
+    const int q = lane >> 4, l16 = lane & 15;
+    const int ci0 = blockIdx.y * 16, co0 = blockIdx.z * 16 * MTP;
+    const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
+    const int64_t bricks = (int64_t)V.n * nzb * nyb * nxb;
+    f32x4 acc[27];
+#pragma unroll
+    for (int o = 0; o < 27; ++o) acc[o] = f32x4{0, 0, 0, 0};
+    for (int64_t br = blockIdx.x; br < bricks; br += gridDim.x) {
+        int64_t b = br;
+        const int bx = (int)(b % nxb); b /= nxb;
+        const int by = (int)(b % nyb); b /= nyb;
+        const int bz = (int)(b % nzb);
+        const int64_t bn = b / nzb;
+        const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
+        __syncthreads();                       // the last brick's reads
+        // dy, transposed: item = (voxel octet, channel pair)
+        for (int i = threadIdx.x; i < 8 * MTP * 32; i += 256) {
+            const int cp = i % (8 * MTP), oc = i / (8 * MTP);
+            const int row = oc >> 1, xo = 8 * (oc & 1);
+            const int rz = row / kBY, ry = row % kBY;
+            const int64_t v =
+                ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0 + xo;
+            const bf16_t *src = dy + v * Cout + co0 + 2 * cp;
+            uint32_t p[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                p[j] = *reinterpret_cast<const uint32_t *>(src + j * Cout);
+            put_pair_rows(s_dy + (2 * cp) * kWgDyPitch + row * 16 + xo,
+                          s_dy + (2 * cp + 1) * kWgDyPitch + row * 16 + xo, p);
+        }
+        __syncthreads();
+        bf16x8 a[NKS];
+#pragma unroll
+        for (int m = 0; m < NKS; ++m) {
+            const int st = kg + NKG * m;
+            const int row = 2 * st + (q >> 1), xo = 8 * (q & 1);
+            a[m] = *reinterpret_cast<const bf16x8 *>(
+                s_dy + (tw * 16 + l16) * kWgDyPitch + row * 16 + xo);
+        }
+#pragma unroll
+        for (int dx = 0; dx < 3; ++dx) {
+            if (dx) __syncthreads();           // the last shift's reads
+            // x shifted by dx - 1, transposed: item = (row octet, pair)
+            for (int i = threadIdx.x; i < 8 * kWgXRows * 2; i += 256) {
+                const int cp = i % 8, rest = i / 8;
+                const int oct = rest & 1, hr = rest >> 1;
+                const int hz = hr / (kBY + 2), hy = hr % (kBY + 2);
+                const int zz = z0 + hz - 1, yy = y0 + hy - 1;
+                const int xb = x0 + 8 * oct + dx - 1;
+                uint32_t p[8];
+                const bool zy = (unsigned)zz < (unsigned)V.d &&
+                                (unsigned)yy < (unsigned)V.h;
+                const int64_t vrow = ((bn * V.d + zz) * V.h + yy) * V.w;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int xx = xb + j;
+                    p[j] = 0u;
+                    if (zy && (unsigned)xx < (unsigned)V.w)
+                        p[j] = *reinterpret_cast<const uint32_t *>(
+                            x + (vrow + xx) * Cin + ci0 + 2 * cp);
+                }
+                put_pair_rows(s_x + (2 * cp) * kWgXPitch + hr * 16 + 8 * oct,
+                              s_x + (2 * cp + 1) * kWgXPitch + hr * 16 +
+                                  8 * oct, p);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+                for (int dyo = 0; dyo < 3; ++dyo) {
+                    const int o = dz * 9 + dyo * 3 + dx;
+#pragma unroll
+                    for (int m = 0; m < NKS; ++m) {
+                        const int st = kg + NKG * m;
+                        const int row = 2 * st + (q >> 1), xo = 8 * (q & 1);
+                        const int rz = row / kBY, ry = row % kBY;
+                        const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(
+                            s_x + l16 * kWgXPitch +
+                            ((rz + dz) * (kBY + 2) + (ry + dyo)) * 16 + xo);
+                        acc[o] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[m], bv, acc[o], 0, 0, 0);
+                    }
+                }
+        }
+    }
+    // sum the waves of each tile, then write this block's partial sums:
+    // acc[o][r] is (co = 16 tw + 4 (lane/16) + r, ci = lane % 16)
+    float *dst = part + (int64_t)blockIdx.x * 27 * Cout * Cin;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        if (NKG > 1) {
+            __syncthreads();
+            if (kg > 0) s_red[((kg - 1) * MTP + tw) * 64 + lane] = acc[o];
+            __syncthreads();
+            if (kg == 0)
+                for (int g = 1; g < NKG; ++g) {
+                    const f32x4 t = s_red[((g - 1) * MTP + tw) * 64 + lane];
+                    acc[o] += t;
+                }
+        }
+        if (kg == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = co0 + tw * 16 + 4 * q + r;
+                dst[((int64_t)o * Cout + co) * Cin + ci0 + l16] = acc[o][r];
+            }
+        }
+    }
+}
+
+// dW[co][o Cin + ci] += sum over b < nb of part[b][o][co][ci].  A block
+// takes 16 entries; its 16 thread groups sum the partials b = g mod 16,
+// eight at a time into independent sums (so that eight loads are in flight),
+// and the groups are added in order: a fixed order for a given nb.
+__global__ void __launch_bounds__(256)
+k_wgrad_reduce(const float *__restrict__ part, int nb, int Cout, int Cin,
+               float *__restrict__ dW, int Kp) {
+    __shared__ float s_sum[16][17];
+    const int64_t slab = (int64_t)27 * Cout * Cin;
+    const int e = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int64_t i = (int64_t)blockIdx.x * 16 + e;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < slab) {
+        int b = g;
+        for (; b + 16 * 7 < nb; b += 16 * 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                acc[k] += part[(int64_t)(b + 16 * k) * slab + i];
+        for (; b < nb; b += 16) acc[0] += part[(int64_t)b * slab + i];
+    }
+    s_sum[g][e] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) +
+                  ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    __syncthreads();
+    if (g == 0 && i < slab) {
+        float t = 0.0f;
+        for (int k = 0; k < 16; ++k) t += s_sum[k][e];
+        const int ci = (int)(i % Cin);
+        const int co = (int)((i / Cin) % Cout);
+        const int o = (int)(i / ((int64_t)Cin * Cout));
+        dW[(int64_t)co * Kp + o * Cin + ci] += t;
+    }
+}
+
+// dbias[co] += sum_v dy[v][co].  A thread sums 8 channels (one 16-byte
+// load per voxel) over a strided set of voxels; the block adds its rows in
+// LDS and issues one atomic per channel.
 __global__ void __launch_bounds__(256)
 k_bias_grad(const bf16_t *__restrict__ dy, int64_t nvox, int C,
             float *__restrict__ db) {
-    __shared__ float s[256];
-    const int c = threadIdx.x % C;
-    const int rows = 256 / C;
-    const int r0 = threadIdx.x / C;
-    float acc = 0.0f;
-    if (threadIdx.x < rows * C)
+    __shared__ float s[256 * 8];
+    const int groups = C / 8;
+    const int rows = 256 / groups;
+    const int cg = threadIdx.x % groups, r0 = threadIdx.x / groups;
+    float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (r0 < rows)
         for (int64_t v = (int64_t)blockIdx.x * rows + r0; v < nvox;
-             v += (int64_t)gridDim.x * rows)
-            acc += bf2f(dy[v * C + c]);
-    s[threadIdx.x] = acc;
+             v += (int64_t)gridDim.x * rows) {
+            const uint4 q =
+                *reinterpret_cast<const uint4 *>(dy + v * C + cg * 8);
+            const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                acc[2 * m] += __uint_as_float(w4[m] << 16);
+                acc[2 * m + 1] += __uint_as_float(w4[m] & 0xffff0000u);
+            }
+        }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s[threadIdx.x * 8 + k] = acc[k];
     __syncthreads();
     if (threadIdx.x < C) {
+        const int c = threadIdx.x, g = c / 8, k = c % 8;
         float t = 0.0f;
-        for (int r = 0; r < rows; ++r) t += s[r * C + threadIdx.x];
-        unsafeAtomicAdd(&db[threadIdx.x], t);
+        for (int r = 0; r < rows; ++r) t += s[(r * groups + g) * 8 + k];
+        unsafeAtomicAdd(&db[c], t);
     }
 }
 
@@ -771,6 +970,7 @@ struct Acts {
     unsigned int *maxbits;
     // backward
     bf16_t *gA, *gB, *gC, *sk0, *sk1, *sk2, *wt;
+    float *wpart;         // weight-gradient partial sums per block
     size_t bytes;
 };
 
@@ -806,6 +1006,7 @@ Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
     a.scale = c.take<float>(n);
     a.maxbits = c.take<unsigned int>(n);
     a.gA = a.gB = a.gC = a.sk0 = a.sk1 = a.sk2 = a.wt = nullptr;
+    a.wpart = nullptr;
     if (train) {
         const int64_t big = std::max({v0 * (c1 + c0), v1 * (c2 + c1),
                                       v2 * (c3 + c2)});
@@ -816,6 +1017,7 @@ Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
         a.sk1 = c.take<bf16_t>(v1 * c1);
         a.sk2 = c.take<bf16_t>(v2 * c2);
         a.wt = c.take<bf16_t>((int64_t)(c3 + c2) * ((27 * c3 + 31) / 32 * 32));
+        a.wpart = c.take<float>(kWgPartFloats);
     }
     a.bytes = c.used;
     return a;
@@ -980,12 +1182,37 @@ psl_status layer_back(const Ctx &c, const Acts &a, int i, const bf16_t *x,
                       const bf16_t *dx_mask) {
     const ConvL &l = c.net.L[i];
     const int64_t nv = V.voxels();
-    // about 64 chunks per offset (27 x 64 blocks): enough blocks to fill
-    // the chip, few enough that the per-block atomics stay small
-    int64_t chunk = std::max<int64_t>(256, (nv / 64 + 31) / 32 * 32);
-    const unsigned nch = (unsigned)((nv + chunk - 1) / chunk);
-    hipLaunchKernelGGL(k_conv3_wgrad, dim3(nch, 27), dim3(256), 0, c.st, x, V,
-                       l.cin, dy, l.cout, chunk, grads + l.w_off, l.kp);
+    if (V.w % 16 == 0 && V.h % kBY == 0 && V.d % kBZ == 0 &&
+        l.cin % 16 == 0 && l.cout % 16 == 0) {
+        // bricks: partial sums per block, then an ordered reduction.  Up to
+        // about 2048 blocks in all, at most the partial buffer's worth.
+        const int64_t bricks = nv / (16 * kBY * kBZ);
+        const int nt = l.cout / 16;
+        const int mtp = nt % 2 == 0 ? 2 : 1;
+        const int64_t chunks = (int64_t)(l.cin / 16) * (nt / mtp);
+        const int64_t slab = (int64_t)27 * l.cout * l.cin;
+        const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(
+            {bricks, kWgPartFloats / slab, (2048 + chunks - 1) / chunks}));
+        const dim3 grid((unsigned)nb, (unsigned)(l.cin / 16),
+                        (unsigned)(nt / mtp));
+        if (mtp == 2)
+            hipLaunchKernelGGL(k_conv3_wgrad_bk<2>, grid, dim3(256), 0, c.st,
+                               x, V, l.cin, dy, l.cout, a.wpart);
+        else
+            hipLaunchKernelGGL(k_conv3_wgrad_bk<1>, grid, dim3(256), 0, c.st,
+                               x, V, l.cin, dy, l.cout, a.wpart);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nblk(slab, 16)), dim3(256), 0,
+                           c.st, a.wpart, (int)nb, l.cout, l.cin,
+                           grads + l.w_off, l.kp);
+    } else {
+        // about 64 chunks per offset (27 x 64 blocks): enough blocks to
+        // fill the chip, few enough that the per-block atomics stay small
+        int64_t chunk = std::max<int64_t>(256, (nv / 64 + 31) / 32 * 32);
+        const unsigned nch = (unsigned)((nv + chunk - 1) / chunk);
+        hipLaunchKernelGGL(k_conv3_wgrad, dim3(nch, 27), dim3(256), 0, c.st,
+                           x, V, l.cin, dy, l.cout, chunk, grads + l.w_off,
+                           l.kp);
+    }
     hipLaunchKernelGGL(k_bias_grad, dim3(256), dim3(256), 0, c.st, dy, nv,
                        l.cout, grads + l.b_off);
     if (dx) {
