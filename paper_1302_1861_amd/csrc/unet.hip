@@ -268,6 +268,89 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     }
 }
 
+// The first layer: of the 16 padded input channels only the first two
+// (dose, density) are non-zero, so the reduction runs over 27 offsets x 2
+// channels, padded to 64 (two matrix instructions) instead of 27 x 16.
+// Slot k holds offset k / 2, channel k % 2; a lane's 8 slots are 4 offsets
+// with both channels, i.e. 4 32-bit halo words.  16 output channels; same
+// bricks as k_conv3_bk, the halo staged as one 32-bit word per voxel.
+__global__ void __launch_bounds__(256)
+k_conv3_first(const bf16_t *__restrict__ x, Vol V, int Cin,
+              const bf16_t *__restrict__ W, int Kp,
+              const float *__restrict__ bias, bf16_t *__restrict__ y) {
+    constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
+    constexpr int HVOX = HZ * HY * HX;
+    constexpr int ROWS = kBZ * kBY / 4;
+    constexpr int C = 16, KS = 64;
+    __shared__ uint32_t s_in[HVOX];
+    __shared__ __attribute__((aligned(16))) bf16_t s_w[C * KS];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
+    int64_t b = blockIdx.x;
+    const int bx = (int)(b % nxb); b /= nxb;
+    const int by = (int)(b % nyb); b /= nyb;
+    const int bz = (int)(b % nzb);
+    const int64_t bn = b / nzb;
+    const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
+    const int q = lane >> 4, vx = lane & 15;
+    for (int i = threadIdx.x; i < C * KS; i += 256) {
+        const int co = i / KS, k = i % KS;
+        s_w[i] = k < 54 ? W[(int64_t)co * Kp + (k >> 1) * Cin + (k & 1)]
+                        : (bf16_t)0;
+    }
+    for (int i = threadIdx.x; i < HVOX; i += 256) {
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+        uint32_t val = 0u;
+        if ((unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
+            (unsigned)xx < (unsigned)V.w)
+            val = *reinterpret_cast<const uint32_t *>(
+                x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * Cin);
+        s_in[i] = val;
+    }
+    __syncthreads();
+    f32x4 acc[ROWS];
+#pragma unroll
+    for (int t = 0; t < ROWS; ++t) acc[t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+        const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
+            s_w + vx * KS + 32 * st + 8 * q);
+#pragma unroll
+        for (int t = 0; t < ROWS; ++t) {
+            const int row = wid * ROWS + t;
+            const int rz = row / kBY, ry = row % kBY;
+            uint32_t w4[4];
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+                const int o = 16 * st + 4 * q + jj;
+                const int oc = o < 27 ? o : 0;
+                const int dz = oc / 9, dy = (oc / 3) % 3, dx = oc % 3;
+                const uint32_t v =
+                    s_in[((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)];
+                w4[jj] = o < 27 ? v : 0u;
+            }
+            const bf16x8 a = __builtin_bit_cast(
+                bf16x8, make_uint4(w4[0], w4[1], w4[2], w4[3]));
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wv, acc[t],
+                                                             0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < ROWS; ++t) {
+        const int row = wid * ROWS + t;
+        const int rz = row / kBY, ry = row % kBY;
+        const int64_t vrow =
+            ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0;
+        const int co = vx;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t vv = vrow + 4 * q + r;
+            y[vv * C + co] = f2bf(fmaxf(acc[t][r] + bias[co], 0.0f));
+        }
+    }
+}
+
 // W'[ci][o'][co] = W[co][26 - o'][ci]: the weights of the transposed
 // convolution (data gradient), padded to Kp2 = roundup(27 Cout, 32).
 __global__ void k_flip_weights(const bf16_t *__restrict__ W, int Cin,
@@ -809,16 +892,19 @@ __global__ void k_head(const bf16_t *__restrict__ f, int C,
 }
 
 // loss = mean over voxels of (out - target * scale)^2; g = dL/dout; head
-// gradients; df = g wh masked by the ReLU of f
+// gradients; df = g wh masked by the ReLU of f.  Each block writes its sums
+// of the squared error, of g and of g f[c] (kLossParts values) to
+// part[blockIdx.x]; k_loss_head_sum adds them up in block order.
+constexpr int kLossParts = 18;
+constexpr int kLossBlocks = 1024;
 __global__ void __launch_bounds__(256)
 k_loss_head_back(const float *__restrict__ out, const float *__restrict__ tgt,
                  int64_t per_sample, const float *__restrict__ scale,
                  int64_t nvox, const bf16_t *__restrict__ f,
-                 const float *__restrict__ wh, float *__restrict__ dwh,
-                 float *__restrict__ dbh, bf16_t *__restrict__ df,
-                 double *__restrict__ loss) {
+                 const float *__restrict__ wh, bf16_t *__restrict__ df,
+                 float *__restrict__ part) {
     constexpr int C = 16;
-    __shared__ float s_r[256];
+    __shared__ float s_r[4][kLossParts];
     const float inv_n = 1.0f / (float)nvox;
     float l = 0.0f, gb = 0.0f;
     float gw[C];
@@ -830,32 +916,79 @@ k_loss_head_back(const float *__restrict__ out, const float *__restrict__ tgt,
         l += e * e;
         const float g = 2.0f * e * inv_n;
         gb += g;
+        // the 16 channels as two 16-byte loads and stores (bf16 halves
+        // split by shifts)
+        const uint4 *fv4 = reinterpret_cast<const uint4 *>(f + v * C);
+        uint4 *dv4 = reinterpret_cast<uint4 *>(df + v * C);
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const float fv = bf2f(f[v * C + c]);
-            gw[c] += g * fv;
-            df[v * C + c] = f2bf(fv > 0.0f ? g * wh[c] : 0.0f);
+        for (int h = 0; h < 2; ++h) {
+            const uint4 q4 = fv4[h];
+            const uint32_t w4[4] = {q4.x, q4.y, q4.z, q4.w};
+            uint32_t o4[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int c = 8 * h + 2 * m;
+                const float f0 = __uint_as_float(w4[m] << 16);
+                const float f1 = __uint_as_float(w4[m] & 0xffff0000u);
+                gw[c] += g * f0;
+                gw[c + 1] += g * f1;
+                o4[m] = (uint32_t)f2bf(f0 > 0.0f ? g * wh[c] : 0.0f) |
+                        ((uint32_t)f2bf(f1 > 0.0f ? g * wh[c + 1] : 0.0f)
+                         << 16);
+            }
+            dv4[h] = make_uint4(o4[0], o4[1], o4[2], o4[3]);
         }
     }
-    // block sums of l, gb and gw[0..15], one value at a time
-    for (int q = 0; q < C + 2; ++q) {
-        float val = q == 0 ? l : (q == 1 ? gb : gw[0]);
+    // block sums of l, gb and gw[0..15]: wave sums, then the four waves
+    float vals[kLossParts];
+    vals[0] = l;
+    vals[1] = gb;
 #pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (q == c + 2) val = gw[c];
-        s_r[threadIdx.x] = val;
-        __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if (threadIdx.x < h) s_r[threadIdx.x] += s_r[threadIdx.x + h];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            if (q == 0) unsafeAtomicAdd(loss, (double)(s_r[0] * inv_n));
-            else if (q == 1) unsafeAtomicAdd(dbh, s_r[0]);
-            else unsafeAtomicAdd(&dwh[q - 2], s_r[0]);
-        }
-        __syncthreads();
+    for (int c = 0; c < C; ++c) vals[2 + c] = gw[c];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kLossParts; ++k) {
+        float v = vals[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) s_r[wid][k] = v;
     }
+    __syncthreads();
+    if (threadIdx.x < kLossParts) {
+        const int k = threadIdx.x;
+        part[(int64_t)blockIdx.x * kLossParts + k] =
+            (s_r[0][k] + s_r[1][k]) + (s_r[2][k] + s_r[3][k]);
+    }
+}
+
+// loss += sum of the blocks' squared errors / nvox; dbh, dwh += their sums.
+// One block: thread t takes blocks t, t + 256, ...; the threads' sums are
+// then added in a fixed order (wave butterflies, then the four waves).
+__global__ void __launch_bounds__(256)
+k_loss_head_sum(const float *__restrict__ part, int nblocks, int64_t nvox,
+                double *__restrict__ loss, float *__restrict__ dbh,
+                float *__restrict__ dwh) {
+    __shared__ double s_w[4][kLossParts];
+    double t[kLossParts];
+#pragma unroll
+    for (int k = 0; k < kLossParts; ++k) t[k] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256)
+#pragma unroll
+        for (int k = 0; k < kLossParts; ++k)
+            t[k] += part[(int64_t)b * kLossParts + k];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < kLossParts; ++k) {
+        double v = t[k];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if (lane == 0) s_w[wid][k] = v;
+    }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k >= kLossParts) return;
+    const double sum = (s_w[0][k] + s_w[1][k]) + (s_w[2][k] + s_w[3][k]);
+    if (k == 0) loss[0] += sum / (double)nvox;
+    else if (k == 1) dbh[0] += (float)sum;
+    else dwh[k - 2] += (float)sum;
 }
 
 // de-normalise: y = o / scale of the sample
@@ -971,6 +1104,7 @@ struct Acts {
     // backward
     bf16_t *gA, *gB, *gC, *sk0, *sk1, *sk2, *wt;
     float *wpart;         // weight-gradient partial sums per block
+    float *lpart;         // loss and head-gradient sums per block
     size_t bytes;
 };
 
@@ -1006,7 +1140,7 @@ Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
     a.scale = c.take<float>(n);
     a.maxbits = c.take<unsigned int>(n);
     a.gA = a.gB = a.gC = a.sk0 = a.sk1 = a.sk2 = a.wt = nullptr;
-    a.wpart = nullptr;
+    a.wpart = a.lpart = nullptr;
     if (train) {
         const int64_t big = std::max({v0 * (c1 + c0), v1 * (c2 + c1),
                                       v2 * (c3 + c2)});
@@ -1018,6 +1152,7 @@ Acts carve_acts(void *base, int n, int d, int h, int w, int b, bool train) {
         a.sk2 = c.take<bf16_t>(v2 * c2);
         a.wt = c.take<bf16_t>((int64_t)(c3 + c2) * ((27 * c3 + 31) / 32 * 32));
         a.wpart = c.take<float>(kWgPartFloats);
+        a.lpart = c.take<float>((int64_t)kLossBlocks * kLossParts);
     }
     a.bytes = c.used;
     return a;
@@ -1134,8 +1269,16 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
     bf16_t *pools[3] = {a.p1, a.p2, a.p3};
     for (int l = 0; l < 4; ++l) {
         const ConvL &la = L[2 * l], &lb = L[2 * l + 1];
-        if ((s = conv(ins[l], V[l], la.cin, W(2 * l), la.kp, B(2 * l), 1,
-                      nullptr, ea[l], la.cout, c.st)))
+        if (l == 0 && la.cout == 16 && V[0].w % 16 == 0 &&
+            V[0].h % kBY == 0 && V[0].d % kBZ == 0) {
+            // the input's two real channels only
+            hipLaunchKernelGGL(k_conv3_first,
+                               dim3((unsigned)(V[0].voxels() /
+                                               (16 * kBY * kBZ))),
+                               dim3(256), 0, c.st, ins[0], V[0], la.cin,
+                               W(0), la.kp, B(0), ea[0]);
+        } else if ((s = conv(ins[l], V[l], la.cin, W(2 * l), la.kp,
+                             B(2 * l), 1, nullptr, ea[l], la.cout, c.st)))
             return s;
         if ((s = conv(ea[l], V[l], lb.cin, W(2 * l + 1), lb.kp, B(2 * l + 1),
                       1, nullptr, eb[l], lb.cout, c.st)))
@@ -1235,10 +1378,12 @@ psl_status backward(const Ctx &c, const Acts &a, const float *tgt,
     const Vol *V = a.V;
     const int64_t per = V[0].voxels() / V[0].n;
     bf16_t *g = a.gA, *g2 = a.gB, *t = a.gC;
-    hipLaunchKernelGGL(k_loss_head_back, dim3(512), dim3(256), 0, c.st, a.out,
-                       tgt, per, a.scale, V[0].voxels(), a.d0b,
-                       c.p + c.net.head_w, grads + c.net.head_w,
-                       grads + c.net.head_b, g, loss);
+    hipLaunchKernelGGL(k_loss_head_back, dim3(kLossBlocks), dim3(256), 0,
+                       c.st, a.out, tgt, per, a.scale, V[0].voxels(), a.d0b,
+                       c.p + c.net.head_w, g, a.lpart);
+    hipLaunchKernelGGL(k_loss_head_sum, dim3(1), dim3(256), 0, c.st, a.lpart,
+                       kLossBlocks, V[0].voxels(), loss, grads + c.net.head_b,
+                       grads + c.net.head_w);
     // decoder, level 0 .. 2 (gradient g of the level's output d_lb)
     bf16_t *cats[3] = {a.cat0, a.cat1, a.cat2};
     bf16_t *da[3] = {a.d0a, a.d1a, a.d2a};
