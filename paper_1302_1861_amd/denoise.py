@@ -21,8 +21,8 @@ gamma 2%/2mm pass rate from dose_gamma.
 Run as ``python -m paper_1302_1861_amd.denoise --help``.  The weights the
 package ships (data/denoiser_128.npy) were written by
 
-    python -m paper_1302_1861_amd.denoise --draws 2000 --steps 30000 \
-        --batch 2 --crop 64 64 64 --save denoiser_128.npy
+    python -m paper_1302_1861_amd.denoise --draws 2000 --steps 60000 \
+        --batch 4 --crop 64 64 64 --save denoiser_128.npy
 
 at the defaults below: 128^3 phantoms at 2.5 mm, 1e7-history inputs and
 1e9-history targets.
