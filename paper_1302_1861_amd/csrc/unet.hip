@@ -178,20 +178,32 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     for (int t = 0; t < ROWS; ++t)
 #pragma unroll
         for (int c = 0; c < NB; ++c) acc[t][c] = f32x4{0, 0, 0, 0};
+    constexpr int NIT = (HVOX * G + 255) / 256;  // halo loads per thread
     for (int c0 = 0; c0 < Cin; c0 += CC) {
         if (c0) __syncthreads();               // the last chunk's reads
-        // halo: voxel (hz, hy, hx) = input (z0+hz-1, y0+hy-1, x0+hx-1)
-        for (int i = threadIdx.x; i < HVOX * G; i += 256) {
+        // halo: voxel (hz, hy, hx) = input (z0+hz-1, y0+hy-1, x0+hx-1); all
+        // of a thread's loads are issued before its LDS stores, so their
+        // latencies overlap
+        uint4 hval[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = threadIdx.x + 256 * it;
             const int g = i % G, hv = i / G;
             const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
             const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
-            uint4 val = make_uint4(0, 0, 0, 0);
-            if ((unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
-                (unsigned)xx < (unsigned)V.w)
-                val = *reinterpret_cast<const uint4 *>(
+            hval[it] = make_uint4(0, 0, 0, 0);
+            if (i < HVOX * G && (unsigned)zz < (unsigned)V.d &&
+                (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w)
+                hval[it] = *reinterpret_cast<const uint4 *>(
                     x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * Cin + c0 +
                     g * 8);
-            *reinterpret_cast<uint4 *>(s_in + hv * PITCH + g * 8) = val;
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            if (i < HVOX * G)
+                *reinterpret_cast<uint4 *>(s_in + (i / G) * PITCH +
+                                           (i % G) * 8) = hval[it];
         }
         __syncthreads();
         // Weights of step j + 1 are loaded while step j computes.  Slots
@@ -298,15 +310,23 @@ k_conv3_first(const bf16_t *__restrict__ x, Vol V, int Cin,
         s_w[i] = k < 54 ? W[(int64_t)co * Kp + (k >> 1) * Cin + (k & 1)]
                         : (bf16_t)0;
     }
-    for (int i = threadIdx.x; i < HVOX; i += 256) {
+    constexpr int NIT = (HVOX + 255) / 256;
+    uint32_t hval[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int i = threadIdx.x + 256 * it;
         const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
         const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
-        uint32_t val = 0u;
-        if ((unsigned)zz < (unsigned)V.d && (unsigned)yy < (unsigned)V.h &&
-            (unsigned)xx < (unsigned)V.w)
-            val = *reinterpret_cast<const uint32_t *>(
+        hval[it] = 0u;
+        if (i < HVOX && (unsigned)zz < (unsigned)V.d &&
+            (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w)
+            hval[it] = *reinterpret_cast<const uint32_t *>(
                 x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * Cin);
-        s_in[i] = val;
+    }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int i = threadIdx.x + 256 * it;
+        if (i < HVOX) s_in[i] = hval[it];
     }
     __syncthreads();
     f32x4 acc[ROWS];
@@ -539,20 +559,30 @@ k_conv3_wgrad_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
         const int64_t bn = b / nzb;
         const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
         __syncthreads();                       // the last brick's reads
-        // dy, transposed: item = (voxel octet, channel pair)
-        for (int i = threadIdx.x; i < 8 * MTP * 32; i += 256) {
+        // dy, transposed: item = (voxel octet, channel pair); MTP items
+        // per thread, all loads issued before the LDS stores
+        uint32_t pd[MTP][8];
+#pragma unroll
+        for (int it = 0; it < MTP; ++it) {
+            const int i = threadIdx.x + 256 * it;
             const int cp = i % (8 * MTP), oc = i / (8 * MTP);
             const int row = oc >> 1, xo = 8 * (oc & 1);
             const int rz = row / kBY, ry = row % kBY;
             const int64_t v =
                 ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0 + xo;
             const bf16_t *src = dy + v * Cout + co0 + 2 * cp;
-            uint32_t p[8];
 #pragma unroll
             for (int j = 0; j < 8; ++j)
-                p[j] = *reinterpret_cast<const uint32_t *>(src + j * Cout);
+                pd[it][j] = *reinterpret_cast<const uint32_t *>(src + j * Cout);
+        }
+#pragma unroll
+        for (int it = 0; it < MTP; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            const int cp = i % (8 * MTP), oc = i / (8 * MTP);
+            const int row = oc >> 1, xo = 8 * (oc & 1);
             put_pair_rows(s_dy + (2 * cp) * kWgDyPitch + row * 16 + xo,
-                          s_dy + (2 * cp + 1) * kWgDyPitch + row * 16 + xo, p);
+                          s_dy + (2 * cp + 1) * kWgDyPitch + row * 16 + xo,
+                          pd[it]);
         }
         __syncthreads();
         bf16x8 a[NKS];
@@ -566,28 +596,41 @@ k_conv3_wgrad_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
 #pragma unroll
         for (int dx = 0; dx < 3; ++dx) {
             if (dx) __syncthreads();           // the last shift's reads
-            // x shifted by dx - 1, transposed: item = (row octet, pair)
-            for (int i = threadIdx.x; i < 8 * kWgXRows * 2; i += 256) {
+            // x shifted by dx - 1, transposed: item = (row octet, pair);
+            // all of a thread's loads are issued before its LDS stores
+            constexpr int NXI = 8 * kWgXRows * 2, NIT = (NXI + 255) / 256;
+            uint32_t px[NIT][8];
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int i = threadIdx.x + 256 * it;
                 const int cp = i % 8, rest = i / 8;
                 const int oct = rest & 1, hr = rest >> 1;
                 const int hz = hr / (kBY + 2), hy = hr % (kBY + 2);
                 const int zz = z0 + hz - 1, yy = y0 + hy - 1;
                 const int xb = x0 + 8 * oct + dx - 1;
-                uint32_t p[8];
-                const bool zy = (unsigned)zz < (unsigned)V.d &&
+                const bool zy = i < NXI && (unsigned)zz < (unsigned)V.d &&
                                 (unsigned)yy < (unsigned)V.h;
                 const int64_t vrow = ((bn * V.d + zz) * V.h + yy) * V.w;
 #pragma unroll
                 for (int j = 0; j < 8; ++j) {
                     const int xx = xb + j;
-                    p[j] = 0u;
+                    px[it][j] = 0u;
                     if (zy && (unsigned)xx < (unsigned)V.w)
-                        p[j] = *reinterpret_cast<const uint32_t *>(
+                        px[it][j] = *reinterpret_cast<const uint32_t *>(
                             x + (vrow + xx) * Cin + ci0 + 2 * cp);
                 }
-                put_pair_rows(s_x + (2 * cp) * kWgXPitch + hr * 16 + 8 * oct,
-                              s_x + (2 * cp + 1) * kWgXPitch + hr * 16 +
-                                  8 * oct, p);
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int i = threadIdx.x + 256 * it;
+                if (i < NXI) {
+                    const int cp = i % 8, rest = i / 8;
+                    const int oct = rest & 1, hr = rest >> 1;
+                    put_pair_rows(
+                        s_x + (2 * cp) * kWgXPitch + hr * 16 + 8 * oct,
+                        s_x + (2 * cp + 1) * kWgXPitch + hr * 16 + 8 * oct,
+                        px[it]);
+                }
             }
             __syncthreads();
 #pragma unroll

@@ -42,7 +42,7 @@ def test_shipped_weights_reduce_the_error_of_a_full_size_dose():
     1e7-history inputs) on a held-out draw outside the training and
     evaluation seeds: the denoised 1e7-history dose has at most 80% of the
     raw dose's RMS error against an independent 1e9-history run.  Seeds,
-    tally and network are deterministic, so the ratio is too (0.59 for
+    tally and network are deterministic, so the ratio is too (0.61 for
     the committed weights); the margin only absorbs kernel changes
     that reorder floating-point sums."""
     from paper_1302_1861_amd import denoise as D
