@@ -286,9 +286,15 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
 // Slot k holds offset k / 2, channel k % 2; a lane's 8 slots are 4 offsets
 // with both channels, i.e. 4 32-bit halo words.  16 output channels; same
 // bricks as k_conv3_bk, the halo staged as one 32-bit word per voxel.
+// DIRECT: the words are made here from the fp32 dose (times the sample's
+// scale) and density, rounded exactly as k_pack_input rounds them, so the
+// padded input need not be written at all (inference); otherwise they are
+// read from the padded input x.
+template <bool DIRECT>
 __global__ void __launch_bounds__(256)
-k_conv3_first(const bf16_t *__restrict__ x, Vol V, int Cin,
-              const bf16_t *__restrict__ W, int Kp,
+k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
+              const float *__restrict__ rho, const float *__restrict__ scale,
+              Vol V, int Cin, const bf16_t *__restrict__ W, int Kp,
               const float *__restrict__ bias, bf16_t *__restrict__ y) {
     constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
     constexpr int HVOX = HZ * HY * HX;
@@ -319,9 +325,14 @@ k_conv3_first(const bf16_t *__restrict__ x, Vol V, int Cin,
         const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
         hval[it] = 0u;
         if (i < HVOX && (unsigned)zz < (unsigned)V.d &&
-            (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w)
-            hval[it] = *reinterpret_cast<const uint32_t *>(
-                x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * Cin);
+            (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w) {
+            const int64_t v = ((bn * V.d + zz) * V.h + yy) * V.w + xx;
+            if (DIRECT)
+                hval[it] = (uint32_t)f2bf(dose[v] * scale[bn]) |
+                           ((uint32_t)f2bf(rho[v]) << 16);
+            else
+                hval[it] = *reinterpret_cast<const uint32_t *>(x + v * Cin);
+        }
     }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
@@ -1285,8 +1296,9 @@ struct Ctx {
     hipStream_t st;
 };
 
+// train: the backward pass follows and needs the padded input written
 psl_status forward(const Ctx &c, const Acts &a, const float *dose,
-                   const float *rho) {
+                   const float *rho, bool train) {
     psl_status s;
     const auto &L = c.net.L;
     auto W = [&](int i) { return c.pb + L[i].w_off; };
@@ -1302,9 +1314,12 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
                        dim3(256), 0, c.st, dose, per, a.maxbits);
     hipLaunchKernelGGL(k_scale_from_max, dim3(nblk(V[0].n)), dim3(256), 0,
                        c.st, a.maxbits, V[0].n, a.scale);
-    hipLaunchKernelGGL(k_pack_input, dim3(nblk(V[0].voxels())),
-                       dim3(256), 0, c.st, dose, rho, V[0].voxels(), per,
-                       a.scale, a.xin);
+    const bool first_bk = L[0].cout == 16 && V[0].w % 16 == 0 &&
+                          V[0].h % kBY == 0 && V[0].d % kBZ == 0;
+    if (train || !first_bk)
+        hipLaunchKernelGGL(k_pack_input, dim3(nblk(V[0].voxels())),
+                           dim3(256), 0, c.st, dose, rho, V[0].voxels(), per,
+                           a.scale, a.xin);
     // encoder
     bf16_t *ins[4] = {a.xin, a.p1, a.p2, a.p3};
     bf16_t *ea[4] = {a.e0a, a.e1a, a.e2a, a.e3a};
@@ -1312,14 +1327,17 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
     bf16_t *pools[3] = {a.p1, a.p2, a.p3};
     for (int l = 0; l < 4; ++l) {
         const ConvL &la = L[2 * l], &lb = L[2 * l + 1];
-        if (l == 0 && la.cout == 16 && V[0].w % 16 == 0 &&
-            V[0].h % kBY == 0 && V[0].d % kBZ == 0) {
+        if (l == 0 && first_bk) {
             // the input's two real channels only
-            hipLaunchKernelGGL(k_conv3_first,
-                               dim3((unsigned)(V[0].voxels() /
-                                               (16 * kBY * kBZ))),
-                               dim3(256), 0, c.st, ins[0], V[0], la.cin,
-                               W(0), la.kp, B(0), ea[0]);
+            const dim3 grid((unsigned)(V[0].voxels() / (16 * kBY * kBZ)));
+            if (train)
+                hipLaunchKernelGGL(k_conv3_first<false>, grid, dim3(256), 0,
+                                   c.st, ins[0], dose, rho, a.scale, V[0],
+                                   la.cin, W(0), la.kp, B(0), ea[0]);
+            else
+                hipLaunchKernelGGL(k_conv3_first<true>, grid, dim3(256), 0,
+                                   c.st, ins[0], dose, rho, a.scale, V[0],
+                                   la.cin, W(0), la.kp, B(0), ea[0]);
         } else if ((s = conv(ins[l], V[l], la.cin, W(2 * l), la.kp,
                              B(2 * l), 1, nullptr, ea[l], la.cout, c.st)))
             return s;
@@ -1546,7 +1564,7 @@ extern "C" psl_status unet_forward(const psl_unet *u, const float *d_dose,
     hipStream_t st = (hipStream_t)stream;
     Acts a = carve_acts(d_ws, n, nz, ny, nx, u->base, false);
     Ctx c{make_net(u->base), u->params, u->params_bf16, st};
-    if ((s = forward(c, a, d_dose, d_density))) return s;
+    if ((s = forward(c, a, d_dose, d_density, false))) return s;
     const int64_t nv = a.V[0].voxels();
     hipLaunchKernelGGL(k_out_scale, dim3(nblk(nv)), dim3(256), 0, st, a.out,
                        nv, nv / n, a.scale, d_out);
@@ -1574,7 +1592,7 @@ extern "C" psl_status unet_backward(const psl_unet *u, const float *d_dose,
     hipStream_t st = (hipStream_t)stream;
     Acts a = carve_acts(d_ws, n, nz, ny, nx, u->base, true);
     Ctx c{make_net(u->base), u->params, u->params_bf16, st};
-    if ((s = forward(c, a, d_dose, d_density))) return s;
+    if ((s = forward(c, a, d_dose, d_density, true))) return s;
     return backward(c, a, d_target, d_grads, d_loss);
 }
 

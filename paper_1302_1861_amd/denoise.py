@@ -99,13 +99,19 @@ class PairMaker:
         return self.S.Field(X1, X2, Y1, Y2,
                             fluence=self.S.fluence_map(seed))
 
-    def dose(self, ph, field, histories, seed, batches=10):
-        """Dose (Gy per phase-space particle) of `histories` histories in
-        `batches` batches, with its batch sigma: device float32 [nz,ny,nx]."""
-        hpb = int(histories // batches)
-        eng = self.engine(hpb)
+    def prepare(self, ph, field, histories, batches=10):
+        """The engine for `histories` histories in `batches` batches, with
+        the phantom and field loaded (host-to-device copies included)."""
+        eng = self.engine(int(histories // batches))
         eng.set_phantom(ph)
         eng.set_fields([field])
+        return eng
+
+    def run(self, eng, seed, batches=10):
+        """Sampling, transport and tally of a prepared engine: dose (Gy per
+        phase-space particle), its batch sigma and the density, device
+        float32 [nz,ny,nx]."""
+        eng.reset_tally()
         eng.set_seed(seed)
         for b in range(batches):
             eng.step(b)
@@ -113,6 +119,11 @@ class PairMaker:
         nx, ny, nz = self.shape
         return (d.view(nz, ny, nx).clone(), s.view(nz, ny, nx).clone(),
                 eng.density.view(nz, ny, nx).clone())
+
+    def dose(self, ph, field, histories, seed, batches=10):
+        """prepare() then run()."""
+        return self.run(self.prepare(ph, field, histories, batches), seed,
+                        batches)
 
 
 def make_pairs(pm: PairMaker, n_draws, n_in, n_tgt, seed0=TRAIN_SEED0,
@@ -292,35 +303,51 @@ def denoise_vs_plain(pm: PairMaker, net, draw=EVAL_SEED0 + 900,
                      plain_ladder=(int(1e7), int(2e7), int(5e7), int(1e8),
                                    int(2e8))):
     """Time to a dose accuracy, PSL + denoiser against plain MC (the same
-    PSL engine without the network), on one held-out draw.
+    PSL engine without the network), on one held-out draw.  Plain MC runs
+    at least 10 batches (its uncertainty comes from batch statistics); the
+    denoiser's input runs in at least 2 batches (the tally's minimum) of up
+    to 1e7 histories.
 
     Accuracy is judged against an independent n_ref run (_Judge): RMS error
     <= `target` of the maximum, and gamma 2%/2mm >= `gamma_target`.  Every
     rung is a live, timed run (sampling, transport, tally and, for the
-    denoised rungs, the network) with engines built beforehand.  For plain
+    denoised rungs, the network) with engines built and the phantom and
+    field loaded beforehand.  For plain
     MC the time to `target` is also measured directly: the history count
     that the 1/sqrt(N) law predicts from the first rung is run and judged
     (and raised again if it falls short)."""
     import torch
 
     def timed(n, seed, den):
+        # Plain MC states its uncertainty from batch statistics, so it runs
+        # at least 10 batches; the denoised dose has no batch sigma and runs
+        # in as few batches as the tally accepts (two) and the engine holds
+        # (at most 1e7 histories each).  The phantom and field upload is
+        # common to both sides and stays outside the clock.
+        nb = den_batches(n) if den else batches_for(n)
+        eng = pm.prepare(ph, f, n, nb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        d, _, rho = pm.dose(ph, f, n, seed, batches_for(n))
+        d, _, rho = pm.run(eng, seed, nb)
         if den:
             d = net.denoise(d, rho)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         err, g = judge(d)
-        return {"histories": int(n), "seconds": dt, "rms_error": err,
-                "gamma": g}
+        return {"histories": int(n), "batches": nb, "seconds": dt,
+                "rms_error": err, "gamma": g}
 
     ph, f = pm.phantom(draw), pm.field(draw)
     ref, sref, _ = pm.dose(ph, f, n_ref, draw + 3 * MC_SEED_OFFSET,
                            batches_for(n_ref))
     judge = _Judge(ref, sref, pm.voxel)
-    for n in set(in_ladder) | set(plain_ladder):
+    def den_batches(n):
+        return max(2, -(-int(n) // 10_000_000))
+
+    for n in plain_ladder:
         pm.engine(int(n // batches_for(n)))
+    for n in in_ladder:
+        pm.engine(int(n // den_batches(n)))
     timed(in_ladder[0], draw + 5 * MC_SEED_OFFSET, True)       # warm-up
     seed = draw + 4 * MC_SEED_OFFSET
     den = [timed(n, seed, True) for n in in_ladder]
