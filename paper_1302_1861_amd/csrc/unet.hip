@@ -1395,6 +1395,11 @@ psl_status layer_back(const Ctx &c, const Acts &a, int i, const bf16_t *x,
         const int mtp = nt % 2 == 0 ? 2 : 1;
         const int64_t chunks = (int64_t)(l.cin / 16) * (nt / mtp);
         const int64_t slab = (int64_t)27 * l.cout * l.cin;
+        if (slab > kWgPartFloats) {
+            set_error("layer %d: %lld weights exceed the partial-sum buffer",
+                      i, (long long)slab);
+            return PSL_EINVAL;
+        }
         const int64_t nb = std::max<int64_t>(1, std::min<int64_t>(
             {bricks, kWgPartFloats / slab, (2048 + chunks - 1) / chunks}));
         const dim3 grid((unsigned)nb, (unsigned)(l.cin / 16),
