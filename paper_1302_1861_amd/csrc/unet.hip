@@ -136,6 +136,78 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
         }
 }
 
+// bf16 pair (x in the low half) by the hardware's round-to-nearest-even
+// conversion; equal to f2bf for every non-NaN value
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+
+constexpr int kBZ = 4, kBY = 4;
+
+// The epilogue of the brick kernels.  acc[t][c][r] is voxel x = 4 (lane/16)
+// + r of brick row wid ROWS + t, channel (cb0 + c) 16 + lane % 16.  Bias and
+// ReLU are applied per value and the results packed to bf16; the wave's
+// tile then goes through LDS (s_out, ROWS x 16 x (16 NB + 8) elements per
+// wave, free for reuse by the caller) so that each lane stores 16 bytes: 8
+// consecutive channels of one voxel.  The data-gradient mask is applied to
+// those 16 bytes (a value is kept where the mask is > 0).
+template <int ROWS, int NB>
+__device__ __forceinline__ void store_tiles(
+    const f32x4 (&acc)[ROWS][NB], bf16_t *s_out, int wid, int lane,
+    int64_t bn, int z0, int y0, int x0, Vol V, int cb0,
+    const float *__restrict__ bias, int relu, const bf16_t *__restrict__ mask,
+    bf16_t *__restrict__ y, int Cout) {
+    constexpr int OP = 16 * NB + 8;            // LDS pitch per voxel
+    const int q = lane >> 4, l16 = lane & 15;
+    bf16_t *tile = s_out + wid * ROWS * 16 * OP;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+        const int ch = c * 16 + l16;
+        const float bv = bias ? bias[cb0 * 16 + ch] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < ROWS; ++t)
+#pragma unroll
+            for (int r = 0; r < 4; r += 2) {
+                float v0 = acc[t][c][r] + bv, v1 = acc[t][c][r + 1] + bv;
+                if (relu) { v0 = fmaxf(v0, 0.0f); v1 = fmaxf(v1, 0.0f); }
+                const uint32_t pk = pack_bf16x2(v0, v1);
+                bf16_t *dst = tile + (t * 16 + 4 * q + r) * OP + ch;
+                dst[0] = (bf16_t)(pk & 0xffffu);
+                dst[OP] = (bf16_t)(pk >> 16);
+            }
+    }
+    __syncthreads();
+    constexpr int PER = ROWS * 16 * 2 * NB / 64;   // 16-byte stores per lane
+#pragma unroll
+    for (int h = 0; h < PER; ++h) {
+        const int idx = lane + 64 * h;
+        const int p = idx / (2 * NB), k = idx % (2 * NB);
+        const int t = p / 16, xv = p % 16;
+        const int row = wid * ROWS + t;
+        const int rz = row / kBY, ry = row % kBY;
+        uint4 val = *reinterpret_cast<const uint4 *>(tile + p * OP + 8 * k);
+        const int64_t off =
+            (((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0 + xv) * Cout +
+            cb0 * 16 + 8 * k;
+        if (mask) {
+            const uint4 m = *reinterpret_cast<const uint4 *>(mask + off);
+            const uint32_t mw[4] = {m.x, m.y, m.z, m.w};
+            uint32_t vw[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool klo = __uint_as_float(mw[e] << 16) > 0.0f;
+                const bool khi = __uint_as_float(mw[e] & 0xffff0000u) > 0.0f;
+                vw[e] &= (klo ? 0x0000ffffu : 0u) | (khi ? 0xffff0000u : 0u);
+            }
+            val = make_uint4(vw[0], vw[1], vw[2], vw[3]);
+        }
+        *reinterpret_cast<uint4 *>(y + off) = val;
+    }
+}
+
 // The same convolution with the input staged in LDS.  A block computes a
 // brick of kBZ x kBY rows of 16 consecutive x-voxels for NB blocks of 16
 // output channels (channel group blockIdx.y); each wave owns kBZ*kBY/4 rows.
@@ -145,9 +217,9 @@ k_conv3(const bf16_t *__restrict__ x, Vol V, int Cin,
 // distinct LDS banks.  Within a chunk the reduction runs over slots
 // (tap o, 8-channel group g), four per matrix instruction (one per lane
 // quarter); A and B take the same slot, so any slot order sums the same
-// products.  Requires W % 16 == 0, H % kBY == 0, D % kBZ == 0 and
-// Cin % CC == 0.
-constexpr int kBZ = 4, kBY = 4;
+// products.  A per-block table holds each slot's LDS and weight offsets, so
+// the steps do no index arithmetic.  Requires W % 16 == 0, H % kBY == 0,
+// D % kBZ == 0 and Cin % CC == 0.
 template <int CC, int NB>
 __global__ void __launch_bounds__(256)
 k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
@@ -162,7 +234,10 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     constexpr int SLOTS = 27 * G;
     constexpr int STEPS = (SLOTS + 3) / 4;
     constexpr int ROWS = kBZ * kBY / 4;        // rows (tiles) per wave
+    static_assert(HVOX * PITCH >= 4 * ROWS * 16 * (16 * NB + 8),
+                  "the epilogue reuses the halo buffer");
     __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * PITCH];
+    __shared__ int2 s_tab[STEPS * 4];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
     int64_t b = blockIdx.x;
@@ -173,6 +248,23 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
     const int cb0 = blockIdx.y * NB;
     const int q = lane >> 4, vx = lane & 15;
+    // slot -> (LDS offset of tap o and group g relative to the lane's first
+    // row, weight offset o Cin + 8 g); slots past the last tap point at
+    // tap 0 and are zeroed in the last step
+    for (int sl = threadIdx.x; sl < STEPS * 4; sl += 256) {
+        const int o = sl < SLOTS ? sl / G : 0, g = sl < SLOTS ? sl % G : 0;
+        const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;
+        s_tab[sl] = make_int2(((dz * HY + dy) * HX + dx) * PITCH + 8 * g,
+                              o * Cin + 8 * g);
+    }
+    // the lane's A row in the halo: brick row wid ROWS (rz = wid, ry = 0
+    // for 4 x 4 bricks of 4 rows per wave), voxel vx; row t adds t HX PITCH
+    const int a_base = ((wid * ROWS / kBY) * HY + (wid * ROWS) % kBY) * HX *
+                           PITCH + vx * PITCH;
+    const bf16_t *wrow[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+        wrow[c] = W + (int64_t)((cb0 + c) * 16 + vx) * Kp;
     f32x4 acc[ROWS][NB];
 #pragma unroll
     for (int t = 0; t < ROWS; ++t)
@@ -206,32 +298,25 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
                                            (i % G) * 8) = hval[it];
         }
         __syncthreads();
-        // Weights of step j + 1 are loaded while step j computes.  Slots
-        // past the last tap (only when 27 G is not a multiple of 4) read
-        // tap 0 and get a zero A fragment, so no load is conditional.
-        auto wload = [&](int j, bf16x8 *wv) {
-            const int sl = 4 * j + q;
-            const bool ok = (SLOTS % 4 == 0) || sl < SLOTS;
-            const int o = ok ? sl / G : 0, g = ok ? sl % G : 0;
+        // Weights of step j + 1 are loaded while step j computes (two
+        // buffers in turn; the empty asm statements keep each prefetch
+        // ahead of the step that does not use it -- the compiler otherwise
+        // moves the loads next to their use).  Each buffer carries its
+        // step's LDS offset.
+        auto wload = [&](int j, bf16x8 *wv, int &aoff) {
+            const int2 tb = s_tab[4 * j + q];
+            aoff = a_base + tb.x;
 #pragma unroll
             for (int c = 0; c < NB; ++c)
-                wv[c] = *reinterpret_cast<const bf16x8 *>(
-                    W + (int64_t)((cb0 + c) * 16 + vx) * Kp + o * Cin + c0 +
-                    8 * g);
+                wv[c] = *reinterpret_cast<const bf16x8 *>(wrow[c] + c0 +
+                                                          tb.y);
         };
-        auto step = [&](int j, const bf16x8 *wv) {
-            const int sl = 4 * j + q;
-            const bool ok = (SLOTS % 4 == 0) || sl < SLOTS;
-            const int o = ok ? sl / G : 0, g = ok ? sl % G : 0;
-            const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;
+        auto step = [&](const bf16x8 *wv, int aoff, bool ok) {
             bf16x8 a[ROWS];
 #pragma unroll
             for (int t = 0; t < ROWS; ++t) {
-                const int row = wid * ROWS + t;
-                const int rz = row / kBY, ry = row % kBY;
                 const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
-                    s_in + (((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)) *
-                               PITCH + 8 * g);
+                    s_in + aoff + t * HX * PITCH);
                 a[t] = ok ? v : bf16x8{};
             }
 #pragma unroll
@@ -241,43 +326,33 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
                     acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         a[t], wv[c], acc[t][c], 0, 0, 0);
         };
-        // two weight buffers in turn; the empty asm statements keep each
-        // prefetch ahead of the step that does not use it (the compiler
-        // otherwise moves the loads next to their use)
         bf16x8 wa[NB], wb[NB];
-        wload(0, wa);
+        int oa, ob;
+        wload(0, wa, oa);
+        int j = 0;
 #pragma unroll 1
-        for (int j = 0; j + 1 < STEPS; j += 2) {
-            wload(j + 1, wb);
+        for (; j + 2 < STEPS; j += 2) {        // pairs before the last step
+            wload(j + 1, wb, ob);
             asm volatile("" ::: "memory");
-            step(j, wa);
-            wload(j + 2 < STEPS ? j + 2 : j + 1, wa);
+            step(wa, oa, true);
+            wload(j + 2, wa, oa);
             asm volatile("" ::: "memory");
-            step(j + 1, wb);
+            step(wb, ob, true);
         }
-        if (STEPS % 2) step(STEPS - 1, wa);
-    }
-    // acc[t][c][r]: voxel (row, x = 4 (lane/16) + r), channel of block c
-#pragma unroll
-    for (int t = 0; t < ROWS; ++t) {
-        const int row = wid * ROWS + t;
-        const int rz = row / kBY, ry = row % kBY;
-        const int64_t vrow =
-            ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0;
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-            const int co = (cb0 + c) * 16 + vx;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t vv = vrow + 4 * q + r;
-                float val = acc[t][c][r] + (bias ? bias[co] : 0.0f);
-                if (relu) val = fmaxf(val, 0.0f);
-                if (mask && !(bf2f(mask[vv * Cout + co]) > 0.0f))
-                    val = 0.0f;
-                y[vv * Cout + co] = f2bf(val);
-            }
+        // the last one or two steps; only the last can hold padding slots
+        const bool ok_last = (SLOTS % 4 == 0) || 4 * (STEPS - 1) + q < SLOTS;
+        if (j + 1 < STEPS) {
+            wload(j + 1, wb, ob);
+            asm volatile("" ::: "memory");
+            step(wa, oa, true);
+            step(wb, ob, ok_last);
+        } else {
+            step(wa, oa, ok_last);
         }
     }
+    __syncthreads();                           // the halo is free
+    store_tiles<ROWS, NB>(acc, s_in, wid, lane, bn, z0, y0, x0, V, cb0, bias,
+                          relu, mask, y, Cout);
 }
 
 // The first layer: of the 16 padded input channels only the first two
@@ -302,6 +377,7 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
     constexpr int C = 16, KS = 64;
     __shared__ uint32_t s_in[HVOX];
     __shared__ __attribute__((aligned(16))) bf16_t s_w[C * KS];
+    __shared__ __attribute__((aligned(16))) bf16_t s_out[4 * ROWS * 16 * 24];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
     int64_t b = blockIdx.x;
@@ -340,9 +416,9 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
         if (i < HVOX) s_in[i] = hval[it];
     }
     __syncthreads();
-    f32x4 acc[ROWS];
+    f32x4 acc[ROWS][1];
 #pragma unroll
-    for (int t = 0; t < ROWS; ++t) acc[t] = f32x4{0, 0, 0, 0};
+    for (int t = 0; t < ROWS; ++t) acc[t][0] = f32x4{0, 0, 0, 0};
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
         const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
@@ -363,23 +439,13 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
             }
             const bf16x8 a = __builtin_bit_cast(
                 bf16x8, make_uint4(w4[0], w4[1], w4[2], w4[3]));
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, wv, acc[t],
-                                                             0, 0, 0);
+            acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                a, wv, acc[t][0], 0, 0, 0);
         }
     }
-#pragma unroll
-    for (int t = 0; t < ROWS; ++t) {
-        const int row = wid * ROWS + t;
-        const int rz = row / kBY, ry = row % kBY;
-        const int64_t vrow =
-            ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0;
-        const int co = vx;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t vv = vrow + 4 * q + r;
-            y[vv * C + co] = f2bf(fmaxf(acc[t][r] + bias[co], 0.0f));
-        }
-    }
+    __syncthreads();                           // the tables are free
+    store_tiles<ROWS, 1>(acc, s_out, wid, lane, bn, z0, y0, x0, V, 0, bias,
+                         1, nullptr, y, C);
 }
 
 // W'[ci][o'][co] = W[co][26 - o'][ci]: the weights of the transposed
