@@ -220,13 +220,16 @@ __device__ __forceinline__ void store_tiles(
 // products.  A per-block table holds each slot's LDS and weight offsets, so
 // the steps do no index arithmetic.  Requires W % 16 == 0, H % kBY == 0,
 // D % kBZ == 0 and Cin % CC == 0.
+// With xc given, the input is the decoder's concatenation read in place:
+// channels [0, cc) are xc (half resolution, nearest up-sampling) and
+// [cc, Cin) are x (cc and Cin - cc multiples of CC).
 template <int CC, int NB>
 __global__ void __launch_bounds__(256)
 k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
            const bf16_t *W, int Kp,
            const float *__restrict__ bias, int relu,
            const bf16_t *__restrict__ mask, bf16_t *__restrict__ y,
-           int Cout) {
+           int Cout, const bf16_t *__restrict__ xc, int cc) {
     constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
     constexpr int HVOX = HZ * HY * HX;
     constexpr int G = CC / 8;                  // 16-byte groups per voxel
@@ -273,6 +276,13 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     constexpr int NIT = (HVOX * G + 255) / 256;  // halo loads per thread
     for (int c0 = 0; c0 < Cin; c0 += CC) {
         if (c0) __syncthreads();               // the last chunk's reads
+        // the chunk's source: x, or with xc the coarse or the skip part
+        const bool up = xc && c0 < cc;
+        const bf16_t *src = up ? xc : x;
+        const int sC = xc ? (up ? cc : Cin - cc) : Cin;
+        const int sc0 = (xc && !up) ? c0 - cc : c0;
+        const int sh = up ? 1 : 0;
+        const int sd = V.d >> sh, shh = V.h >> sh, sw = V.w >> sh;
         // halo: voxel (hz, hy, hx) = input (z0+hz-1, y0+hy-1, x0+hx-1); all
         // of a thread's loads are issued before its LDS stores, so their
         // latencies overlap
@@ -287,8 +297,8 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
             if (i < HVOX * G && (unsigned)zz < (unsigned)V.d &&
                 (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w)
                 hval[it] = *reinterpret_cast<const uint4 *>(
-                    x + (((bn * V.d + zz) * V.h + yy) * V.w + xx) * Cin + c0 +
-                    g * 8);
+                    src + (((bn * sd + (zz >> sh)) * shh + (yy >> sh)) * sw +
+                           (xx >> sh)) * sC + sc0 + g * 8);
         }
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -1298,9 +1308,16 @@ void launch_conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
 // waves instead of leaving most of the chip idle.
 constexpr int64_t kConvWaves = 2048;
 
+// xc, cc: see k_conv3_bk (brick volumes only; brick_ok tells)
+bool brick_ok(Vol V, int cin) {
+    return cin % 16 == 0 && V.w % 16 == 0 && V.h % kBY == 0 &&
+           V.d % kBZ == 0;
+}
+
 psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                 const float *bias, int relu, const bf16_t *mask, bf16_t *y,
-                int cout, hipStream_t st) {
+                int cout, hipStream_t st, const bf16_t *xc = nullptr,
+                int cc = 0) {
     if (cout % 16 != 0 || cout > 16 * 12) {
         set_error("unsupported channel count %d", cout);
         return PSL_EINVAL;
@@ -1311,14 +1328,18 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
     // channel blocks per wave up to 32 channels (the fine levels, where the
     // volume gives blocks enough), one above (the coarse levels, small
     // volumes: more blocks)
-    if (cin % 16 == 0 && V.w % 16 == 0 && V.h % kBY == 0 &&
-        V.d % kBZ == 0) {
+    if (xc && !(brick_ok(V, cin) && cc % (cin % 32 == 0 ? 32 : 16) == 0 &&
+                (cin - cc) % (cin % 32 == 0 ? 32 : 16) == 0)) {
+        set_error("fused concatenation needs brick volumes");
+        return PSL_EINVAL;
+    }
+    if (brick_ok(V, cin)) {
         const unsigned bricks = (unsigned)(nv / (16 * kBY * kBZ));
         const int nbk = (cout == 32) ? 2 : 1;
         const dim3 grid(bricks, (unsigned)(nc / nbk));
 #define PSL_CONV_BK(CC, NBV)                                                  \
     hipLaunchKernelGGL((k_conv3_bk<CC, NBV>), grid, dim3(256), 0, st, x, V,  \
-                       cin, W, kp, bias, relu, mask, y, cout)
+                       cin, W, kp, bias, relu, mask, y, cout, xc, cc)
         if (cin % 32 == 0) {
             if (nbk == 2) PSL_CONV_BK(32, 2);
             else PSL_CONV_BK(32, 1);
@@ -1425,13 +1446,22 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
         const int ia = (l == 2) ? D2A : (l == 1 ? D1A : D0A);
         const ConvL &la = L[ia], &lb = L[ia + 1];
         const int cf = L[2 * l + 1].cout;
-        hipLaunchKernelGGL(k_up_concat,
-                           dim3(nblk(V[l].voxels() * ((cc + cf) / 8))),
-                           dim3(256), 0, c.st, coarse, cc, eb[l], cf, V[l],
-                           cats[l]);
-        if ((s = conv(cats[l], V[l], la.cin, W(ia), la.kp, B(ia), 1, nullptr,
-                      da[l], la.cout, c.st)))
-            return s;
+        const int ccs = la.cin % 32 == 0 ? 32 : 16;
+        if (!train && brick_ok(V[l], la.cin) && cc % ccs == 0 &&
+            cf % ccs == 0) {
+            // inference: the convolution reads the concatenation in place
+            if ((s = conv(eb[l], V[l], la.cin, W(ia), la.kp, B(ia), 1,
+                          nullptr, da[l], la.cout, c.st, coarse, cc)))
+                return s;
+        } else {
+            hipLaunchKernelGGL(k_up_concat,
+                               dim3(nblk(V[l].voxels() * ((cc + cf) / 8))),
+                               dim3(256), 0, c.st, coarse, cc, eb[l], cf,
+                               V[l], cats[l]);
+            if ((s = conv(cats[l], V[l], la.cin, W(ia), la.kp, B(ia), 1,
+                          nullptr, da[l], la.cout, c.st)))
+                return s;
+        }
         if ((s = conv(da[l], V[l], lb.cin, W(ia + 1), lb.kp, B(ia + 1), 1,
                       nullptr, db[l], lb.cout, c.st)))
             return s;
