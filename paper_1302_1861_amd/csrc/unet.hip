@@ -153,13 +153,15 @@ constexpr int kBZ = 4, kBY = 4;
 // tile then goes through LDS (s_out, ROWS x 16 x (16 NB + 8) elements per
 // wave, free for reuse by the caller) so that each lane stores 16 bytes: 8
 // consecutive channels of one voxel.  The data-gradient mask is applied to
-// those 16 bytes (a value is kept where the mask is > 0).
+// those 16 bytes (a value is kept where the mask is > 0).  With yp given
+// (no mask), the brick's 2x2x2 averages go to yp on the half-resolution
+// grid as well, summed in the order and precision of k_pool.
 template <int ROWS, int NB>
 __device__ __forceinline__ void store_tiles(
     const f32x4 (&acc)[ROWS][NB], bf16_t *s_out, int wid, int lane,
     int64_t bn, int z0, int y0, int x0, Vol V, int cb0,
     const float *__restrict__ bias, int relu, const bf16_t *__restrict__ mask,
-    bf16_t *__restrict__ y, int Cout) {
+    bf16_t *__restrict__ y, int Cout, bf16_t *__restrict__ yp = nullptr) {
     constexpr int OP = 16 * NB + 8;            // LDS pitch per voxel
     const int q = lane >> 4, l16 = lane & 15;
     bf16_t *tile = s_out + wid * ROWS * 16 * OP;
@@ -206,6 +208,39 @@ __device__ __forceinline__ void store_tiles(
         }
         *reinterpret_cast<uint4 *>(y + off) = val;
     }
+    if (yp) {
+        // one thread per pooled voxel of the brick and 8 channels: wave w
+        // holds brick z-slice w, row t holds y-row t (4 x 4 bricks)
+        static_assert(ROWS == kBY && kBZ == 4, "pooling assumes 4x4 bricks");
+        __syncthreads();
+        const int i = threadIdx.x;
+        if (i < 64 * NB) {
+            const int k = i % (2 * NB), pv = i / (2 * NB);
+            const int px = pv % 8, py = (pv / 8) % 2, pz = pv / 16;
+            float sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            for (int a = 0; a < 8; ++a) {
+                const int zz = 2 * pz + (a >> 2), yy = 2 * py + ((a >> 1) & 1),
+                          xx = 2 * px + (a & 1);
+                const uint4 u = *reinterpret_cast<const uint4 *>(
+                    s_out + zz * ROWS * 16 * OP + (yy * 16 + xx) * OP + 8 * k);
+                const uint32_t uw[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    sum[2 * e] += __uint_as_float(uw[e] << 16);
+                    sum[2 * e + 1] += __uint_as_float(uw[e] & 0xffff0000u);
+                }
+            }
+            const Vol U{V.n, V.d / 2, V.h / 2, V.w / 2};
+            const int64_t pofs =
+                (((bn * U.d + z0 / 2 + pz) * U.h + (y0 / 2 + py)) * U.w +
+                 x0 / 2 + px) * Cout + cb0 * 16 + 8 * k;
+            *reinterpret_cast<uint4 *>(yp + pofs) = make_uint4(
+                pack_bf16x2(0.125f * sum[0], 0.125f * sum[1]),
+                pack_bf16x2(0.125f * sum[2], 0.125f * sum[3]),
+                pack_bf16x2(0.125f * sum[4], 0.125f * sum[5]),
+                pack_bf16x2(0.125f * sum[6], 0.125f * sum[7]));
+        }
+    }
 }
 
 // The same convolution with the input staged in LDS.  A block computes a
@@ -222,14 +257,16 @@ __device__ __forceinline__ void store_tiles(
 // D % kBZ == 0 and Cin % CC == 0.
 // With xc given, the input is the decoder's concatenation read in place:
 // channels [0, cc) are xc (half resolution, nearest up-sampling) and
-// [cc, Cin) are x (cc and Cin - cc multiples of CC).
+// [cc, Cin) are x (cc and Cin - cc multiples of CC).  With yp given, the
+// 2x2x2 average pool of the output is written there too.
 template <int CC, int NB>
 __global__ void __launch_bounds__(256)
 k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
            const bf16_t *W, int Kp,
            const float *__restrict__ bias, int relu,
            const bf16_t *__restrict__ mask, bf16_t *__restrict__ y,
-           int Cout, const bf16_t *__restrict__ xc, int cc) {
+           int Cout, const bf16_t *__restrict__ xc, int cc,
+           bf16_t *__restrict__ yp) {
     constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
     constexpr int HVOX = HZ * HY * HX;
     constexpr int G = CC / 8;                  // 16-byte groups per voxel
@@ -362,7 +399,7 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     }
     __syncthreads();                           // the halo is free
     store_tiles<ROWS, NB>(acc, s_in, wid, lane, bn, z0, y0, x0, V, cb0, bias,
-                          relu, mask, y, Cout);
+                          relu, mask, y, Cout, yp);
 }
 
 // The first layer: of the 16 padded input channels only the first two
@@ -1317,7 +1354,7 @@ bool brick_ok(Vol V, int cin) {
 psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                 const float *bias, int relu, const bf16_t *mask, bf16_t *y,
                 int cout, hipStream_t st, const bf16_t *xc = nullptr,
-                int cc = 0) {
+                int cc = 0, bf16_t *yp = nullptr) {
     if (cout % 16 != 0 || cout > 16 * 12) {
         set_error("unsupported channel count %d", cout);
         return PSL_EINVAL;
@@ -1328,9 +1365,10 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
     // channel blocks per wave up to 32 channels (the fine levels, where the
     // volume gives blocks enough), one above (the coarse levels, small
     // volumes: more blocks)
-    if (xc && !(brick_ok(V, cin) && cc % (cin % 32 == 0 ? 32 : 16) == 0 &&
-                (cin - cc) % (cin % 32 == 0 ? 32 : 16) == 0)) {
-        set_error("fused concatenation needs brick volumes");
+    if ((yp && (mask || !brick_ok(V, cin))) ||
+        (xc && !(brick_ok(V, cin) && cc % (cin % 32 == 0 ? 32 : 16) == 0 &&
+                (cin - cc) % (cin % 32 == 0 ? 32 : 16) == 0))) {
+        set_error("fused concatenation or pooling needs brick volumes");
         return PSL_EINVAL;
     }
     if (brick_ok(V, cin)) {
@@ -1339,7 +1377,7 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
         const dim3 grid(bricks, (unsigned)(nc / nbk));
 #define PSL_CONV_BK(CC, NBV)                                                  \
     hipLaunchKernelGGL((k_conv3_bk<CC, NBV>), grid, dim3(256), 0, st, x, V,  \
-                       cin, W, kp, bias, relu, mask, y, cout, xc, cc)
+                       cin, W, kp, bias, relu, mask, y, cout, xc, cc, yp)
         if (cin % 32 == 0) {
             if (nbk == 2) PSL_CONV_BK(32, 2);
             else PSL_CONV_BK(32, 1);
@@ -1428,10 +1466,14 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
         } else if ((s = conv(ins[l], V[l], la.cin, W(2 * l), la.kp,
                              B(2 * l), 1, nullptr, ea[l], la.cout, c.st)))
             return s;
+        // the pooled features come out of the convolution's epilogue where
+        // the volume tiles into bricks
+        const bool fuse_pool = l < 3 && brick_ok(V[l], lb.cin);
         if ((s = conv(ea[l], V[l], lb.cin, W(2 * l + 1), lb.kp, B(2 * l + 1),
-                      1, nullptr, eb[l], lb.cout, c.st)))
+                      1, nullptr, eb[l], lb.cout, c.st, nullptr, 0,
+                      fuse_pool ? pools[l] : nullptr)))
             return s;
-        if (l < 3)
+        if (l < 3 && !fuse_pool)
             hipLaunchKernelGGL(k_pool, dim3(nblk(V[l + 1].voxels() * lb.cout)),
                                dim3(256), 0, c.st, eb[l], V[l], lb.cout,
                                pools[l]);
