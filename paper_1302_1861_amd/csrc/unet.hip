@@ -147,6 +147,13 @@ __device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
 
 constexpr int kBZ = 4, kBY = 4;
 
+// The output head fused into the last convolution (inference): out[v] =
+// dose[v] scale[sample] + bh + sum_c f[v][c] wh[c], in k_head's order.
+struct HeadArgs {
+    const float *wh, *bh, *dose, *scale;
+    float *out;                 // nullptr: no head
+};
+
 // The epilogue of the brick kernels.  acc[t][c][r] is voxel x = 4 (lane/16)
 // + r of brick row wid ROWS + t, channel (cb0 + c) 16 + lane % 16.  Bias and
 // ReLU are applied per value and the results packed to bf16; the wave's
@@ -161,7 +168,8 @@ __device__ __forceinline__ void store_tiles(
     const f32x4 (&acc)[ROWS][NB], bf16_t *s_out, int wid, int lane,
     int64_t bn, int z0, int y0, int x0, Vol V, int cb0,
     const float *__restrict__ bias, int relu, const bf16_t *__restrict__ mask,
-    bf16_t *__restrict__ y, int Cout, bf16_t *__restrict__ yp = nullptr) {
+    bf16_t *__restrict__ y, int Cout, bf16_t *__restrict__ yp = nullptr,
+    HeadArgs hd = HeadArgs{}) {
     constexpr int OP = 16 * NB + 8;            // LDS pitch per voxel
     const int q = lane >> 4, l16 = lane & 15;
     bf16_t *tile = s_out + wid * ROWS * 16 * OP;
@@ -182,6 +190,31 @@ __device__ __forceinline__ void store_tiles(
             }
     }
     __syncthreads();
+    if (NB == 1 && hd.out) {
+        // one voxel per lane: its 16 channels from the tile, the head's
+        // products in channel order, the residual input added last
+        static_assert(ROWS * 16 == 64, "a wave's tile is 64 voxels");
+        const int t = lane / 16, xv = lane % 16;
+        const int row = wid * ROWS + t;
+        const int rz = row / kBY, ry = row % kBY;
+        const int64_t v =
+            ((bn * V.d + z0 + rz) * V.h + (y0 + ry)) * V.w + x0 + xv;
+        float sacc = hd.bh[0];
+#pragma unroll
+        for (int g = 0; g < 2; ++g) {
+            const uint4 u =
+                *reinterpret_cast<const uint4 *>(tile + lane * OP + 8 * g);
+            const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                sacc += __uint_as_float(w4[m] << 16) * hd.wh[8 * g + 2 * m];
+                sacc += __uint_as_float(w4[m] & 0xffff0000u) *
+                        hd.wh[8 * g + 2 * m + 1];
+            }
+        }
+        hd.out[v] = hd.dose[v] * hd.scale[bn] + sacc;
+        return;
+    }
     constexpr int PER = ROWS * 16 * 2 * NB / 64;   // 16-byte stores per lane
 #pragma unroll
     for (int h = 0; h < PER; ++h) {
@@ -258,7 +291,9 @@ __device__ __forceinline__ void store_tiles(
 // With xc given, the input is the decoder's concatenation read in place:
 // channels [0, cc) are xc (half resolution, nearest up-sampling) and
 // [cc, Cin) are x (cc and Cin - cc multiples of CC).  With yp given, the
-// 2x2x2 average pool of the output is written there too.
+// 2x2x2 average pool of the output is written there too.  With hd.out
+// given (16 output channels), the output head is applied and y is not
+// written.
 template <int CC, int NB>
 __global__ void __launch_bounds__(256)
 k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
@@ -266,7 +301,7 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
            const float *__restrict__ bias, int relu,
            const bf16_t *__restrict__ mask, bf16_t *__restrict__ y,
            int Cout, const bf16_t *__restrict__ xc, int cc,
-           bf16_t *__restrict__ yp) {
+           bf16_t *__restrict__ yp, HeadArgs hd) {
     constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
     constexpr int HVOX = HZ * HY * HX;
     constexpr int G = CC / 8;                  // 16-byte groups per voxel
@@ -399,7 +434,7 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     }
     __syncthreads();                           // the halo is free
     store_tiles<ROWS, NB>(acc, s_in, wid, lane, bn, z0, y0, x0, V, cb0, bias,
-                          relu, mask, y, Cout, yp);
+                          relu, mask, y, Cout, yp, hd);
 }
 
 // The first layer: of the 16 padded input channels only the first two
@@ -1354,7 +1389,8 @@ bool brick_ok(Vol V, int cin) {
 psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                 const float *bias, int relu, const bf16_t *mask, bf16_t *y,
                 int cout, hipStream_t st, const bf16_t *xc = nullptr,
-                int cc = 0, bf16_t *yp = nullptr) {
+                int cc = 0, bf16_t *yp = nullptr,
+                HeadArgs hd = HeadArgs{}) {
     if (cout % 16 != 0 || cout > 16 * 12) {
         set_error("unsupported channel count %d", cout);
         return PSL_EINVAL;
@@ -1365,10 +1401,12 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
     // channel blocks per wave up to 32 channels (the fine levels, where the
     // volume gives blocks enough), one above (the coarse levels, small
     // volumes: more blocks)
-    if ((yp && (mask || !brick_ok(V, cin))) ||
+    if ((hd.out && (cout != 16 || mask || yp || !brick_ok(V, cin))) ||
+        (yp && (mask || !brick_ok(V, cin))) ||
         (xc && !(brick_ok(V, cin) && cc % (cin % 32 == 0 ? 32 : 16) == 0 &&
                 (cin - cc) % (cin % 32 == 0 ? 32 : 16) == 0))) {
-        set_error("fused concatenation or pooling needs brick volumes");
+        set_error("fused concatenation, pooling or head needs brick "
+                  "volumes");
         return PSL_EINVAL;
     }
     if (brick_ok(V, cin)) {
@@ -1377,7 +1415,8 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
         const dim3 grid(bricks, (unsigned)(nc / nbk));
 #define PSL_CONV_BK(CC, NBV)                                                  \
     hipLaunchKernelGGL((k_conv3_bk<CC, NBV>), grid, dim3(256), 0, st, x, V,  \
-                       cin, W, kp, bias, relu, mask, y, cout, xc, cc, yp)
+                       cin, W, kp, bias, relu, mask, y, cout, xc, cc, yp, \
+                       hd)
         if (cin % 32 == 0) {
             if (nbk == 2) PSL_CONV_BK(32, 2);
             else PSL_CONV_BK(32, 1);
@@ -1504,16 +1543,23 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
                           nullptr, da[l], la.cout, c.st)))
                 return s;
         }
+        // inference: the head comes out of the last convolution's epilogue
+        HeadArgs hd{};
+        if (l == 0 && !train && lb.cout == 16 && brick_ok(V[0], lb.cin))
+            hd = HeadArgs{c.p + c.net.head_w, c.p + c.net.head_b, dose,
+                          a.scale, a.out};
         if ((s = conv(da[l], V[l], lb.cin, W(ia + 1), lb.kp, B(ia + 1), 1,
-                      nullptr, db[l], lb.cout, c.st)))
+                      nullptr, db[l], lb.cout, c.st, nullptr, 0, nullptr,
+                      hd)))
             return s;
         coarse = db[l];
         cc = lb.cout;
+        if (l == 0 && !hd.out)
+            hipLaunchKernelGGL(k_head, dim3(nblk(V[0].voxels())), dim3(256),
+                               0, c.st, a.d0b, L[D0B].cout,
+                               c.p + c.net.head_w, c.p + c.net.head_b, dose,
+                               per, a.scale, V[0].voxels(), a.out);
     }
-    hipLaunchKernelGGL(k_head, dim3(nblk(V[0].voxels())), dim3(256), 0, c.st,
-                       a.d0b, L[D0B].cout, c.p + c.net.head_w,
-                       c.p + c.net.head_b, dose, per, a.scale, V[0].voxels(),
-                       a.out);
     PSL_LAUNCHED();
     return PSL_OK;
 }
