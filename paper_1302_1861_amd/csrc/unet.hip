@@ -1035,11 +1035,19 @@ k_sample_max(const float *__restrict__ dose, int64_t per_sample,
              unsigned int *__restrict__ mbits) {
     __shared__ float s[256];
     const float *d = dose + (int64_t)blockIdx.y * per_sample;
-    float m = 0.0f;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_sample;
-         i += (int64_t)gridDim.x * 256)
-        m = fmaxf(m, d[i]);
-    s[threadIdx.x] = m;
+    // four independent maxima, so that four loads are in flight (the
+    // maximum does not depend on the order)
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f, m3 = 0.0f;
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    for (; i + 3 * stride < per_sample; i += 4 * stride) {
+        m0 = fmaxf(m0, d[i]);
+        m1 = fmaxf(m1, d[i + stride]);
+        m2 = fmaxf(m2, d[i + 2 * stride]);
+        m3 = fmaxf(m3, d[i + 3 * stride]);
+    }
+    for (; i < per_sample; i += stride) m0 = fmaxf(m0, d[i]);
+    s[threadIdx.x] = fmaxf(fmaxf(m0, m1), fmaxf(m2, m3));
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if (threadIdx.x < h) s[threadIdx.x] = fmaxf(s[threadIdx.x],
