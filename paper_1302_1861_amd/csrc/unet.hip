@@ -684,17 +684,19 @@ constexpr int kWgDyPitch = 16 * kBY * kBZ + 8;          // 264
 constexpr int kWgXRows = (kBZ + 2) * (kBY + 2);          // 36
 constexpr int kWgXPitch = kWgXRows * 16 + 8;             // 584
 constexpr int64_t kWgPartFloats = int64_t(8) << 20;      // 32 MB
+// One byte permute per output word: 0x05040100 takes the low halves of
+// (p[2m], p[2m+1]), 0x07060302 the high halves.
 __device__ __forceinline__ void put_pair_rows(bf16_t *row0, bf16_t *row1,
                                               const uint32_t p[8]) {
     uint4 lo, hi;
-    lo.x = (p[0] & 0xffffu) | (p[1] << 16);
-    lo.y = (p[2] & 0xffffu) | (p[3] << 16);
-    lo.z = (p[4] & 0xffffu) | (p[5] << 16);
-    lo.w = (p[6] & 0xffffu) | (p[7] << 16);
-    hi.x = (p[0] >> 16) | (p[1] & 0xffff0000u);
-    hi.y = (p[2] >> 16) | (p[3] & 0xffff0000u);
-    hi.z = (p[4] >> 16) | (p[5] & 0xffff0000u);
-    hi.w = (p[6] >> 16) | (p[7] & 0xffff0000u);
+    lo.x = __builtin_amdgcn_perm(p[1], p[0], 0x05040100u);
+    lo.y = __builtin_amdgcn_perm(p[3], p[2], 0x05040100u);
+    lo.z = __builtin_amdgcn_perm(p[5], p[4], 0x05040100u);
+    lo.w = __builtin_amdgcn_perm(p[7], p[6], 0x05040100u);
+    hi.x = __builtin_amdgcn_perm(p[1], p[0], 0x07060302u);
+    hi.y = __builtin_amdgcn_perm(p[3], p[2], 0x07060302u);
+    hi.z = __builtin_amdgcn_perm(p[5], p[4], 0x07060302u);
+    hi.w = __builtin_amdgcn_perm(p[7], p[6], 0x07060302u);
     *reinterpret_cast<uint4 *>(row0) = lo;
     *reinterpret_cast<uint4 *>(row1) = hi;
 }
@@ -764,17 +766,20 @@ k_conv3_wgrad_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
             if (dx) __syncthreads();           // the last shift's reads
             // x shifted by dx - 1, transposed: item = (row octet, pair);
             // all of a thread's loads are issued before its LDS stores
+            // item i = threadIdx.x + 256 it: channel pair i % 8, octet
+            // (i / 8) % 2, halo row i / 16 (the first two do not depend on
+            // it)
             constexpr int NXI = 8 * kWgXRows * 2, NIT = (NXI + 255) / 256;
+            const int cp = threadIdx.x % 8, oct = (threadIdx.x / 8) & 1;
+            const int xb = x0 + 8 * oct + dx - 1;
             uint32_t px[NIT][8];
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
-                const int i = threadIdx.x + 256 * it;
-                const int cp = i % 8, rest = i / 8;
-                const int oct = rest & 1, hr = rest >> 1;
+                const int hr = threadIdx.x / 16 + 16 * it;
                 const int hz = hr / (kBY + 2), hy = hr % (kBY + 2);
                 const int zz = z0 + hz - 1, yy = y0 + hy - 1;
-                const int xb = x0 + 8 * oct + dx - 1;
-                const bool zy = i < NXI && (unsigned)zz < (unsigned)V.d &&
+                const bool zy = hr < kWgXRows &&
+                                (unsigned)zz < (unsigned)V.d &&
                                 (unsigned)yy < (unsigned)V.h;
                 const int64_t vrow = ((bn * V.d + zz) * V.h + yy) * V.w;
 #pragma unroll
@@ -788,15 +793,12 @@ k_conv3_wgrad_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
-                const int i = threadIdx.x + 256 * it;
-                if (i < NXI) {
-                    const int cp = i % 8, rest = i / 8;
-                    const int oct = rest & 1, hr = rest >> 1;
+                const int hr = threadIdx.x / 16 + 16 * it;
+                if (hr < kWgXRows)
                     put_pair_rows(
                         s_x + (2 * cp) * kWgXPitch + hr * 16 + 8 * oct,
                         s_x + (2 * cp + 1) * kWgXPitch + hr * 16 + 8 * oct,
                         px[it]);
-                }
             }
             __syncthreads();
 #pragma unroll
