@@ -456,8 +456,9 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
     constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
     constexpr int HVOX = HZ * HY * HX;
     constexpr int ROWS = kBZ * kBY / 4;
-    constexpr int C = 16;
+    constexpr int C = 16, KS = 64;
     __shared__ uint32_t s_in[HVOX];
+    __shared__ __attribute__((aligned(16))) bf16_t s_w[C * KS];
     __shared__ __attribute__((aligned(16))) bf16_t s_out[4 * ROWS * 16 * 24];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
@@ -468,19 +469,11 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
     const int64_t bn = b / nzb;
     const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
     const int q = lane >> 4, vx = lane & 15;
-    // B fragments straight from the weights: the lane's 8 slots of step st
-    // are offsets 16 st + 4 q + jj (jj < 4) with both channels, one 32-bit
-    // load each (offsets past 26 are zero); issued with the halo loads
-    uint32_t bw[2][4];
-#pragma unroll
-    for (int st = 0; st < 2; ++st)
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-            const int o = 16 * st + 4 * q + jj;
-            bw[st][jj] = o < 27 ? *reinterpret_cast<const uint32_t *>(
-                                      W + (int64_t)vx * Kp + o * Cin)
-                                : 0u;
-        }
+    for (int i = threadIdx.x; i < C * KS; i += 256) {
+        const int co = i / KS, k = i % KS;
+        s_w[i] = k < 54 ? W[(int64_t)co * Kp + (k >> 1) * Cin + (k & 1)]
+                        : (bf16_t)0;
+    }
     constexpr int NIT = (HVOX + 255) / 256;
     uint32_t hval[NIT];
 #pragma unroll
@@ -510,8 +503,8 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
     for (int t = 0; t < ROWS; ++t) acc[t][0] = f32x4{0, 0, 0, 0};
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
-        const bf16x8 wv = __builtin_bit_cast(
-            bf16x8, make_uint4(bw[st][0], bw[st][1], bw[st][2], bw[st][3]));
+        const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
+            s_w + vx * KS + 32 * st + 8 * q);
 #pragma unroll
         for (int t = 0; t < ROWS; ++t) {
             const int row = wid * ROWS + t;
