@@ -21,7 +21,8 @@ def _bf16_round(a):
     return t.to(torch.bfloat16).to(torch.float64).numpy()
 
 
-def _setup(n=2, size=16, seed=5):
+def _setup(n=2, size=16, seed=5, shape=None):
+    """shape (d, h, w) overrides the cube of side size."""
     import torch
     import paper_1302_1861_amd as P
     rng = np.random.default_rng(seed)
@@ -33,8 +34,9 @@ def _setup(n=2, size=16, seed=5):
     blob = U.pack(P_).astype(np.float32)
     net = P.Denoiser()
     net.set_params(blob)
-    dose = (rng.random((n, size, size, size)) + 0.1).astype(np.float32)
-    rho = rng.uniform(0.2, 1.9, (n, size, size, size)).astype(np.float32)
+    dims = (n,) + (tuple(shape) if shape else (size, size, size))
+    dose = (rng.random(dims) + 0.1).astype(np.float32)
+    rho = rng.uniform(0.2, 1.9, dims).astype(np.float32)
     tgt = (dose * 1.1 + 0.05 * rng.random(dose.shape)).astype(np.float32)
     # the reference uses the bf16-rounded weights the kernels compute with
     ref = U.unpack(_bf16_round(blob).astype(np.float64))
@@ -51,10 +53,13 @@ def _setup(n=2, size=16, seed=5):
 # 32^3 adds the 32-channel level on bricks (two channel blocks per wave,
 # 32-channel staging), 64^3 (one volume) the 64-channel level (one block
 # per wave, several 32-channel stages).
-@pytest.mark.parametrize("size,n", [(16, 2), (32, 2), (64, 1)])
-def test_forward_matches_reference(size, n):
+# The last case is not a cube: bricks whose counts differ per axis at the
+# finest level, direct gathers below.
+@pytest.mark.parametrize("size,n,shape", [(16, 2, None), (32, 2, None),
+                                          (64, 1, None), (0, 1, (24, 40, 48))])
+def test_forward_matches_reference(size, n, shape):
     import torch
-    net, ref, dose, rho, tgt, T = _setup(n=n, size=size)
+    net, ref, dose, rho, tgt, T = _setup(n=n, size=size, shape=shape)
     out = net.forward(T(dose), T(rho))
     torch.cuda.synchronize()
     got = out.cpu().numpy().astype(np.float64)
@@ -70,10 +75,11 @@ def test_forward_matches_reference(size, n):
     assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-2
 
 
-@pytest.mark.parametrize("size", [16, 32])
-def test_gradients_match_reference(size):
+@pytest.mark.parametrize("size,n,shape", [(16, 2, None), (32, 2, None),
+                                          (0, 1, (16, 24, 32))])
+def test_gradients_match_reference(size, n, shape):
     import torch
-    net, ref, dose, rho, tgt, T = _setup(size=size)
+    net, ref, dose, rho, tgt, T = _setup(n=n, size=size, shape=shape)
     net.loss.zero_()
     net.grads.zero_()
     net.backward(T(dose), T(rho), T(tgt))
