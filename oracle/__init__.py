@@ -89,6 +89,15 @@ class OPhys(C.Structure):
 FLAG_FIRST_COLLISION = 1
 FLAG_NO_MSC = 2
 
+# Columns of the per-particle trace of ``transport(..., trace=True)``:
+# depth, scattering cosine, recoil energy and incident energy of the first
+# photon interaction; the recoil electron's cosine to the incident photon;
+# the normalised (d0 x d') . (d0 x p_e) (-1: photon and electron on opposite
+# sides of the incident axis); |E d0 - E' d'| over sqrt(T (T + 2 m)); and
+# the primary's direction (3) at escape.
+TRACE_N = 10
+TR_Z, TR_COS, TR_T, TR_E, TR_COSE, TR_SIDE, TR_PNORM, TR_EXIT = range(8)
+
 
 def _declare(L):
     vp, i64, i32, d, u64 = C.c_void_p, C.c_int64, C.c_int32, C.c_double, \
@@ -315,7 +324,8 @@ def ophys(n_e=3.343e23, I_eV=75.0, X0=36.08, step=0.1, p_cut=0.010,
 def transport(types, state, uid, seed, phantom, phys=None, acc=None,
               ledger=False, trace=False, n_threads=0):
     """Transport particles (rows E x y z u v w wt) and return
-    (acc [voxels] MeV*weight, counts[2], ledger or None, trace or None)."""
+    (acc [voxels] MeV*weight, counts[2], ledger or None, trace or None);
+    the trace has the TR_* columns above."""
     phys = phys or ophys()
     n = int(len(types))
     nvox = int(np.prod(phantom.density.shape))
@@ -323,7 +333,7 @@ def transport(types, state, uid, seed, phantom, phys=None, acc=None,
         acc = np.zeros(nvox, np.float64)
     P, rho = ophantom(phantom)
     led = np.zeros((n, 4), np.float64) if ledger else None
-    tr = np.zeros((n, 3), np.float64) if trace else None
+    tr = np.zeros((n, TRACE_N), np.float64) if trace else None
     counts = np.zeros(2, np.int64)
     types = np.ascontiguousarray(types, np.uint8)
     state = np.ascontiguousarray(state, np.float64)

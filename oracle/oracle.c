@@ -522,6 +522,18 @@ double oracle_highland(double T, double t, double X0)
     return th > 0.0 ? th : 0.0;
 }
 
+static double dot3(const double a[3], const double b[3])
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+static void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
 /* New direction after deflection by polar angle theta and azimuth phi about
  * d, built from an explicit orthonormal frame (e1, e2, d). */
 static void deflect(double d[3], double cth, double sth, double phi)
@@ -541,6 +553,25 @@ static void deflect(double d[3], double cth, double sth, double phi)
     for (int i = 0; i < 3; ++i) d[i] = nd[i] / nn;
 }
 
+/* Multiple-scattering deflection after one electron step: two independent
+ * Gaussian projected angles of width theta0 = Highland(T0, t_mass) (Box-
+ * Muller), T0 the kinetic energy at the start of the step and t_mass the
+ * mass thickness it crossed; the polar angle is resampled while it exceeds
+ * pi.  d is turned by that polar angle at the azimuth of the pair. */
+static void msc_deflect(xrng *R, double T0, double t_mass, double X0,
+                        double d[3])
+{
+    double th0 = oracle_highland(T0, t_mass, X0), th, ax, ay;
+    do {
+        double u1 = 1.0 - urand(R), u2 = urand(R);
+        double rr = sqrt(-2.0 * log(u1));
+        ax = th0 * rr * cos(2.0 * PI * u2);
+        ay = th0 * rr * sin(2.0 * PI * u2);
+        th = sqrt(ax * ax + ay * ay);
+    } while (th > PI);
+    deflect(d, cos(th), sin(th), atan2(ay, ax));
+}
+
 typedef struct {
     const ophantom *P;
     const ophys *Y;
@@ -548,8 +579,22 @@ typedef struct {
     double dep, esc, killed;    /* per-history ledger (MeV, unweighted) */
     int64_t n_interactions;     /* photon interactions */
     int64_t n_segments;         /* electron voxel segments */
-    double *trace;              /* optional: first-interaction depth / cos */
+    double *trace;              /* optional: per-particle trace (TRACE_N) */
 } octx;
+
+/* Per-particle trace columns (optional output of oracle_transport). */
+#define TRACE_N 10
+#define TR_Z 0          /* photon: depth z of the first interaction        */
+#define TR_COS 1        /*         its scattering cosine                   */
+#define TR_T 2          /*         recoil kinetic energy                   */
+#define TR_E 3          /*         photon energy before the interaction    */
+#define TR_COSE 4       /*         cosine of the recoil electron's         */
+                        /*         direction to the incident photon's      */
+#define TR_SIDE 5       /*         normalised (d0 x d') . (d0 x p_e): -1   */
+                        /*         when photon and electron leave on       */
+                        /*         opposite sides of the incident axis     */
+#define TR_PNORM 6      /*         |E d0 - E' d'| / sqrt(T (T + 2 m))      */
+#define TR_EXIT 7       /* both: direction (3) of the primary at escape    */
 
 static int voxel_of(const ophantom *P, const double p[3], int ijk[3])
 {
@@ -579,6 +624,15 @@ static int voxel_of_clamped(const ophantom *P, const double p[3], int ijk[3])
         ijk[a] = (int)f;
     }
     return 1;
+}
+
+/* Energy leaving the phantom; the primary (trace row given) also records
+ * its direction at escape. */
+static void escape(octx *C, double e, const double d[3], double *tr)
+{
+    C->esc += e;
+    if (tr)
+        for (int a = 0; a < 3; ++a) tr[TR_EXIT + a] = d[a];
 }
 
 static int64_t vindex(const ophantom *P, const int ijk[3])
@@ -633,13 +687,13 @@ static int step_voxel(const ophantom *P, int ijk[3], int axis,
  * projected angles for the pre-step energy and the step's mass
  * thickness. */
 static void transport_electron(octx *C, xrng *R, double T, double p[3],
-                               double d[3], double wgt)
+                               double d[3], double wgt, double *tr)
 {
     const ophantom *P = C->P;
     const ophys *Y = C->Y;
     double n_e = Y->n_e;
     int ijk[3];
-    if (!voxel_of_clamped(P, p, ijk)) { C->esc += T; return; }
+    if (!voxel_of_clamped(P, p, ijk)) { escape(C, T, d, tr); return; }
     if (T <= Y->t_cut) { deposit(C, ijk, T, wgt); return; }
     double r_left = oracle_csda_range(Y->t_cut, T, n_e, Y->I_eV);
     for (;;) {
@@ -664,23 +718,14 @@ static void transport_electron(octx *C, xrng *R, double T, double p[3],
             for (int a = 0; a < 3; ++a) p[a] += seg * d[a];
             remaining -= seg;
             if (seg == sb && axis >= 0) {
-                if (!step_voxel(P, ijk, axis, d)) { C->esc += T; return; }
+                if (!step_voxel(P, ijk, axis, d)) {
+                    escape(C, T, d, tr);
+                    return;
+                }
             }
         }
-        if (!(Y->flags & FLAG_NO_MSC) && t_mass > 0.0) {
-            double th0 = oracle_highland(T0, t_mass, Y->X0), th;
-            double ax, ay;
-            do {
-                /* two independent Gaussian projected angles (Box-Muller) */
-                double u1 = 1.0 - urand(R), u2 = urand(R);
-                double rr = sqrt(-2.0 * log(u1));
-                ax = th0 * rr * cos(2.0 * PI * u2);
-                ay = th0 * rr * sin(2.0 * PI * u2);
-                th = sqrt(ax * ax + ay * ay);
-            } while (th > PI);
-            double phi = atan2(ay, ax);
-            deflect(d, cos(th), sin(th), phi);
-        }
+        if (!(Y->flags & FLAG_NO_MSC) && t_mass > 0.0)
+            msc_deflect(R, T0, t_mass, Y->X0, d);
     }
 }
 
@@ -697,8 +742,9 @@ static void transport_photon(octx *C, xrng *R, double E, double p[3],
 {
     const ophantom *P = C->P;
     const ophys *Y = C->Y;
+    double *tr = C->trace;
     int ijk[3];
-    if (!voxel_of_clamped(P, p, ijk)) { C->esc += E; return; }
+    if (!voxel_of_clamped(P, p, ijk)) { escape(C, E, d, tr); return; }
     int first = 1;
     for (;;) {
         if (E < Y->p_cut) { deposit(C, ijk, E, wgt); return; }
@@ -716,7 +762,7 @@ static void transport_photon(octx *C, xrng *R, double E, double p[3],
             tau -= mu * sb;
             for (int a = 0; a < 3; ++a) p[a] += sb * d[a];
             if (axis < 0 || !step_voxel(P, ijk, axis, d)) {
-                C->esc += E;
+                escape(C, E, d, tr);
                 return;
             }
         }
@@ -736,11 +782,25 @@ static void transport_photon(octx *C, xrng *R, double E, double p[3],
         double dold[3] = {d[0], d[1], d[2]};
         deflect(d, ct, st, phi);
         C->n_interactions++;
-        if (C->trace && first) {
-            /* depth along the incident axis and the scattering cosine */
-            C->trace[0] = p[2];
-            C->trace[1] = ct;
-            C->trace[2] = T;
+        /* recoil electron: momentum conservation, p_e = p_photon - p'
+         * (in MeV/c, photon momentum = its energy) */
+        double pe[3];
+        for (int a = 0; a < 3; ++a) pe[a] = E * dold[a] - Es * d[a];
+        double pn = sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
+        for (int a = 0; a < 3; ++a) pe[a] /= pn;
+        if (tr && first) {
+            double c1[3], c2[3];
+            cross3(dold, d, c1);
+            cross3(dold, pe, c2);
+            double n1 = sqrt(dot3(c1, c1)), n2 = sqrt(dot3(c2, c2));
+            tr[TR_Z] = p[2];
+            tr[TR_COS] = ct;
+            tr[TR_T] = T;
+            tr[TR_E] = E;
+            tr[TR_COSE] = dot3(dold, pe);
+            tr[TR_SIDE] = n1 > 0.0 && n2 > 0.0 ? dot3(c1, c2) / (n1 * n2)
+                                               : NAN;
+            tr[TR_PNORM] = pn / sqrt(T * (T + 2.0 * ME));
         }
         first = 0;
         if (first_only) {
@@ -749,12 +809,8 @@ static void transport_photon(octx *C, xrng *R, double E, double p[3],
             return;
         }
         if (T > Y->t_cut) {
-            double pe[3];
-            for (int a = 0; a < 3; ++a) pe[a] = E * dold[a] - Es * d[a];
-            double pn = sqrt(pe[0] * pe[0] + pe[1] * pe[1] + pe[2] * pe[2]);
-            for (int a = 0; a < 3; ++a) pe[a] /= pn;
             double pp[3] = {p[0], p[1], p[2]};
-            transport_electron(C, R, T, pp, pe, wgt);
+            transport_electron(C, R, T, pp, pe, wgt, NULL);
         } else {
             deposit(C, ijk, T, wgt);
         }
@@ -766,8 +822,9 @@ static void transport_photon(octx *C, xrng *R, double E, double p[3],
  * and accumulate energy x weight per voxel into acc (MeV).  The random
  * stream of particle i is keyed by (seed, uid[i]).  ledger, if given,
  * receives per particle (E0, deposited, escaped, killed) unweighted;
- * trace, if given, receives per particle (z, cos theta, T) of the first
- * photon interaction (NaN if none).  counts[0] += photon interactions,
+ * trace, if given, receives TRACE_N values per particle: the kinematics of
+ * the first photon interaction and the primary's direction at escape (the
+ * TR_* columns; NaN where they do not apply).  counts[0] += photon interactions,
  * counts[1] += electron voxel segments. */
 void oracle_transport(int64_t n, const uint8_t *type, const double *state,
                       const uint64_t *uid, uint64_t seed, const ophantom *P,
@@ -788,7 +845,8 @@ void oracle_transport(int64_t n, const uint8_t *type, const double *state,
         C.acc = acc;
         C.dep = C.esc = C.killed = 0.0;
         C.n_interactions = C.n_segments = 0;
-        double tr[3] = {NAN, NAN, NAN};
+        double tr[TRACE_N];
+        for (int a = 0; a < TRACE_N; ++a) tr[a] = NAN;
         C.trace = trace ? tr : NULL;
         xrng R;
         xseed(&R, seed, uid[i]);
@@ -800,18 +858,15 @@ void oracle_transport(int64_t n, const uint8_t *type, const double *state,
             transport_photon(&C, &R, S[0], p, d, S[7],
                              Y->flags & FLAG_FIRST_COLLISION);
         else
-            transport_electron(&C, &R, S[0], p, d, S[7]);
+            transport_electron(&C, &R, S[0], p, d, S[7], C.trace);
         if (ledger) {
             ledger[4 * i + 0] = S[0];
             ledger[4 * i + 1] = C.dep;
             ledger[4 * i + 2] = C.esc;
             ledger[4 * i + 3] = C.killed;
         }
-        if (trace) {
-            trace[3 * i + 0] = tr[0];
-            trace[3 * i + 1] = tr[1];
-            trace[3 * i + 2] = tr[2];
-        }
+        if (trace)
+            for (int a = 0; a < TRACE_N; ++a) trace[TRACE_N * i + a] = tr[a];
         ni += C.n_interactions;
         ns += C.n_segments;
     }
@@ -827,18 +882,9 @@ void oracle_msc_samples(int64_t n, double T, double t, double X0,
 {
     xrng R;
     xseed(&R, seed, 0);
-    double th0 = oracle_highland(T, t, X0);
     for (int64_t i = 0; i < n; ++i) {
-        double ax, ay, th;
-        do {
-            double u1 = 1.0 - urand(&R), u2 = urand(&R);
-            double rr = sqrt(-2.0 * log(u1));
-            ax = th0 * rr * cos(2.0 * PI * u2);
-            ay = th0 * rr * sin(2.0 * PI * u2);
-            th = sqrt(ax * ax + ay * ay);
-        } while (th > PI);
         double d[3] = {0.0, 0.0, 1.0};
-        deflect(d, cos(th), sin(th), atan2(ay, ax));
+        msc_deflect(&R, T, t, X0, d);
         proj[2 * i + 0] = atan2(d[0], d[2]);
         proj[2 * i + 1] = atan2(d[1], d[2]);
     }

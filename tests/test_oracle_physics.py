@@ -192,6 +192,83 @@ def test_highland_sampler_projected_variance(oracle_lib):
         assert stats.kstest(s[:20000, a] / th0, "norm").pvalue > 1e-3
 
 
+def _slab_then_vacuum(rho, thick):
+    """A slab of density rho and thickness `thick` cm over a vacuum layer of
+    the same thickness, one 200 cm voxel wide laterally."""
+    dens = np.array([rho, 0.0], np.float32).reshape(2, 1, 1)
+    return S.Phantom(dens, (200.0, 200.0, thick), (-100.0, -100.0, 100.0))
+
+
+@pytest.mark.parametrize("T0,rho,step", [(1.0, 1.0, 0.05), (1.0, 0.26, 0.1),
+                                         (6.0, 1.0, 0.1), (3.0, 1.85, 0.1)])
+def test_highland_deflection_inside_transport(oracle_lib, T0, rho, step):
+    """One electron step through a slab exactly one step thick, then
+    vacuum (no further energy loss or scattering): the exit direction is the
+    one deflection the transport loop applied.  Its projected angles must be
+    Gaussian with width theta0 of the Highland formula for the energy at the
+    START of the step and the step's mass thickness rho x step.  (theta0 is
+    kept below 0.3 rad so that no electron turns back into the slab.)"""
+    ph = _slab_then_vacuum(rho, step)
+    n = 40_000
+    st = np.zeros((n, 8))
+    st[:, 0] = T0
+    st[:, 1:3] = 1e-3
+    st[:, 3] = 100.0
+    st[:, 6] = 1.0
+    st[:, 7] = 1.0
+    O = oracle_lib
+    _, _, led, tr = O.transport(np.ones(n, np.uint8), st,
+                                np.arange(n, dtype=np.uint64), 17, ph,
+                                O.ophys(step=step), ledger=True, trace=True)
+    d = tr[:, O.TR_EXIT:O.TR_EXIT + 3]
+    assert np.isfinite(d).all()          # every electron left the box
+    th = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    sp = np.hypot(d[:, 0], d[:, 1])
+    ax = th * d[:, 0] / sp
+    ay = th * d[:, 1] / sp
+    th0 = oracle_lib.highland(T0, rho * step)
+    for a in (ax, ay):
+        # the standard error of a standard deviation is sd / sqrt(2 n)
+        assert a.std() == pytest.approx(th0, rel=5 / math.sqrt(2 * n))
+        assert abs(a.mean()) < 5 * th0 / math.sqrt(n)
+    assert stats.kstest(ax[:20000] / th0, "norm").pvalue > 1e-4
+    assert stats.kstest(th[:20000] / th0, "rayleigh").pvalue > 1e-4
+    # the electron lost the CSDA energy of the slab and nothing after it
+    lost = led[:, 1]
+    S_mid = oracle_lib.stopping_power(T0 - 0.5 * lost.mean())
+    assert lost.mean() == pytest.approx(S_mid * rho * step, rel=5e-3)
+
+
+@pytest.mark.parametrize("E", [0.3, 1.0, 6.0])
+def test_compton_recoil_electron_direction(oracle_lib, E):
+    """Compton kinematics of the recoil electron the transport creates: its
+    angle theta_e to the incident photon obeys
+    cot(theta_e) = (1 + k) tan(theta / 2), k = E / m c^2, theta the photon's
+    scattering angle; it leaves on the opposite side of the incident axis
+    from the scattered photon (azimuths differ by pi); and the momentum
+    E d0 - E' d' has the magnitude sqrt(T (T + 2 m c^2)) of an electron of
+    kinetic energy T = E - E'."""
+    O = oracle_lib
+    ph = S.water_phantom((4, 4, 400), 1.0, (-2.0, -2.0, 100.0))
+    _, _, _, tr = _pencil(O, E, 6000, ph, O.FLAG_FIRST_COLLISION)
+    hit = ~np.isnan(tr[:, O.TR_COS])
+    assert hit.sum() > 3000
+    tr = tr[hit]
+    k = tr[:, O.TR_E] / ME
+    theta = np.arccos(np.clip(tr[:, O.TR_COS], -1.0, 1.0))
+    cot_e = (1.0 + k) * np.tan(theta / 2.0)
+    np.testing.assert_allclose(tr[:, O.TR_COSE],
+                               cot_e / np.sqrt(1.0 + cot_e ** 2), atol=1e-7)
+    side = tr[:, O.TR_SIDE]
+    ok = np.abs(np.sin(theta)) > 1e-6
+    np.testing.assert_allclose(side[ok], -1.0, atol=1e-9)
+    np.testing.assert_allclose(tr[:, O.TR_PNORM], 1.0, rtol=1e-8)
+    # energy of the first interaction: E' = E / (1 + k (1 - cos theta))
+    np.testing.assert_allclose(
+        tr[:, O.TR_T], tr[:, O.TR_E] - tr[:, O.TR_E] /
+        (1.0 + k * (1.0 - tr[:, O.TR_COS])), rtol=1e-12, atol=1e-15)
+
+
 # --------------------------------------------------------- ledger --------
 def test_energy_conservation_per_history(oracle_lib):
     ph = S.heterogeneous_phantom((24, 24, 24), 0.5, (-6.0, -6.0, 100.0), 4)
