@@ -477,6 +477,10 @@ size_t unet_workspace_bytes(const psl_unet *u, int32_t n, int32_t nz,
                             int32_t ny, int32_t nx, int32_t training);
 /* He-normal weights (counter-based, from seed), zero biases, zero head. */
 psl_status unet_init(psl_unet *u, uint64_t seed, void *stream);
+/* Refreshes the bf16 copy from the fp32 master weights (round to nearest
+ * even), after the caller has written u->params (for example weights loaded
+ * from a file in the blob layout above). */
+psl_status unet_set_params(psl_unet *u, void *stream);
 /* d_out [n][nz][ny][nx] = denoised dose (same units as d_dose).  Each axis
  * must be a multiple of 8. */
 psl_status unet_forward(const psl_unet *u, const float *d_dose,

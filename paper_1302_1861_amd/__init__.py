@@ -39,7 +39,8 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_bench_atomics", "psl_plan_workspace_bytes", "psl_plan_create",
            "psl_plan_run", "psl_autotune", "psl_plan_get", "psl_plan_destroy",
            "unet_param_count", "unet_workspace_bytes", "unet_init",
-           "unet_forward", "unet_backward", "unet_adam_step", "dose_denoise",
+           "unet_set_params", "unet_forward", "unet_backward",
+           "unet_adam_step", "dose_denoise",
            "dose_gamma"]
 
 
@@ -218,6 +219,8 @@ def lib():
         L.unet_workspace_bytes.restype = sz
         L.unet_init.argtypes = [vp, u64, vp]
         L.unet_init.restype = i32
+        L.unet_set_params.argtypes = [vp, vp]
+        L.unet_set_params.restype = i32
         L.unet_forward.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, sz,
                                    vp]
         L.unet_forward.restype = i32
@@ -465,13 +468,14 @@ class Denoiser:
                                _stream()))
 
     def set_params(self, blob):
-        """Load fp32 master weights (the documented blob layout); the bf16
-        copy is their round-to-nearest-even rounding."""
-        torch = self.torch
-        t = torch.as_tensor(np.asarray(blob, np.float32)).to(
-            self.params.device)
-        self.params.copy_(t)
-        self.params_bf16.copy_(t.to(torch.bfloat16).view(torch.int16))
+        """Load fp32 master weights (the documented blob layout); the
+        library refreshes the bf16 copy (unet_set_params)."""
+        a = np.ascontiguousarray(blob, np.float32)
+        if a.size != self.n:
+            raise ValueError("blob holds %d floats, the network %d" %
+                             (a.size, self.n))
+        self.params.copy_(self.torch.from_numpy(a))
+        _check(lib().unet_set_params(C.byref(self.net), _stream()))
 
     def _workspace(self, shape, training):
         key = (tuple(shape), training)

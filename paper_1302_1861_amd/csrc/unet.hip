@@ -1746,6 +1746,19 @@ extern "C" psl_status unet_init(psl_unet *u, uint64_t seed, void *stream) {
     return PSL_OK;
 }
 
+extern "C" psl_status unet_set_params(psl_unet *u, void *stream) {
+    PSL_REQUIRE(u && u->params && u->params_bf16, "NULL network");
+    PSL_REQUIRE(u->levels == 4 && u->base == 16, "unsupported architecture");
+    PSL_REQUIRE(u->n_params == make_net(u->base).n_params,
+                "n_params mismatch");
+    if (psl_status s = check_device()) return s;
+    hipLaunchKernelGGL(k_to_bf16, dim3(nblk(u->n_params)), dim3(256), 0,
+                       (hipStream_t)stream, u->params, u->n_params,
+                       u->params_bf16);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
 extern "C" psl_status unet_forward(const psl_unet *u, const float *d_dose,
                                    const float *d_density, int32_t n,
                                    int32_t nz, int32_t ny, int32_t nx,

@@ -297,38 +297,49 @@ class _Judge:
         return math.sqrt(max(e * e - self.s_ref ** 2, 0.0)), g
 
 
+PLAIN_LADDER = tuple(int(v) for v in (1e6, 2e6, 3e6, 5e6, 7e6, 1e7, 1.5e7,
+                                       2e7, 3e7, 5e7, 7e7, 1e8, 1.5e8, 2e8))
+DENOISED_LADDER = tuple(int(v) for v in (3e6, 5e6, 1e7, 2e7, 5e7))
+
+
+def tally_batches(n, max_hpb=10_000_000):
+    """The fewest batches the tally accepts (two) with at most max_hpb
+    histories each.  Every side of the time-to-accuracy comparison runs at
+    this count: all of them are judged against an independent reference,
+    none by its own batch sigma."""
+    return max(2, -(-int(n) // max_hpb))
+
+
 def denoise_vs_plain(pm: PairMaker, net, draw=EVAL_SEED0 + 900,
                      n_ref=int(1e9), target=0.01, gamma_target=0.99,
-                     in_ladder=(int(1e7), int(2e7), int(5e7)),
-                     plain_ladder=(int(1e7), int(2e7), int(5e7), int(1e8),
-                                   int(2e8))):
-    """Time to a dose accuracy, PSL + denoiser against plain MC (the same
-    PSL engine without the network), on one held-out draw.  Plain MC runs
-    at least 10 batches (its uncertainty comes from batch statistics); the
-    denoiser's input runs in at least 2 batches (the tally's minimum) of up
-    to 1e7 histories.
+                     in_ladder=DENOISED_LADDER, plain_ladder=PLAIN_LADDER,
+                     pm_unsorted: PairMaker = None):
+    """Time to a dose accuracy on one held-out draw, for three variants
+    judged the same way:
+      * psl_denoise: the PSL engine at `in_ladder` histories, then the
+        network;
+      * plain: the same PSL engine without the network (plain MC);
+      * plain_unsorted (if pm_unsorted is given): the plain-method analogue,
+        phase space in file order, no ROI cull, no re-bucketing.
+    Every rung runs in the same number of batches for a given history count
+    (tally_batches), so the per-batch cost is the same on every side.
 
     Accuracy is judged against an independent n_ref run (_Judge): RMS error
     <= `target` of the maximum, and gamma 2%/2mm >= `gamma_target`.  Every
     rung is a live, timed run (sampling, transport, tally and, for the
     denoised rungs, the network) with engines built and the phantom and
-    field loaded beforehand.  For plain
-    MC the time to `target` is also measured directly: the history count
-    that the 1/sqrt(N) law predicts from the first rung is run and judged
-    (and raised again if it falls short)."""
+    field loaded beforehand.  A variant's time to a criterion is the fastest
+    rung that meets it; `speedup` is plain's time over psl_denoise's."""
     import torch
 
-    def timed(n, seed, den):
-        # Plain MC states its uncertainty from batch statistics, so it runs
-        # at least 10 batches; the denoised dose has no batch sigma and runs
-        # in as few batches as the tally accepts (two) and the engine holds
-        # (at most 1e7 histories each).  The phantom and field upload is
-        # common to both sides and stays outside the clock.
-        nb = den_batches(n) if den else batches_for(n)
-        eng = pm.prepare(ph, f, n, nb)
+    def timed(maker, n, seed, den):
+        # the phantom and field upload is common to every side and stays
+        # outside the clock
+        nb = tally_batches(n)
+        eng = maker.prepare(ph, f, n, nb)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        d, _, rho = pm.run(eng, seed, nb)
+        d, _, rho = maker.run(eng, seed, nb)
         if den:
             d = net.denoise(d, rho)
         torch.cuda.synchronize()
@@ -341,28 +352,20 @@ def denoise_vs_plain(pm: PairMaker, net, draw=EVAL_SEED0 + 900,
     ref, sref, _ = pm.dose(ph, f, n_ref, draw + 3 * MC_SEED_OFFSET,
                            batches_for(n_ref))
     judge = _Judge(ref, sref, pm.voxel)
-    def den_batches(n):
-        return max(2, -(-int(n) // 10_000_000))
-
-    for n in plain_ladder:
-        pm.engine(int(n // batches_for(n)))
-    for n in in_ladder:
-        pm.engine(int(n // den_batches(n)))
-    timed(in_ladder[0], draw + 5 * MC_SEED_OFFSET, True)       # warm-up
+    makers = [(pm, plain_ladder), (pm, in_ladder)]
+    if pm_unsorted is not None:
+        makers.append((pm_unsorted, plain_ladder))
+    for maker, ladder in makers:
+        for n in ladder:
+            maker.engine(int(n // tally_batches(n)))
+    timed(pm, in_ladder[0], draw + 5 * MC_SEED_OFFSET, True)       # warm-up
     seed = draw + 4 * MC_SEED_OFFSET
-    den = [timed(n, seed, True) for n in in_ladder]
-    plain = [timed(n, seed, False) for n in plain_ladder]
-    direct = []
-    c, n = plain[0]["rms_error"], plain[0]["histories"]
-    for k in range(3):
-        # aim at the target itself first, then 10% past it
-        n = int(math.ceil(n * (c / target) ** 2 * (1.0 if k == 0 else 1.1)
-                          / 1e6)) * int(1e6)
-        pm.engine(int(n // batches_for(n)))
-        direct.append(timed(n, seed, False))
-        c = direct[-1]["rms_error"]
-        if c <= target:
-            break
+    den = [timed(pm, n, seed, True) for n in in_ladder]
+    plain = [timed(pm, n, seed, False) for n in plain_ladder]
+    unsorted = []
+    if pm_unsorted is not None:
+        timed(pm_unsorted, plain_ladder[0], draw + 5 * MC_SEED_OFFSET, False)
+        unsorted = [timed(pm_unsorted, n, seed, False) for n in plain_ladder]
 
     def first(rungs, key, ok):
         hit = [r for r in rungs if ok(r[key])]
@@ -373,20 +376,31 @@ def denoise_vs_plain(pm: PairMaker, net, draw=EVAL_SEED0 + 900,
 
     err_ok = (lambda v: v <= target)
     gam_ok = (lambda v: v >= gamma_target)
-    t1_plain = first(plain + direct, "rms_error", err_ok)
-    t1_den = first(den, "rms_error", err_ok)
-    g_plain = first(plain + direct, "gamma", gam_ok)
-    g_den = first(den, "gamma", gam_ok)
-    return {"draw": draw, "voxel_cm": pm.voxel, "shape": list(pm.shape),
-            "reference_histories": int(n_ref),
-            "reference_noise": judge.s_ref,
-            "criterion": {"rms_error_of_max": target,
-                          "gamma_2pct_2mm": gamma_target},
-            "time_to_error": {"plain": t1_plain, "psl_denoise": t1_den,
-                              "speedup": ratio(t1_plain, t1_den)},
-            "time_to_gamma": {"plain": g_plain, "psl_denoise": g_den,
-                              "speedup": ratio(g_plain, g_den)},
-            "rungs_denoised": den, "rungs_plain": plain + direct}
+    out = {"draw": draw, "voxel_cm": pm.voxel, "shape": list(pm.shape),
+           "reference_histories": int(n_ref),
+           "reference_noise": judge.s_ref,
+           "criterion": {"rms_error_of_max": target,
+                         "gamma_2pct_2mm": gamma_target},
+           "batches": "tally_batches(n) = max(2, ceil(n / 1e7)) on every "
+                      "side"}
+    for name, key, ok in (("time_to_error", "rms_error", err_ok),
+                          ("time_to_gamma", "gamma", gam_ok)):
+        rec = {"plain": first(plain, key, ok),
+               "psl_denoise": first(den, key, ok)}
+        if pm_unsorted is not None:
+            rec["plain_unsorted"] = first(unsorted, key, ok)
+        rec["speedup"] = ratio(rec["plain"], rec["psl_denoise"])
+        if pm_unsorted is not None:
+            rec["speedup_vs_unsorted"] = ratio(rec["plain_unsorted"],
+                                               rec["psl_denoise"])
+            rec["psl_over_unsorted"] = ratio(rec["plain_unsorted"],
+                                             rec["plain"])
+        out[name] = rec
+    out["rungs_denoised"] = den
+    out["rungs_plain"] = plain
+    if pm_unsorted is not None:
+        out["rungs_plain_unsorted"] = unsorted
+    return out
 
 
 def compare_time_to_gamma(pm: PairMaker, pm_plain: PairMaker, net, n_draws,
