@@ -139,9 +139,13 @@ __device__ __forceinline__ void tally(void *acc, int64_t v, float e, float wt,
                                       double scale, uint32_t &n_dep) {
     ++n_dep;
     if (MODE == PSL_ACC_FIXED64) {
-        double q = (double)e * (double)wt * scale + 0.5;
+        // the product of two floats is exact in double; rounded to the
+        // nearest step, ties to even (rounding ties up biased the sum:
+        // sub-p_cut photon deposits at weight 1/4 are exact halves half of
+        // the time); two's complement, so a negative value subtracts
+        const double q = __builtin_rint((double)e * (double)wt * scale);
         atomicAdd(reinterpret_cast<unsigned long long *>(acc) + v,
-                  (unsigned long long)q);
+                  (unsigned long long)(long long)q);
     } else {
         unsafeAtomicAdd(reinterpret_cast<double *>(acc) + v,
                         (double)e * (double)wt);

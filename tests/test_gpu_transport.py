@@ -80,6 +80,46 @@ def test_fold_and_finalize_match_numpy():
     np.testing.assert_allclose(sig.cpu().numpy(), ws, rtol=1e-5, atol=1e-30)
 
 
+def test_fixed_point_tally_within_rounding_bound_of_fp64():
+    """The same histories tallied in u64 fixed point (2^-32 MeV) and in
+    FP64 (the transport is keyed by history id, so both runs deposit the
+    same energies in the same voxels): each deposit is rounded to the
+    nearest 2^-32 MeV, so the summed absolute difference over voxels is at
+    most (number of deposits) x 2^-33 MeV, and the signed total is a sum of
+    independent roundings of zero mean and variance at most 2^-66, within 6
+    of its largest standard deviation 2^-33 sqrt(N) (a truncating
+    conversion would bias it by about N 2^-33; rounding exact halves up
+    biased it by 0.011 N 2^-32 here, 2.9 times this bound)."""
+    import torch
+    wl = S.workload_clinical(side=10.0, n_particles=500_000)
+    wl.phantom = S.water_phantom((64, 64, 64), 0.5, (-16.0, -16.0, 100.0))
+    out, st = {}, None
+    for fixed in (True, False):
+        wl.fixed_point = fixed
+        eng = _engine(wl, 300_000)
+        eng.sample(3)
+        eng.transport(3)
+        torch.cuda.synchronize()
+        a = eng.acc_t.cpu().numpy()
+        out[fixed] = (a.astype(np.float64) * 2.0 ** -32 if fixed
+                      else a.astype(np.float64))
+        s = eng.stats_dict()
+        n_dep = s["deposits"] + s["photon_deposits"]
+        if st is not None:
+            assert n_dep == st, "the two runs deposited differently"
+        st = n_dep
+    d = out[True] - out[False]
+    # FP64 atomics round too (at most n_v eps |acc_v| per voxel), far
+    # below the fixed-point step
+    fp64 = 1e-12 * np.abs(out[False]).sum()
+    sd = 2.0 ** -33 * np.sqrt(st)
+    _say("deposits", st, "sum |d|", np.abs(d).sum(), "bound",
+         st * 2.0 ** -33, "signed", d.sum(), "sd bound", sd)
+    assert st > 100_000 and np.abs(out[False]).sum() > 0
+    assert np.abs(d).sum() <= st * 2.0 ** -33 + fp64
+    assert abs(d.sum()) <= 6 * sd + fp64
+
+
 # ------------------------------------------------- closed-form transport --
 def test_first_collision_dose_closed_form():
     """Broad parallel 1.25 MeV beam over the whole face of a water block,
@@ -331,3 +371,82 @@ def test_dose_gamma_against_high_statistics_oracle():
                                     threshold=0.1)
     _say("gamma 2%/2mm", rate)
     assert rate >= 0.99
+
+
+# ------------------------- high-statistics oracle doses at full size ------
+def _golden_hetero_lung():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_oracle_dose", os.path.join(GOLDEN, "make_oracle_dose.py"))
+    m = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(m)
+    return m
+
+
+GOLDEN_FULL = {
+    # name: (workload, GPU histories, batches)
+    "clinical10": (lambda: S.workload_clinical(side=10.0), 1_000_000_000, 50),
+    "hetero": (lambda: S.workload_heterogeneous(), 300_000_000, 50),
+    "hetero_lung": (lambda: _golden_hetero_lung().hetero_lung_workload(),
+                    300_000_000, 50),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GOLDEN_FULL))
+def test_dose_against_high_statistics_oracle_full_size(name):
+    """Full-size workloads against the oracle's high-statistics dose
+    (written by tests/golden/make_oracle_dose.py, which calls only the
+    oracle): the clinical 10x10 cm field on 128^3 water at 2.5 mm with ROI
+    culling and the u64 fixed-point tally, and the heterogeneous
+    256x256x160 phantom at 2 mm with its jaws and fluence map (and the
+    same with the beam through the lung).  Above the 10% isodose: at least
+    99% of voxels within |z| <= 3, |mean z| < 0.1, sd of z in [0.9, 1.1];
+    gamma 2%/2mm (Table 1's criterion) >= 99% with the oracle as the
+    reference."""
+    import torch
+    m = _golden_hetero_lung()
+    path = os.path.join(GOLDEN, "oracle_dose_%s.npz" % name)
+    assert os.path.exists(path), "missing " + path
+    d_o, s_o, keep = m.load_sparse(path)
+    make, hist, B = GOLDEN_FULL[name]
+    wl = make()
+    shp = wl.phantom.density.shape
+    assert d_o.shape == shp
+    _say(name, "GPU", hist, "histories in", B, "batches")
+    eng = _engine(wl, hist // B)
+    for b in range(B):
+        eng.step(b)
+    d_g, s_g = eng.finalize()
+    torch.cuda.synchronize()
+    d_g = d_g.cpu().numpy().astype(np.float64).reshape(shp)
+    s_g = s_g.cpu().numpy().astype(np.float64).reshape(shp)
+    del eng
+    torch.cuda.empty_cache()
+    # the oracle stores voxels at or above 5% of its maximum; the 10%
+    # isodose region (on the mean of the two doses) lies inside it
+    mean = 0.5 * (d_g + np.nan_to_num(d_o))
+    region = mean >= 0.1 * mean.max()
+    assert keep[region].mean() > 0.999
+    region &= keep
+    z = (d_g[region] - d_o[region]) / np.sqrt(s_g[region] ** 2 +
+                                              s_o[region] ** 2)
+    stats = {"n": int(z.size), "frac_le3": float((np.abs(z) <= 3).mean()),
+             "mean": float(z.mean()), "sd": float(z.std())}
+    # gamma on the oracle's side: every shift of the evaluated (GPU) dose
+    # on a 1 mm grid inside the 2 mm sphere (a coarser search than the
+    # 0.4 mm one, so the pass rate is a lower bound), over the box that
+    # holds the region plus the search radius
+    ref = np.nan_to_num(d_o)
+    nz = np.nonzero(ref >= 0.1 * ref.max())
+    pad = 2
+    sl = tuple(slice(max(0, int(a.min()) - pad), int(a.max()) + pad + 1)
+               for a in nz)
+    vox = (wl.phantom.voxel[2], wl.phantom.voxel[1], wl.phantom.voxel[0])
+    rate = analysis.gamma_pass_rate(ref[sl], d_g[sl], vox, dose_crit=0.02,
+                                    dta=0.2, threshold=0.1, step=0.1)
+    _say(name, "z", stats, "gamma 2%/2mm", rate)
+    assert stats["frac_le3"] >= 0.99
+    assert abs(stats["mean"]) < 0.1
+    assert 0.9 <= stats["sd"] <= 1.1
+    assert rate >= 0.99
+
