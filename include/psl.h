@@ -217,6 +217,30 @@ psl_status psl_sample(const psl_phsp *sorted, const int64_t *d_offsets,
                       psl_stats *d_stats, void *d_ws, size_t ws_bytes,
                       void *stream);
 
+/*
+ * psl_sample_noalloc - psl_sample without a workspace argument, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and errors as psl_sample; the workspace is a static device array of
+ * psl_sample_noalloc_max_bytes() (64 MiB) that each GPU holds from the
+ * first call on it until the process ends.  That bounds the problem: one
+ * field of a 2 x 32 x 22 x 22 grid takes about 1.4M histories per call.
+ * Larger requests fail with PSL_ENOSPC before anything is enqueued.  The
+ * call allocates nothing (no hipMalloc, no hipFree).
+ * Every call on one GPU uses that GPU's one array, which keeps the last
+ * call's contents (the sampling writes everything it later reads, so stale
+ * contents do not matter): calls that overlap on one GPU (several host
+ * threads, or several streams without ordering between them) race, and the
+ * caller must order them.
+ */
+size_t psl_sample_noalloc_max_bytes(void);
+psl_status psl_sample_noalloc(const psl_phsp *sorted,
+                              const int64_t *d_offsets, const psl_grid *g,
+                              const psl_field *fields, int32_t n_fields,
+                              const psl_sample_cfg *cfg, psl_queue *q,
+                              uint8_t *d_mask, int64_t *d_alloc,
+                              psl_stats *d_stats, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Transport.                                                                */
 /* ------------------------------------------------------------------------ */

@@ -41,7 +41,8 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "unet_param_count", "unet_workspace_bytes", "unet_init",
            "unet_set_params", "unet_forward", "unet_backward",
            "unet_adam_step", "dose_denoise",
-           "dose_gamma"]
+           "dose_gamma", "psl_sample_noalloc_max_bytes",
+           "psl_sample_noalloc"]
 
 
 class PslError(RuntimeError):
@@ -183,6 +184,11 @@ def lib():
         L.psl_sample.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, vp,
                                  sz, vp]
         L.psl_sample.restype = i32
+        L.psl_sample_noalloc_max_bytes.argtypes = []
+        L.psl_sample_noalloc_max_bytes.restype = sz
+        L.psl_sample_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp,
+                                         vp, vp]
+        L.psl_sample_noalloc.restype = i32
         L.psl_physics_init.argtypes = [vp, vp, vp]
         L.psl_physics_init.restype = i32
         L.transport_batch_workspace_bytes.argtypes = [vp]
@@ -352,6 +358,20 @@ def psl_sample(sorted_phsp: Dict, offsets, grid: psl_grid, fields_arr,
                             C.byref(queue), _ptr(mask), _ptr(alloc),
                             _ptr(stats), _ptr(ws),
                             ws.numel() * ws.element_size(), _stream(stream)))
+
+
+def psl_sample_noalloc(sorted_phsp: Dict, offsets, grid: psl_grid,
+                       fields_arr, cfg: psl_sample_cfg, queue: psl_queue,
+                       stats, mask=None, alloc=None, n_sorted=None,
+                       stream=None):
+    """psl_sample with the library's static scratch instead of a
+    workspace (for callers that cannot allocate)."""
+    s = make_phsp(sorted_phsp, n_sorted)
+    _check(lib().psl_sample_noalloc(C.byref(s), _ptr(offsets),
+                                    C.byref(grid), fields_arr,
+                                    len(fields_arr), C.byref(cfg),
+                                    C.byref(queue), _ptr(mask), _ptr(alloc),
+                                    _ptr(stats), _stream(stream)))
 
 
 def psl_physics_init(phys: psl_physics, tables, stream=None):

@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 namespace psl {
@@ -639,4 +640,81 @@ extern "C" psl_status psl_sample(const psl_phsp *sorted,
     if ((s = sample_alloc(ctx, st))) return s;
     if ((s = set_i64(ctx.w.batch, cfg->batch, st))) return s;
     return sample_batch(ctx, ctx.w.batch, st);
+}
+
+// ------------------------------------------------ allocation-free variant --
+// psl_sample with its workspace in a file-scope device array instead of a
+// caller buffer.  Each GPU the library runs on holds its own copy of the
+// array (kNoAllocScratchBytes) until the process ends; host code reaches it
+// only through the address hipGetSymbolAddress returns for the current
+// device (the array's name in host code is a host-side stand-in).
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+psl_status scratch_address(void **out) {
+    int dev = 0;
+    PSL_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices) {
+        set_error("device %d: psl_sample_noalloc supports devices 0..%d",
+                  dev, kNoAllocMaxDevices - 1);
+        return PSL_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                      hipGetErrorString(e));
+            return PSL_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return PSL_OK;
+}
+
+}  // namespace
+
+extern "C" size_t psl_sample_noalloc_max_bytes(void) {
+    return kNoAllocScratchBytes;
+}
+
+extern "C" psl_status psl_sample_noalloc(const psl_phsp *sorted,
+                                         const int64_t *d_offsets,
+                                         const psl_grid *g,
+                                         const psl_field *fields,
+                                         int32_t n_fields,
+                                         const psl_sample_cfg *cfg,
+                                         psl_queue *q, uint8_t *d_mask,
+                                         int64_t *d_alloc,
+                                         psl_stats *d_stats, void *stream) {
+    PSL_REQUIRE(g && cfg, "NULL argument");
+    PSL_REQUIRE(n_fields >= 1 && cfg->n_histories >= 0,
+                "n_fields = %d, n_histories = %lld", n_fields,
+                (long long)cfg->n_histories);
+    const size_t need =
+        psl_sample_workspace_bytes(g, n_fields, cfg->n_histories);
+    if (need == 0 || need > kNoAllocScratchBytes) {
+        set_error("psl_sample_noalloc: this grid, %d field(s) and %lld "
+                  "histories need %zu bytes of scratch; the static scratch "
+                  "holds %zu (use psl_sample with a workspace)",
+                  n_fields, (long long)cfg->n_histories, need,
+                  kNoAllocScratchBytes);
+        return PSL_ENOSPC;
+    }
+    psl_status s;
+    void *ws = nullptr;
+    if ((s = check_device())) return s;
+    if ((s = scratch_address(&ws))) return s;
+    return psl_sample(sorted, d_offsets, g, fields, n_fields, cfg, q, d_mask,
+                      d_alloc, d_stats, ws, kNoAllocScratchBytes, stream);
 }
