@@ -69,19 +69,32 @@ def _traffic(group):
     return rec["bytes_per_launch"]
 
 
+# Algorithmic HBM bytes (the byte model of the design notes): a queue entry
+# is 44 B (E x y z u v w wt f32, uid u64, ctr u32; the queue, not a type
+# byte, carries the particle type), read once by the kernel that transports
+# it and written once by the kernel that creates it; a dose deposit is one
+# 8 B atomic read-modify-write of the accumulator; a sampled history reads
+# its 29 B phase-space particle.  Density and table reads are not counted:
+# the 8.4 MB (clinical) to 42 MB (heterogeneous) density stays resident in
+# the L2 and Infinity Cache.
+QUEUE_ENTRY_B = 44
+DEPOSIT_B = 8
+PARTICLE_B = 29
+
+
 def _algorithmic_bytes(group, st, nvox):
     """Algorithmic HBM bytes of one launch of a kernel group, from the
-    batch statistics (definitions in the design notes)."""
-    q = 44  # queue entry: E x y z u v w wt (32) + uid (8) + ctr (4)
+    batch statistics."""
+    q = QUEUE_ENTRY_B
     if group == "electrons":
-        n_el = st["electrons"] + st["secondaries"]
-        return q * n_el + 16 * st["deposits"] + 4 * st["segments"]
+        return q * (st["electrons"] + st["secondaries"]) + \
+            DEPOSIT_B * st["deposits"]
     if group == "photons":
-        return (q * st["photons"] + 4 * st["flights"] + q * st["secondaries"]
-                + 16 * st["photon_deposits"])
+        return (q * st["photons"] + q * st["secondaries"]
+                + DEPOSIT_B * st["photon_deposits"])
     if group == "sample":
         acc = st["photons"] + st["electrons"]
-        return 29 * st["histories"] + q * acc
+        return PARTICLE_B * st["histories"] + q * acc
     if group == "fold":
         return 48 * nvox
     return None
@@ -122,7 +135,17 @@ def bench_imrt(P, S, torch, hpb, n_batches):
         plan.run(0, n_batches, use_graph=True)
         stream.synchronize()
         dt = time.perf_counter() - t0
+        # kernel times of one batch run eagerly (the graph replays the same
+        # launches; events are not recorded inside a captured graph)
+        P.profile_read(reset=True)
+        P.profile_enable(True)
+        plan.run(n_batches, 1, use_graph=False)
+        stream.synchronize()
+        P.profile_enable(False)
+        groups = _kernel_groups(P.profile_read(reset=True))
     st = eng.stats_dict()
+    roof = hbm_roofline(groups, st, eng.nvox)
+    atom = atomic_roofline(P, eng, groups, st, 0, replay=False)
     plan.destroy()
     return {"workload": "IMRT-like plan: 7 coplanar beams x 20 segments, "
                         "MU-proportional, 128^3 water at 2.5 mm, "
@@ -135,6 +158,9 @@ def bench_imrt(P, S, torch, hpb, n_batches):
                       "n_ebuckets": r.n_ebuckets,
                       "configs_tried": r.configs_tried,
                       "tune_ms_per_batch": r.ms_per_batch},
+            "roofline": roof, "atomic_rate": atom["achieved"],
+            "kernel_ms": {g: round(v[0] / v[1], 4)
+                          for g, v in groups.items()},
             "lost": st["lost"]}
 
 
@@ -206,9 +232,20 @@ def bench_time_to_accuracy(n_draws=3):
     return out
 
 
-def cpu_baseline(wl, hist_target_s, threads):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(wl, hist_target_s, threads, single_s):
     """The oracle, as it stands, on a bounded sample of the same workload:
-    PSL build (untimed), then batches of sampling + transport + fold."""
+    PSL build (untimed), then one batch of sampling + transport + fold on
+    `threads` threads (the headline figure) and one on a single thread."""
     import numpy as np
     import oracle
     oracle.build(force=False)
@@ -220,29 +257,209 @@ def cpu_baseline(wl, hist_target_s, threads):
     s1 = np.zeros(nvox)
     s2 = np.zeros(nvox)
 
-    def batch(b, H):
+    def batch(b, H, nt):
         N, g, _ = oracle.alloc(wl.fields, wl.alloc_mode, H, off, mask,
                                wl.grid)
         S_ = oracle.sample(wl.fields, geom, off, N, g, b, wl.seed, sps)
         ok = S_["status"] == 1
         acc, _, _, _ = oracle.transport(S_["type"][ok], S_["state"][ok],
                                         S_["uid"][ok], wl.seed, wl.phantom,
-                                        n_threads=threads)
+                                        n_threads=nt)
         oracle.fold(acc, s1, s2)
 
-    t0 = time.perf_counter()
-    batch(0, 300_000)
-    dt = time.perf_counter() - t0
-    rate0 = 300_000 / max(dt, 1e-6)
-    H = int(min(max(rate0 * hist_target_s, 20_000), 50_000_000))
-    t0 = time.perf_counter()
-    batch(1, H)
-    dt = time.perf_counter() - t0
-    return {"value": H / dt, "unit": "histories/s", "cores": threads,
+    def timed(b, target_s, nt, probe):
+        t0 = time.perf_counter()
+        batch(b, probe, nt)
+        rate0 = probe / max(time.perf_counter() - t0, 1e-6)
+        H = int(min(max(rate0 * target_s, 20_000), 50_000_000))
+        t0 = time.perf_counter()
+        batch(b + 1, H, nt)
+        dt = time.perf_counter() - t0
+        return H / dt, H, dt
+
+    v, H, dt = timed(0, hist_target_s, threads, 300_000)
+    v1, H1, dt1 = timed(2, single_s, 1, 20_000)
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"value": v, "unit": "histories/s", "cores": threads,
             "kind": "oracle",
             "sample": "%d histories of the same workload in one batch "
                       "(sampling + transport + fold, %.1f s, PSL build "
-                      "excluded)" % (H, dt)}
+                      "excluded)" % (H, dt),
+            "single_thread": {"value": v1, "unit": "histories/s",
+                              "sample": "%d histories, %.1f s" % (H1, dt1)},
+            "host": {"nproc": os.cpu_count(), "affinity": affinity,
+                     "omp_num_threads": os.environ.get("OMP_NUM_THREADS"),
+                     "cpu_model": _cpu_model()}}
+
+
+def _kernel_groups(prof):
+    return {g: v for g, v in prof.items() if v[1] > 0}
+
+
+def hbm_roofline(groups, st, nvox):
+    """HBM roofline of the dominant kernel (the one with the most time
+    among those with algorithmic bytes defined)."""
+    dom = max((g for g in groups if g in KERNEL_OF_GROUP),
+              key=lambda g: groups[g][0])
+    avg_ms = groups[dom][0] / groups[dom][1]
+    nbytes = _algorithmic_bytes(dom, st, nvox)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": _traffic(dom),
+            "algorithmic_bytes_per_launch": nbytes, "avg_launch_ms": avg_ms}
+
+
+def atomic_roofline(P, eng, groups, st, batch, replay=True):
+    """Dose atomics of the transport kernels against the roof of their own
+    address pattern: one batch's deposit addresses are recorded (trace
+    mode) and replayed as u64 atomic adds at 1-16 blocks of 256 per CU;
+    the roof is the fastest replay."""
+    def avg(g):
+        v = groups.get(g)
+        return v[0] / v[1] * 1e-3 if v else 0.0
+    t_ph, t_el = avg("photons"), avg("electrons")
+    n_atom = st["deposits"] + st["photon_deposits"]
+    achieved = n_atom / (t_ph + t_el) if t_ph + t_el > 0 else 0.0
+    out = {"kernels": "photons+electrons", "achieved": achieved,
+           "unit": "u64 atomic adds/s", "atomics_per_step": n_atom}
+    if not replay:
+        return out
+    trace, n = eng.deposit_trace(batch)
+    sweep = P.bench_atomics_replay(trace, eng.nvox)
+    del trace
+    peak = max(sweep.values())
+    uniform, same = P.bench_atomics(eng.nvox)
+    out.update({
+        "peak": peak, "frac": achieved / peak,
+        "per_kernel_frac": {
+            "photons": st["photon_deposits"] / t_ph / peak if t_ph else 0,
+            "electrons": st["deposits"] / t_el / peak if t_el else 0},
+        "roof": "replay of %d recorded deposit addresses, best of "
+                "blocks_per_cu sweep" % n,
+        "replay_by_blocks_per_cu": sweep, "uniform_scatter_peak": uniform,
+        "same_address_peak": same})
+    return out
+
+
+def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
+                     replay=True, source="psl"):
+    """Times `steps` batches of H histories of one workload (after
+    `warmup` batches) and derives the rooflines.  Returns (record,
+    engine)."""
+    eng = P.Engine(wl, histories_per_batch=H, launch=launch, source=source)
+    for b in range(warmup):
+        eng.step(b)
+    torch.cuda.synchronize()
+    eng.reset_tally()
+    P.profile_read(reset=True)
+    P.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        eng.step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    P.profile_enable(False)
+    groups = _kernel_groups(P.profile_read(reset=True))
+    st = eng.stats_dict()
+    if st["lost"]:
+        raise SystemExit("queue overflow: batch invalid (%s)" % wl.name)
+    d, s = eng.finalize()
+    torch.cuda.synchronize()
+    d = d.cpu().numpy()
+    s = s.cpu().numpy()
+    sel = d >= 0.5 * d.max()
+    sbar = float((s[sel] / d[sel]).mean())
+    rec = {"workload": wl.name, "source": source,
+           "histories_per_step": H, "steps": steps,
+           "histories_per_s": steps * H / elapsed,
+           "ms_per_step": 1e3 * elapsed / steps,
+           "roofline": hbm_roofline(groups, st, eng.nvox),
+           "atomic_roofline": atomic_roofline(P, eng, groups, st, steps,
+                                              replay),
+           "kernel_ms": {g: round(v[0] / v[1], 4) for g, v in groups.items()},
+           "batch_stats": {k: st[k] for k in (
+               "histories", "photons", "electrons", "jaw_rejected",
+               "interactions", "secondaries", "segments", "deposits",
+               "photon_deposits", "flights")},
+           "mean_rel_sigma_50pct": sbar,
+           "time_to_1pct_s": elapsed * (sbar / 0.01) ** 2}
+    return rec, eng
+
+
+def bench_methods(P, torch, S, H, steps=10, sides=(4.0, 10.0, 30.0)):
+    """The paper's Method 2 against Method 3 (PSL) on the open fields:
+    Method 2 reads the phase space in file order and collimates every
+    particle with the jaw model (on-the-fly bins of 2^20), PSL samples only
+    the PSLs its ROI selects.  Both estimate the same dose; they are
+    compared by the time to 1% mean uncertainty above the 50% isodose,
+    T_run (sigma / 1%)^2, from `steps` batches of H histories each."""
+    out = []
+    for side in sides:
+        wl = S.workload_clinical(side=side)
+        rec = {"field_cm": side}
+        for src in ("psl", "method2"):
+            r, e = measure_workload(P, torch, wl, H, steps, 2, replay=False,
+                                    source=src)
+            del e
+            torch.cuda.empty_cache()
+            rec[src] = {k: r[k] for k in (
+                "histories_per_s", "ms_per_step", "mean_rel_sigma_50pct",
+                "time_to_1pct_s", "kernel_ms")}
+            rec[src]["accepted_per_step"] = (r["batch_stats"]["photons"] +
+                                             r["batch_stats"]["electrons"])
+        rec["method2_over_psl_time_to_1pct"] = \
+            rec["method2"]["time_to_1pct_s"] / rec["psl"]["time_to_1pct_s"]
+        out.append(rec)
+        print("methods %g cm done" % side, file=sys.stderr, flush=True)
+    return out
+
+
+def bench_build(P, torch, S, sizes=(10_000_000, 100_000_000, 500_000_000),
+                reps=3):
+    """psl_build (commissioning) at several phase-space sizes: the seeded
+    1e7-particle clinical phase space repeated on the device to the size,
+    so the key distribution is the clinical one.  Algorithmic bytes: 13
+    read for the key (type, E, x, y), 29 read and 29 written for the
+    payload."""
+    import ctypes as C
+    base = S.phase_space(10_000_000, 1002, 20.0, S.Z_PSL)
+    grid = S.clinical_grid()
+    g = P.make_grid(grid.e_edges, grid.x_edges, grid.y_edges, grid.z_plane)
+    raw0 = P.Buffers.phsp_from_numpy(base, "cuda")
+    out = []
+    for n in sizes:
+        rep = -(-n // base.n)
+        raw = {k: v.repeat(rep)[:n].contiguous() for k, v in raw0.items()}
+        srt = P.Buffers.phsp(n, "cuda")
+        off = torch.zeros(grid.n_keys + 1, dtype=torch.int64, device="cuda")
+        nd = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ws = torch.empty(P.lib().psl_build_workspace_bytes(n, C.byref(g)),
+                         dtype=torch.uint8, device="cuda")
+        P.psl_build(raw, g, srt, off, nd, ws)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            P.psl_build(raw, g, srt, off, nd, ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = 71.0 * n / (ms * 1e-3) / 1e9
+        out.append({"particles": n, "ms": ms, "achieved": gbs,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": gbs / HBM_PEAK_GBS,
+                    "algorithmic_bytes_per_particle": 71})
+        print("psl_build %d particles: %.2f ms" % (n, ms), file=sys.stderr,
+              flush=True)
+        del raw, srt, ws
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -253,15 +470,18 @@ def main():
     ap.add_argument("--field", type=float, default=10.0)
     ap.add_argument("--histories-per-step", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-single-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the IMRT-plan and denoiser measurements")
+                    help="skip every measurement beside the main workload")
+    ap.add_argument("--no-replay", action="store_true",
+                    help="skip the atomic-roof replay of the main workload")
     ap.add_argument("--rebucket", type=int, default=None, choices=(0, 1),
                     help="re-bucket secondary electrons (default: library)")
     ap.add_argument("--blocks-per-cu", type=int, default=None)
     ap.add_argument("--extras-only", action="store_true",
-                    help="only the IMRT-plan and denoiser measurements (for "
-                         "profiling them apart from the main workload)")
+                    help="only the measurements beside the main workload "
+                         "(for profiling them apart from it)")
     ap.add_argument("--imrt-batches", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="device-to-device copy of this size before the "
@@ -274,12 +494,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import psl_synth as S
     import paper_1302_1861_amd as P
 
-    wl = S.workload_clinical(side=args.field)
     H = args.histories_per_step
     launch = None
     if args.rebucket is not None or args.blocks_per_cu is not None:
@@ -289,18 +507,46 @@ def main():
         if args.blocks_per_cu is not None:
             kw["blocks_per_cu"] = args.blocks_per_cu
         launch = P.make_launch(**kw)
-    eng = P.Engine(wl, histories_per_batch=H, launch=launch)
+
+    def say(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    def extras(out, eng):
+        nz, ny, nx = eng.wl.phantom.density.shape
+        out["denoiser"] = bench_denoiser(P, torch, eng.dose, eng.density,
+                                         (nz, ny, nx))
+        say("denoiser done")
+        # the other open fields and the heterogeneous workload at their
+        # own sizes (1e8 histories per field; 3e8 for the heterogeneous)
+        out["workloads"] = []
+        for side in (4.0, 30.0):
+            rec, e2 = measure_workload(P, torch,
+                                       S.workload_clinical(side=side), H, 10,
+                                       2, launch)
+            out["workloads"].append(rec)
+            del e2
+            say("field %g done" % side)
+        wl_h = S.workload_heterogeneous()
+        rec, e2 = measure_workload(P, torch, wl_h, H,
+                                   wl_h.histories // H, 2, launch)
+        out["workloads"].append(rec)
+        del e2
+        torch.cuda.empty_cache()
+        say("heterogeneous done")
+        out["imrt_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches)
+        say("imrt done")
+        out["method2_vs_psl"] = bench_methods(P, torch, S, H)
+        out["psl_build"] = bench_build(P, torch, S)
+        out["time_to_accuracy"] = bench_time_to_accuracy()
+
+    wl = S.workload_clinical(side=args.field)
     if args.extras_only:
+        eng = P.Engine(wl, histories_per_batch=H, launch=launch)
         eng.step(0)
         eng.step(1)
-        d, _ = eng.finalize()
-        nz, ny, nx = wl.phantom.density.shape
-        out = {"denoiser": bench_denoiser(P, torch, d, eng.density,
-                                          (nz, ny, nx))}
-        del eng
-        torch.cuda.empty_cache()
-        out["imrt_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches)
-        out["time_to_accuracy"] = bench_time_to_accuracy()
+        eng.finalize()
+        out = {}
+        extras(out, eng)
         print(json.dumps(out))
         return
     torch.cuda.synchronize()
@@ -311,66 +557,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    atom_scatter, atom_same = P.bench_atomics(eng.nvox)
-    for b in range(args.warmup):
-        eng.step(b)
-    torch.cuda.synchronize()
-    eng.reset_tally()
-    P.profile_read(reset=True)
-    P.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        eng.step(k)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    P.profile_enable(False)
-    prof = P.profile_read(reset=True)
-    st = eng.stats_dict()
-    counts = eng.queue_counts()
-    if st["lost"]:
-        raise SystemExit("queue overflow: batch invalid")
-
-    value = args.steps * H / elapsed
-    ms = 1000.0 * elapsed / args.steps
-    # dominant kernel and its HBM roofline
-    groups = {g: v for g, v in prof.items() if v[1] > 0}
-    # the dominant kernel among those with algorithmic bytes defined
-    dom = max((g for g in groups if g in KERNEL_OF_GROUP),
-              key=lambda g: groups[g][0])
-    avg_ms = groups[dom][0] / groups[dom][1]
-    nbytes = _algorithmic_bytes(dom, st, eng.nvox)
-    achieved = nbytes / (avg_ms * 1e-3) / 1e9
-    kernel_ms = {g: round(v[0] / v[1], 4) for g, v in groups.items()}
-    # dose atomics of the transport kernels against the measured roof
-    def _avg(g):
-        v = groups.get(g)
-        return v[0] / v[1] * 1e-3 if v else 0.0
-    t_ph, t_el = _avg("photons"), _avg("electrons")
-    n_atom = st["deposits"] + st["photon_deposits"]
-    atomic_rate = n_atom / (t_ph + t_el) if t_ph + t_el > 0 else 0.0
-    per_kernel_atomics = {
-        "photons": st["photon_deposits"] / t_ph if t_ph else 0.0,
-        "electrons": st["deposits"] / t_el if t_el else 0.0}
-
-    # time to 1% uncertainty from the timed steps (batches)
-    d, s = eng.finalize()
-    torch.cuda.synchronize()
-    d = d.cpu().numpy()
-    s = s.cpu().numpy()
-    sel = d >= 0.5 * d.max()
-    sbar = float((s[sel] / d[sel]).mean())
-    t1 = elapsed * (sbar / 0.01) ** 2
-
+    rec, eng = measure_workload(P, torch, wl, H, args.steps, args.warmup,
+                                launch, replay=not args.no_replay)
+    say("main workload done")
     out = {
         "metric": "MC histories/sec on 1 GPU; time to 1% dose uncertainty, "
                   "PSL+denoise vs plain",
-        "value": value,
+        "value": rec["histories_per_s"],
         "unit": "histories/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -384,43 +582,21 @@ def main():
                    "psl_grid": "2x32x22x22", "phantom": "128^3 x 2.5 mm",
                    "tally": "u64 fixed point 2^-32 MeV",
                    "parallelism": "single GPU"},
-        "roofline": {"kernel": dom, "bound": "hbm",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": _traffic(dom),
-                     "algorithmic_bytes_per_launch": nbytes,
-                     "avg_launch_ms": avg_ms},
-        "kernel_ms": kernel_ms,
-        "atomic_roofline": {"kernels": "photons+electrons",
-                            "achieved": atomic_rate, "peak": atom_scatter,
-                            "unit": "u64 atomic adds/s",
-                            "frac": atomic_rate / atom_scatter,
-                            "per_kernel_frac": {
-                                k: v / atom_scatter
-                                for k, v in per_kernel_atomics.items()},
-                            "same_address_peak": atom_same,
-                            "atomics_per_step": n_atom},
-        "batch_stats": {k: st[k] for k in (
-            "histories", "photons", "electrons", "jaw_rejected",
-            "interactions", "secondaries", "segments", "deposits",
-            "photon_deposits", "flights")},
-        "time_to_1pct_s": t1,
-        "mean_rel_sigma_50pct": sbar,
     }
+    for k in ("roofline", "atomic_roofline", "kernel_ms", "batch_stats",
+              "time_to_1pct_s", "mean_rel_sigma_50pct"):
+        out[k] = rec[k]
     if not args.no_extras:
-        nz, ny, nx = wl.phantom.density.shape
-        out["denoiser"] = bench_denoiser(P, torch, eng.dose, eng.density,
-                                         (nz, ny, nx))
-        del eng
-        torch.cuda.empty_cache()
-        out["imrt_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches)
-        out["time_to_accuracy"] = bench_time_to_accuracy()
+        extras(out, eng)
+    del eng
+    torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or \
-            min(16, os.cpu_count() or 1)
+            len(os.sched_getaffinity(0))
         wl_cpu = S.workload_clinical(side=args.field)
-        out["cpu_baseline"] = cpu_baseline(wl_cpu, args.cpu_seconds, threads)
-        out["cpu_baseline"]["gpu_over_cpu"] = value / \
+        out["cpu_baseline"] = cpu_baseline(wl_cpu, args.cpu_seconds, threads,
+                                           args.cpu_single_seconds)
+        out["cpu_baseline"]["gpu_over_cpu"] = out["value"] / \
             out["cpu_baseline"]["value"]
     print(json.dumps(out))
 

@@ -109,6 +109,11 @@ typedef struct psl_field {
     double f_x0, f_y0, f_pix;   /* map origin (corner) and pixel size, cm   */
     int32_t jaws_on;            /* 0: no jaw model and no ROI for this field */
     int32_t pad;
+    double collimator_deg;      /* rotation of the beam about its central    */
+                                /* axis (the phase space turns with the      */
+                                /* collimator; applied after the jaw test)   */
+    double couch_deg;           /* patient rotation about the vertical axis  */
+                                /* (z at gantry 0) through the isocentre     */
 } psl_field;
 
 #define PSL_ALLOC_COUNTS 0      /* field totals in proportion to the        */
@@ -168,6 +173,7 @@ typedef struct psl_stats {
     uint64_t deposits;          /* dose atomics issued by electrons          */
     uint64_t photon_deposits;   /* dose atomics issued by photons            */
     uint64_t bucket_peak;       /* largest electron bucket fill of the batch */
+    uint64_t dropped;           /* psl_stream_sample: bad type or NaN energy */
     double e_in;                /* sum E*wt of queued source particles       */
     double e_escaped;           /* sum E*wt leaving the phantom              */
     double e_killed;            /* sum E*wt of photons ended by              */
@@ -241,6 +247,75 @@ psl_status psl_sample_noalloc(const psl_phsp *sorted,
                               uint8_t *d_mask, int64_t *d_alloc,
                               psl_stats *d_stats, void *stream);
 
+/*
+ * psl_stream_sample - Methods 1 and 2, the paper's sources before PSLs
+ * (Sec. 2.1, 2.2): the unsorted phase space is read in file order and
+ * sorted on the fly into bins by particle type and energy, each bin
+ * flushed to transport when it holds bin_capacity particles, the rest
+ * flushed at the end of the batch.
+ *  1. History r of batch b reads particle (s + b n_histories + r) mod n,
+ *     s = splitmix64(seed) mod n (a random start; reading wraps at the end
+ *     of the file).  A particle whose type is not 0 or 1, or whose energy
+ *     is NaN, is dropped (stats.dropped).
+ *  2. Method 2 passes the particle through the beam model of `field` (jaw
+ *     test, fluence weight, as psl_sample); Method 1 takes the phase space
+ *     as already collimated (the field's gantry angle applies, its jaws and
+ *     fluence map do not).  w' = w * fluence * weight; gantry rotation; move
+ *     along the ray to the phantom box.
+ *  3. An accepted particle joins bin type * n_e + e, e the largest k with
+ *     E >= e_edges[k] clamped to 0 .. n_e-1.  A bin holding bin_capacity
+ *     particles is flushed (its particles in arrival order) and starts
+ *     empty; after the last history the bins still holding particles are
+ *     flushed in bin order.
+ *  4. d_flushes receives the flushes in the order they happen: bin, count,
+ *     trigger (the history whose arrival filled the bin, -1 for the end of
+ *     the batch), first (offset of the flush in the flushed sequence, all
+ *     types).  The flushed sequence goes to the queues: photons to q->ph,
+ *     electrons to the bucket of q->el that holds their energy, each queue
+ *     in flushed-sequence order; uid = b n_histories + r.
+ *  phsp: device SoA in file order.  field, cfg: host (copied).
+ *  max_flushes must be >= n_histories / bin_capacity + 2 n_e.
+ *  d_n_flushes: device int64.  d_stats is zeroed and filled.
+ * The result equals the sequential process exactly: bins are ranked by a
+ * stable partition of the batch's histories, and a flush's position comes
+ * from the stream position of its trigger.
+ * Errors: PSL_EINVAL (sizes, edges, method not 1 or 2, capacity < 1,
+ * max_flushes too small), PSL_ENOSPC (workspace:
+ * psl_stream_workspace_bytes for the same n_histories, n_e and capacity;
+ * photon queue smaller than n_histories).
+ */
+typedef struct psl_stream_cfg {
+    uint64_t seed;              /* random start of the file reading          */
+    int64_t batch;              /* batch index b                             */
+    int64_t n_histories;        /* particles read in this batch              */
+    int64_t bin_capacity;       /* N: particles a bin holds before a flush   */
+    int32_t method;             /* 1 (collimated phase space) or 2 (jaws)    */
+    int32_t n_e;                /* energy bins, 1 .. PSL_MAX_EBINS           */
+    const float *e_edges;       /* host [n_e + 1], increasing                */
+    double weight;              /* per-history factor g; n / n_histories     */
+                                /* gives dose per phase-space particle       */
+    double z_plane;             /* phase-space plane (cm)                    */
+    double sad, z_jaw_x, z_jaw_y;
+    double iso[3];
+    double box_lo[3], box_hi[3];
+} psl_stream_cfg;
+
+typedef struct psl_flush {
+    int32_t bin;                /* type * n_e + energy bin                   */
+    int32_t pad;
+    int64_t count;
+    int64_t trigger;            /* history that filled the bin, -1 at end    */
+    int64_t first;              /* offset in the flushed sequence            */
+} psl_flush;
+
+size_t psl_stream_workspace_bytes(int64_t n_histories, int32_t n_e,
+                                  int64_t bin_capacity);
+psl_status psl_stream_sample(const psl_phsp *phsp, const psl_field *field,
+                             const psl_stream_cfg *cfg, psl_queue *q,
+                             psl_flush *d_flushes, int64_t max_flushes,
+                             int64_t *d_n_flushes, psl_stats *d_stats,
+                             void *d_ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Transport.                                                                */
 /* ------------------------------------------------------------------------ */
@@ -287,13 +362,22 @@ typedef struct psl_physics {
 psl_status psl_physics_init(const psl_physics *phys, void *d_tables,
                             void *stream);
 
-/* Dose accumulator: energy x weight per voxel for the current batch. */
+/* Dose accumulator: energy x weight per voxel for the current batch.
+ * PSL_ACC_TRACE is a measurement mode, not a tally: the transport kernels
+ * record the voxel index of every deposit instead of adding energy, in the
+ * order the waves issue them (a wave's deposits of one call site are
+ * consecutive).  data then points to a device buffer laid out as a uint64
+ * count followed by trace_capacity uint32 voxel indices; the count must be
+ * zero before the call and ends as the number of deposits (entries past
+ * trace_capacity are counted, not stored).  dose_tally rejects this mode. */
 #define PSL_ACC_F64 0           /* double, MeV                               */
 #define PSL_ACC_FIXED64 1       /* uint64, MeV * 2^frac_bits                 */
+#define PSL_ACC_TRACE 2         /* deposit-address trace (see above)         */
 typedef struct psl_dose_acc {
     int32_t mode;
     int32_t frac_bits;          /* FIXED64 only, 16..40                      */
-    void *data;                 /* device [nz*ny*nx]                         */
+    void *data;                 /* device [nz*ny*nx] (TRACE: see above)      */
+    int64_t trace_capacity;     /* TRACE only: voxel indices data can hold   */
 } psl_dose_acc;
 
 /* Launch shape.  NULL selects defaults (256, 4, 0, 1); the autotuner
@@ -542,6 +626,25 @@ psl_status dose_denoise(const float *d_dose, const float *d_density,
 size_t psl_bench_atomics_workspace_bytes(int64_t n_addresses);
 psl_status psl_bench_atomics(int64_t n_addresses, double *rates, void *d_ws,
                              size_t ws_bytes, void *stream);
+
+/*
+ * psl_bench_atomics_replay - the atomic roof of the tally's own address
+ * pattern: replays d_trace (device uint32 [n_trace] voxel indices below
+ * n_addresses, as recorded by transport_batch in PSL_ACC_TRACE mode) as
+ * 64-bit atomic adds on an n_addresses-entry array in the workspace, entry
+ * j on thread j mod (grid size), `reps` times per launch, for each launch
+ * shape blocks_per_cu[0 .. n_shapes-1] (256-thread blocks per CU, 1..64).
+ * rates[i] receives atomic adds per second for shape i.  Workspace:
+ * psl_bench_atomics_workspace_bytes(n_addresses), contents destroyed.
+ * Entries at or above n_addresses are skipped (still counted in the
+ * rate).  Synchronises the stream.
+ */
+psl_status psl_bench_atomics_replay(const uint32_t *d_trace, int64_t n_trace,
+                                    int64_t n_addresses,
+                                    const int32_t *blocks_per_cu,
+                                    int32_t n_shapes, int32_t reps,
+                                    double *rates, void *d_ws,
+                                    size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -62,7 +62,9 @@ class OField(C.Structure):
                 ("jaws_on", C.c_int32), ("nfx", C.c_int32),
                 ("nfy", C.c_int32), ("pad", C.c_int32),
                 ("f_x0", C.c_double), ("f_y0", C.c_double),
-                ("f_pix", C.c_double), ("fluence", C.c_void_p)]
+                ("f_pix", C.c_double), ("fluence", C.c_void_p),
+                ("cos_c", C.c_double), ("sin_c", C.c_double),
+                ("cos_t", C.c_double), ("sin_t", C.c_double)]
 
 
 class OGeom(C.Structure):
@@ -119,6 +121,9 @@ def _declare(L):
                                 vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp]
     L.oracle_sample.restype = None
+    L.oracle_stream.argtypes = [vp, vp, i32, i64] + [vp] * 8 + \
+        [i32, vp, i64, i64, u64, d, i64, vp, vp, vp, vp, vp, vp, vp]
+    L.oracle_stream.restype = i64
     L.oracle_kn_sigma.argtypes = [d]
     L.oracle_kn_sigma.restype = d
     L.oracle_stopping_power.argtypes = [d, d, d]
@@ -210,6 +215,10 @@ def _ofields(fields):
         a.X1, a.X2, a.Y1, a.Y2 = f.X1, f.X2, f.Y1, f.Y2
         th = math.radians(f.gantry_deg)
         a.cos_g, a.sin_g = math.cos(th), math.sin(th)
+        tc = math.radians(getattr(f, "collimator_deg", 0.0))
+        a.cos_c, a.sin_c = math.cos(tc), math.sin(tc)
+        tt = math.radians(getattr(f, "couch_deg", 0.0))
+        a.cos_t, a.sin_t = math.cos(tt), math.sin(tt)
         a.MU = f.MU
         a.jaws_on = 1 if f.jaws else 0
         if f.fluence is not None:
@@ -274,6 +283,54 @@ def sample(fields, geom, offsets, N, g, batch, seed, ps):
     return {"src": src, "field": fld, "key": key, "status": st,
             "state": state, "uid": uid,
             "type": ps.type[src] if n_hist else np.zeros(0, np.uint8)}
+
+
+def stream_sample(field, geom, ps, e_edges, n_hist, batch, seed, cap,
+                  method=2, weight=None):
+    """Methods 1 and 2 (Sec. 2.1, 2.2) for one batch: the phase space read
+    in file order from a random start, the beam model (Method 2), on-the-fly
+    bins by type and energy flushed when they hold `cap` particles and at
+    the end.  weight: the per-history factor g (default n / n_hist, dose per
+    phase-space particle).  Returns per-history status (0 jaw, 1 accepted,
+    2 zero fluence, 3 miss, 4 dropped: bad type or NaN energy), state
+    [n_hist, 8] = E x y z u v w w', src, uid, type; the flushes (bin, count,
+    trigger, first) in order; seq, the flushed sequence of history
+    indices."""
+    n = int(ps.n)
+    n_hist = int(n_hist)
+    e_edges = np.ascontiguousarray(e_edges, np.float32)
+    n_e = len(e_edges) - 1
+    g = float(n) / n_hist if weight is None else float(weight)
+    st = np.zeros(n_hist, np.uint8)
+    state = np.zeros((max(n_hist, 1), 8), np.float64)
+    max_fl = n_hist // max(int(cap), 1) + 2 * n_e + 1
+    fb = np.zeros(max_fl, np.int32)
+    fc = np.zeros(max_fl, np.int64)
+    ft = np.zeros(max_fl, np.int64)
+    ff = np.zeros(max_fl, np.int64)
+    seq = np.zeros(max(n_hist, 1), np.int64)
+    arr, keep = _ofields([field])
+    G = _ogeom(geom)
+    c = np.ascontiguousarray
+    cols = [c(getattr(ps, k)) for k in ("type", "E", "x", "y", "u", "v", "w",
+                                         "wt")]
+    nf = lib().oracle_stream(C.cast(arr, C.c_void_p), C.byref(G), int(method),
+                             n, *[_p(a) for a in cols], n_e, _p(e_edges),
+                             n_hist, int(batch), C.c_uint64(seed), g,
+                             int(cap), _p(st), _p(state), _p(fb), _p(fc),
+                             _p(ft), _p(ff), _p(seq))
+    del keep
+    s0 = int(splitmix64(seed) % n) if n else 0
+    src = (s0 + int(batch) * n_hist + np.arange(n_hist, dtype=np.int64)) % \
+        max(n, 1)
+    uid = np.uint64(batch) * np.uint64(n_hist) + np.arange(n_hist,
+                                                           dtype=np.uint64)
+    n_seq = int(fc[:nf].sum())
+    return {"status": st, "state": state[:n_hist], "src": src, "uid": uid,
+            "type": ps.type[src] if n_hist else np.zeros(0, np.uint8),
+            "flush_bin": fb[:nf], "flush_count": fc[:nf],
+            "flush_trigger": ft[:nf], "flush_first": ff[:nf],
+            "seq": seq[:n_seq], "weight": g}
 
 
 # ---------------------------------------------------------------------------

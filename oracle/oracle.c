@@ -287,6 +287,8 @@ typedef struct {
     int32_t pad;
     double f_x0, f_y0, f_pix;   /* fluence map origin and pixel at SAD */
     const float *fluence;       /* [nfy][nfx] */
+    double cos_c, sin_c;        /* collimator: about the central axis */
+    double cos_t, sin_t;        /* couch: patient about the vertical axis */
 } ofield;
 
 typedef struct {
@@ -294,6 +296,111 @@ typedef struct {
     double iso[3];              /* isocentre, world frame */
     double box_lo[3], box_hi[3];/* phantom AABB, world frame */
 } ogeom;
+
+/* One phase-space particle through the beam model (Sec. 2.2, 2.4), from
+ * its position (x, y) at the phase-space plane and direction (u, v, w):
+ * the jaw model (perfect collimators at z_x and z_y, zero transmission,
+ * edges given at SAD, closed interval), the fluence weight of the map pixel
+ * its ray crosses at the SAD plane (nearest pixel; outside the map or zero
+ * rejects), the weight w' = wt * fluence * gk, the collimator, gantry
+ * and couch rotations and the straight-line move to the phantom box.
+ * Returns 0 jaw-rejected, 1 accepted, 2 zero fluence, 3 misses the phantom;
+ * S = E x y z u v w w' on acceptance, zeros otherwise. */
+static int beam_particle(const ofield *F, const ogeom *G, float x, float y,
+                         float u, float v, float w, float wt, float E,
+                         double gk, double S[8])
+{
+    for (int q = 0; q < 8; ++q) S[q] = 0.0;
+    double px = x, py = y, pz = G->z_psl;
+    double du = u, dv = v, dw = w;
+    /* jaw model: test the crossing of each jaw plane */
+    if (F->jaws_on) {
+        if (!(dw > 0.0)) return 0;
+        double tx = du / dw, ty = dv / dw;
+        double xj = px + tx * (G->z_x - pz);
+        double yj = py + ty * (G->z_y - pz);
+        double xlo = F->X1 * G->z_x / G->sad;
+        double xhi = F->X2 * G->z_x / G->sad;
+        double ylo = F->Y1 * G->z_y / G->sad;
+        double yhi = F->Y2 * G->z_y / G->sad;
+        if (!(xj >= xlo && xj <= xhi && yj >= ylo && yj <= yhi)) return 0;
+    }
+    /* fluence weight at the SAD plane, nearest pixel */
+    double fl = 1.0;
+    if (F->nfx > 0) {
+        if (!(dw > 0.0)) return 2;
+        double xs = px + (du / dw) * (G->sad - pz);
+        double ys = py + (dv / dw) * (G->sad - pz);
+        double fx = floor((xs - F->f_x0) / F->f_pix);
+        double fy = floor((ys - F->f_y0) / F->f_pix);
+        if (!(fx >= 0.0 && fy >= 0.0 && fx < (double)F->nfx &&
+              fy < (double)F->nfy))
+            fl = 0.0;
+        else
+            fl = (double)F->fluence[(int64_t)fy * F->nfx + (int64_t)fx];
+        if (!(fl > 0.0)) return 2;
+    }
+    double wgt = (double)wt * fl * gk;
+    /* the rotations of the field, applied to the position about the
+     * isocentre and to the direction: collimator (the phase space turns
+     * with it about the central axis, z through the isocentre; the jaw
+     * test above is in its frame), then gantry about +y, then couch (the
+     * patient turns by +angle about the vertical, z at gantry 0, so the
+     * beam turns by -angle).  Collimator and couch act only when one of
+     * them is not zero, so the unturned case is the gantry alone, term for
+     * term. */
+    const int turned = F->cos_c != 1.0 || F->sin_c != 0.0 ||
+                       F->cos_t != 1.0 || F->sin_t != 0.0;
+    double rx = px - G->iso[0], ry = py - G->iso[1], rz = pz - G->iso[2];
+    double au = du, av = dv;
+    if (turned) {
+        double x1 = F->cos_c * rx - F->sin_c * ry;
+        double y1 = F->sin_c * rx + F->cos_c * ry;
+        double u1 = F->cos_c * au - F->sin_c * av;
+        double v1 = F->sin_c * au + F->cos_c * av;
+        rx = x1; ry = y1; au = u1; av = v1;
+    }
+    double qx = F->cos_g * rx + F->sin_g * rz + G->iso[0];
+    double qy = ry + G->iso[1];
+    double qz = -F->sin_g * rx + F->cos_g * rz + G->iso[2];
+    double eu = F->cos_g * au + F->sin_g * dw;
+    double ev = av;
+    double ew = -F->sin_g * au + F->cos_g * dw;
+    if (turned) {
+        double sx = qx - G->iso[0], sy = qy - G->iso[1];
+        qx = F->cos_t * sx + F->sin_t * sy + G->iso[0];
+        qy = -F->sin_t * sx + F->cos_t * sy + G->iso[1];
+        double u2 = F->cos_t * eu + F->sin_t * ev;
+        double v2 = -F->sin_t * eu + F->cos_t * ev;
+        eu = u2; ev = v2;
+    }
+    /* straight-line projection to the phantom box (slab test) */
+    double pos[3] = {qx, qy, qz}, dir[3] = {eu, ev, ew};
+    double tn = -INFINITY, tf = INFINITY;
+    int miss = 0;
+    for (int a = 0; a < 3; ++a) {
+        if (dir[a] != 0.0) {
+            double t1 = (G->box_lo[a] - pos[a]) / dir[a];
+            double t2 = (G->box_hi[a] - pos[a]) / dir[a];
+            double lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
+            if (lo > tn) tn = lo;
+            if (hi < tf) tf = hi;
+        } else if (pos[a] < G->box_lo[a] || pos[a] > G->box_hi[a]) {
+            miss = 1;
+        }
+    }
+    if (miss || tn > tf || tf <= 0.0) return 3;
+    double t = tn > 0.0 ? tn : 0.0;
+    S[0] = E;
+    S[1] = pos[0] + t * dir[0];
+    S[2] = pos[1] + t * dir[1];
+    S[3] = pos[2] + t * dir[2];
+    S[4] = eu;
+    S[5] = ev;
+    S[6] = ew;
+    S[7] = wgt;
+    return 1;
+}
 
 /* Histories of one batch, in canonical order: field-major, then key, then r.
  * History r of PSL k in field i reads the particle at
@@ -338,81 +445,97 @@ void oracle_sample(int n_fields, const ofield *fields, const ogeom *G,
                 src[h] = p;
                 field[h] = f;
                 keyo[h] = (int32_t)k;
-                double *S = state + 8 * h;
-                for (int q = 0; q < 8; ++q) S[q] = 0.0;
-                double px = x[p], py = y[p], pz = G->z_psl;
-                double du = u[p], dv = v[p], dw = w[p];
-                /* jaw model: test the crossing of each jaw plane */
-                if (F->jaws_on) {
-                    if (!(dw > 0.0)) { status[h] = 0; continue; }
-                    double tx = du / dw, ty = dv / dw;
-                    double xj = px + tx * (G->z_x - pz);
-                    double yj = py + ty * (G->z_y - pz);
-                    double xlo = F->X1 * G->z_x / G->sad;
-                    double xhi = F->X2 * G->z_x / G->sad;
-                    double ylo = F->Y1 * G->z_y / G->sad;
-                    double yhi = F->Y2 * G->z_y / G->sad;
-                    if (!(xj >= xlo && xj <= xhi && yj >= ylo && yj <= yhi)) {
-                        status[h] = 0;
-                        continue;
-                    }
-                }
-                /* fluence weight at the SAD plane, nearest pixel */
-                double fl = 1.0;
-                if (F->nfx > 0) {
-                    if (!(dw > 0.0)) { status[h] = 2; continue; }
-                    double xs = px + (du / dw) * (G->sad - pz);
-                    double ys = py + (dv / dw) * (G->sad - pz);
-                    double fx = floor((xs - F->f_x0) / F->f_pix);
-                    double fy = floor((ys - F->f_y0) / F->f_pix);
-                    if (!(fx >= 0.0 && fy >= 0.0 && fx < (double)F->nfx &&
-                          fy < (double)F->nfy))
-                        fl = 0.0;
-                    else
-                        fl = (double)F->fluence[(int64_t)fy * F->nfx +
-                                                (int64_t)fx];
-                    if (!(fl > 0.0)) { status[h] = 2; continue; }
-                }
-                double wgt = (double)wt[p] * fl * gk;
-                /* gantry rotation about the y axis through the isocentre */
-                double rx = px - G->iso[0], ry = py - G->iso[1],
-                       rz = pz - G->iso[2];
-                double qx = F->cos_g * rx + F->sin_g * rz + G->iso[0];
-                double qy = ry + G->iso[1];
-                double qz = -F->sin_g * rx + F->cos_g * rz + G->iso[2];
-                double eu = F->cos_g * du + F->sin_g * dw;
-                double ev = dv;
-                double ew = -F->sin_g * du + F->cos_g * dw;
-                /* straight-line projection to the phantom box (slab test) */
-                double pos[3] = {qx, qy, qz}, dir[3] = {eu, ev, ew};
-                double tn = -INFINITY, tf = INFINITY;
-                int miss = 0;
-                for (int a = 0; a < 3; ++a) {
-                    if (dir[a] != 0.0) {
-                        double t1 = (G->box_lo[a] - pos[a]) / dir[a];
-                        double t2 = (G->box_hi[a] - pos[a]) / dir[a];
-                        double lo = t1 < t2 ? t1 : t2, hi = t1 < t2 ? t2 : t1;
-                        if (lo > tn) tn = lo;
-                        if (hi < tf) tf = hi;
-                    } else if (pos[a] < G->box_lo[a] || pos[a] > G->box_hi[a]) {
-                        miss = 1;
-                    }
-                }
-                if (miss || tn > tf || tf <= 0.0) { status[h] = 3; continue; }
-                double t = tn > 0.0 ? tn : 0.0;
-                status[h] = 1;
-                S[0] = E[p];
-                S[1] = pos[0] + t * dir[0];
-                S[2] = pos[1] + t * dir[1];
-                S[3] = pos[2] + t * dir[2];
-                S[4] = eu;
-                S[5] = ev;
-                S[6] = ew;
-                S[7] = wgt;
-                (void)type;
+                status[h] = (uint8_t)beam_particle(F, G, x[p], y[p], u[p],
+                                                   v[p], w[p], wt[p], E[p],
+                                                   gk, state + 8 * h);
             }
         }
     }
+    (void)type;
+}
+
+/* Methods 1 and 2 (Sec. 2.1, 2.2): the phase space is read in file order
+ * and sorted on the fly into bins by particle type (photon; electron or
+ * positron) and energy.  History r of batch b reads particle
+ *   (s + b * n_hist + r) mod n,  s = splitmix64(seed) mod n,
+ * (a random start, as the PSLs get in Sec. 2.3.3; reading wraps at the end
+ * of the file).  Method 2 passes each particle through the beam model of
+ * field F with weight factor gk; Method 1 (a phase space already
+ * collimated) passes the jaw and fluence tests by construction (F without
+ * jaws or map).  A particle whose type is neither 0 nor 1, or whose energy
+ * is NaN, is dropped (status 4).  An accepted particle joins the bin of its
+ * type and energy (largest k with E >= e_edges[k], clamped to the n_e bins);
+ * when a bin holds cap particles it is flushed: its particles leave as one
+ * transport batch in the order they arrived, and the bin starts empty.
+ * After the last history the bins still holding particles are flushed in
+ * bin order.  Outputs: status and state (E x y z u v w w') per history;
+ * the flushes in order: bin (type * n_e + e), count, trigger (the history
+ * whose arrival filled the bin; -1 at the end) and first (the flush's
+ * offset in the flushed sequence); seq, the history index of every flushed
+ * particle, flushes concatenated.  Returns the number of flushes. */
+int64_t oracle_stream(const ofield *F, const ogeom *G, int method, int64_t n,
+                      const uint8_t *type, const float *E, const float *x,
+                      const float *y, const float *u, const float *v,
+                      const float *w, const float *wt, int n_e,
+                      const float *e_edges, int64_t n_hist, int64_t batch,
+                      uint64_t seed, double gk, int64_t cap, uint8_t *status,
+                      double *state, int32_t *fl_bin, int64_t *fl_count,
+                      int64_t *fl_trigger, int64_t *fl_first, int64_t *seq)
+{
+    ofield open = *F;
+    if (method == 1) { open.jaws_on = 0; open.nfx = 0; open.nfy = 0; }
+    const int n_bins = 2 * n_e;
+    int64_t **bin = (int64_t **)calloc((size_t)n_bins, sizeof(int64_t *));
+    int64_t *fill = (int64_t *)calloc((size_t)n_bins, sizeof(int64_t));
+    int64_t *room = (int64_t *)calloc((size_t)n_bins, sizeof(int64_t));
+    int64_t n_fl = 0, n_seq = 0;
+    const uint64_t s0 = n > 0 ? oracle_splitmix64(seed) % (uint64_t)n : 0;
+    for (int64_t r = 0; r < n_hist; ++r) {
+        const int64_t p = (int64_t)((s0 + (uint64_t)batch * (uint64_t)n_hist +
+                                     (uint64_t)r) % (uint64_t)n);
+        double *S = state + 8 * r;
+        if (type[p] > 1 || E[p] != E[p]) {
+            for (int q = 0; q < 8; ++q) S[q] = 0.0;
+            status[r] = 4;
+            continue;
+        }
+        status[r] = (uint8_t)beam_particle(&open, G, x[p], y[p], u[p], v[p],
+                                           w[p], wt[p], E[p], gk, S);
+        if (status[r] != 1) continue;
+        int e = 0;
+        for (int k = 1; k < n_e; ++k)
+            if (E[p] >= e_edges[k]) e = k;
+        const int b = (int)type[p] * n_e + e;
+        if (fill[b] == room[b]) {
+            room[b] = room[b] ? 2 * room[b] : 64;
+            bin[b] = (int64_t *)realloc(bin[b], (size_t)room[b] * 8);
+        }
+        bin[b][fill[b]++] = r;
+        if (fill[b] == cap) {
+            fl_bin[n_fl] = b;
+            fl_count[n_fl] = cap;
+            fl_trigger[n_fl] = r;
+            fl_first[n_fl] = n_seq;
+            ++n_fl;
+            for (int64_t i = 0; i < cap; ++i) seq[n_seq++] = bin[b][i];
+            fill[b] = 0;
+        }
+    }
+    for (int b = 0; b < n_bins; ++b) {
+        if (fill[b] == 0) continue;
+        fl_bin[n_fl] = b;
+        fl_count[n_fl] = fill[b];
+        fl_trigger[n_fl] = -1;
+        fl_first[n_fl] = n_seq;
+        ++n_fl;
+        for (int64_t i = 0; i < fill[b]; ++i) seq[n_seq++] = bin[b][i];
+        fill[b] = 0;
+    }
+    for (int b = 0; b < n_bins; ++b) free(bin[b]);
+    free(bin);
+    free(fill);
+    free(room);
+    return n_fl;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -27,7 +27,7 @@ PSL_MAX_QBUCKETS = 16
 PSL_QCOUNTS = PSL_MAX_QBUCKETS + 2
 PSL_TABLE_BYTES = 64 * 1024
 PSL_ALLOC_COUNTS, PSL_ALLOC_MU = 0, 1
-PSL_ACC_F64, PSL_ACC_FIXED64 = 0, 1
+PSL_ACC_F64, PSL_ACC_FIXED64, PSL_ACC_TRACE = 0, 1, 2
 PSL_TALLY_FOLD, PSL_TALLY_FINALIZE = 0, 1
 PSL_FLAG_FIRST_COLLISION, PSL_FLAG_NO_MSC = 1, 2
 
@@ -42,7 +42,8 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "unet_set_params", "unet_forward", "unet_backward",
            "unet_adam_step", "dose_denoise",
            "dose_gamma", "psl_sample_noalloc_max_bytes",
-           "psl_sample_noalloc"]
+           "psl_sample_noalloc", "psl_bench_atomics_replay",
+           "psl_stream_workspace_bytes", "psl_stream_sample"]
 
 
 class PslError(RuntimeError):
@@ -72,7 +73,8 @@ class psl_field(C.Structure):
                 ("MU", C.c_double), ("fluence", C.c_void_p),
                 ("nfx", C.c_int32), ("nfy", C.c_int32), ("f_x0", C.c_double),
                 ("f_y0", C.c_double), ("f_pix", C.c_double),
-                ("jaws_on", C.c_int32), ("pad", C.c_int32)]
+                ("jaws_on", C.c_int32), ("pad", C.c_int32),
+                ("collimator_deg", C.c_double), ("couch_deg", C.c_double)]
 
 
 class psl_sample_cfg(C.Structure):
@@ -82,6 +84,23 @@ class psl_sample_cfg(C.Structure):
                 ("z_jaw_x", C.c_double), ("z_jaw_y", C.c_double),
                 ("iso", C.c_double * 3), ("box_lo", C.c_double * 3),
                 ("box_hi", C.c_double * 3)]
+
+
+class psl_stream_cfg(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("batch", C.c_int64),
+                ("n_histories", C.c_int64), ("bin_capacity", C.c_int64),
+                ("method", C.c_int32), ("n_e", C.c_int32),
+                ("e_edges", C.c_void_p), ("weight", C.c_double),
+                ("z_plane", C.c_double), ("sad", C.c_double),
+                ("z_jaw_x", C.c_double), ("z_jaw_y", C.c_double),
+                ("iso", C.c_double * 3), ("box_lo", C.c_double * 3),
+                ("box_hi", C.c_double * 3)]
+
+
+class psl_flush(C.Structure):
+    _fields_ = [("bin", C.c_int32), ("pad", C.c_int32),
+                ("count", C.c_int64), ("trigger", C.c_int64),
+                ("first", C.c_int64)]
 
 
 class psl_particles(C.Structure):
@@ -100,7 +119,7 @@ class psl_queue(C.Structure):
 STATS_FIELDS = ["histories", "jaw_rejected", "fluence_zero", "missed",
                 "photons", "electrons", "lost", "interactions", "secondaries",
                 "segments", "flights", "runaway", "deposits",
-                "photon_deposits", "bucket_peak"]
+                "photon_deposits", "bucket_peak", "dropped"]
 
 
 class psl_stats(C.Structure):
@@ -127,7 +146,7 @@ class psl_physics(C.Structure):
 
 class psl_dose_acc(C.Structure):
     _fields_ = [("mode", C.c_int32), ("frac_bits", C.c_int32),
-                ("data", C.c_void_p)]
+                ("data", C.c_void_p), ("trace_capacity", C.c_int64)]
 
 
 class psl_launch(C.Structure):
@@ -189,6 +208,14 @@ def lib():
         L.psl_sample_noalloc.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, vp,
                                          vp, vp]
         L.psl_sample_noalloc.restype = i32
+        L.psl_bench_atomics_replay.argtypes = [vp, i64, i64, vp, i32, i32, vp,
+                                               vp, sz, vp]
+        L.psl_bench_atomics_replay.restype = i32
+        L.psl_stream_workspace_bytes.argtypes = [i64, i32, i64]
+        L.psl_stream_workspace_bytes.restype = sz
+        L.psl_stream_sample.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp,
+                                        sz, vp]
+        L.psl_stream_sample.restype = i32
         L.psl_physics_init.argtypes = [vp, vp, vp]
         L.psl_physics_init.restype = i32
         L.transport_batch_workspace_bytes.argtypes = [vp]
@@ -313,6 +340,8 @@ def make_fields(fields, fluence_tensors) -> "C.Array":
             a.fluence, a.nfx, a.nfy = None, 0, 0
         a.f_x0, a.f_y0, a.f_pix = f.f_x0, f.f_y0, f.f_pix
         a.jaws_on = 1 if f.jaws else 0
+        a.collimator_deg = f.collimator_deg
+        a.couch_deg = f.couch_deg
     return arr
 
 
@@ -372,6 +401,20 @@ def psl_sample_noalloc(sorted_phsp: Dict, offsets, grid: psl_grid,
                                     len(fields_arr), C.byref(cfg),
                                     C.byref(queue), _ptr(mask), _ptr(alloc),
                                     _ptr(stats), _stream(stream)))
+
+
+def psl_stream_sample(phsp: Dict, field_arr, cfg: psl_stream_cfg,
+                      queue: psl_queue, flushes, n_flushes, stats, ws,
+                      stream=None):
+    """Methods 1/2 source of one batch; flushes: device int64 tensor viewed
+    as psl_flush records ([max_flushes, 4]), n_flushes: device int64 [1]."""
+    s = make_phsp(phsp)
+    _check(lib().psl_stream_sample(C.byref(s), field_arr, C.byref(cfg),
+                                   C.byref(queue), _ptr(flushes),
+                                   int(flushes.shape[0]), _ptr(n_flushes),
+                                   _ptr(stats), _ptr(ws),
+                                   ws.numel() * ws.element_size(),
+                                   _stream(stream)))
 
 
 def psl_physics_init(phys: psl_physics, tables, stream=None):
@@ -573,6 +616,23 @@ def bench_atomics(n_addresses, device="cuda"):
     _check(lib().psl_bench_atomics(int(n_addresses), rates, _ptr(ws), nb,
                                    _stream()))
     return rates[0], rates[1]
+
+
+def bench_atomics_replay(trace, n_addresses, blocks_per_cu=(1, 2, 4, 8, 16),
+                         reps=3, device="cuda"):
+    """Replay of a recorded deposit-address trace (device uint32 tensor) as
+    u64 atomic adds over n_addresses counters, at each launch shape:
+    {blocks_per_cu: adds/s}."""
+    import torch
+    assert trace.dtype == torch.int32 or trace.dtype == torch.uint32
+    nb = lib().psl_bench_atomics_workspace_bytes(int(n_addresses))
+    ws = torch.zeros(nb, dtype=torch.uint8, device=device)
+    shapes = (C.c_int32 * len(blocks_per_cu))(*blocks_per_cu)
+    rates = (C.c_double * len(blocks_per_cu))()
+    _check(lib().psl_bench_atomics_replay(
+        _ptr(trace), int(trace.numel()), int(n_addresses), shapes,
+        len(blocks_per_cu), int(reps), rates, _ptr(ws), nb, _stream()))
+    return {b: rates[i] for i, b in enumerate(blocks_per_cu)}
 
 
 def profile_enable(on=True):

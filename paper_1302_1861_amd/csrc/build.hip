@@ -9,6 +9,7 @@
 //   offsets       exclusive scan of the key histogram (int64)
 //   k_gather      payload copy in PSL order
 #include "common.hpp"
+#include "radix.hpp"
 #include "scan.hpp"
 
 namespace psl {
@@ -202,6 +203,49 @@ psl_status validate_grid(const psl_grid *g) {
 }  // namespace
 
 psl_status validate_grid_public(const psl_grid *g) { return validate_grid(g); }
+
+namespace {
+__global__ void k_digit_start(const uint32_t *__restrict__ tile_off,
+                              int64_t n_tiles, uint32_t *__restrict__ out) {
+    out[threadIdx.x] = tile_off[(int64_t)threadIdx.x * n_tiles];
+}
+}  // namespace
+
+size_t radix_pass_ws_bytes(int64_t n) {
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t n_tiles = (nn + kTile - 1) / kTile;
+    Carver c(nullptr);
+    c.take<uint32_t>(256 * n_tiles);
+    c.take<uint64_t>(scan_chunks(256 * n_tiles) + 1);
+    return c.used;
+}
+
+psl_status radix_pass(const uint32_t *keys_in, const uint32_t *idx_in,
+                      int64_t n, int shift, uint32_t *keys_out,
+                      uint32_t *idx_out, uint32_t *digit_start, void *ws,
+                      hipStream_t st) {
+    const int64_t nn = n > 0 ? n : 1;
+    const int64_t n_tiles = (nn + kTile - 1) / kTile;
+    Carver c(ws);
+    uint32_t *tile = c.take<uint32_t>(256 * n_tiles);
+    uint64_t *chunks = c.take<uint64_t>(scan_chunks(256 * n_tiles) + 1);
+    hipLaunchKernelGGL(k_tile_hist, dim3((unsigned)n_tiles),
+                       dim3(kRadixBlock), 0, st, keys_in, n, shift, tile,
+                       n_tiles);
+    psl_status s = exclusive_scan<uint32_t, uint32_t>(tile, tile,
+                                                      256 * n_tiles, chunks,
+                                                      nullptr, st);
+    if (s) return s;
+    if (n > 0)
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)n_tiles),
+                           dim3(kRadixBlock), 0, st, keys_in, idx_in, n,
+                           shift, tile, n_tiles, keys_out, idx_out);
+    if (digit_start)
+        hipLaunchKernelGGL(k_digit_start, dim3(1), dim3(256), 0, st, tile,
+                           n_tiles, digit_start);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
 
 }  // namespace psl
 

@@ -1,19 +1,37 @@
 // psl_bench_atomics: measured roofs for the dose tally -- 64-bit atomic adds
-// scattered over many addresses (the tally's access pattern) and atomic adds
-// that all hit one address (the pattern this library avoids).
+// scattered over many addresses and atomic adds that all hit one address
+// (the pattern this library avoids); psl_bench_atomics_replay: the tally's
+// own recorded deposit addresses replayed at several occupancies.
 #include "common.hpp"
 
 namespace psl {
 namespace {
 
+// Uniformly scattered addresses: a 32-bit multiplicative hash of (thread,
+// iteration) masked to the largest power of two <= the address count.
 __global__ void __launch_bounds__(256)
-k_atomic_scatter(unsigned long long *a, int64_t n, int iters) {
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+k_atomic_scatter(unsigned long long *a, uint32_t mask, int iters) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int i = 0; i < iters; ++i) {
-        uint64_t h = t * 0x9E3779B97F4A7C15ull + (uint64_t)i * 0xBF58476D1CE4E5B9ull;
-        h ^= h >> 31;
-        atomicAdd(&a[h % (uint64_t)n], 1ull);
+        uint32_t h = t * 0x9E3779B9u ^ (uint32_t)i * 0x85EBCA6Bu;
+        h ^= h >> 15;
+        atomicAdd(&a[h & mask], 1ull);
     }
+}
+
+// Replay of a recorded deposit-address trace: entry j goes to thread
+// j mod (grid size), so the lanes of a wave issue consecutive entries
+// together, as the waves that recorded them did.
+__global__ void __launch_bounds__(256)
+k_atomic_replay(unsigned long long *a, uint32_t n_addr,
+                const uint32_t *__restrict__ trace, int64_t n, int reps) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int r = 0; r < reps; ++r)
+        for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+             j < n; j += stride) {
+            const uint32_t v = trace[j];
+            if (v < n_addr) atomicAdd(&a[v], 1ull);
+        }
 }
 
 __global__ void __launch_bounds__(256)
@@ -52,11 +70,14 @@ extern "C" psl_status psl_bench_atomics(int64_t n_addresses, double *rates,
     const int iters = 16;
     float ms = 0.0f;
     // scattered u64 atomics
+    uint32_t mask = 1;
+    while ((int64_t)mask * 2 <= n_addresses && mask < (1u << 31)) mask *= 2;
+    mask -= 1;
     hipLaunchKernelGGL(k_atomic_scatter, dim3(blocks), dim3(256), 0, st, a,
-                       n_addresses, 2);
+                       mask, 2);
     PSL_HIP(hipEventRecord(e0, st));
     hipLaunchKernelGGL(k_atomic_scatter, dim3(blocks), dim3(256), 0, st, a,
-                       n_addresses, iters);
+                       mask, iters);
     PSL_HIP(hipEventRecord(e1, st));
     PSL_HIP(hipEventSynchronize(e1));
     PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -70,6 +91,49 @@ extern "C" psl_status psl_bench_atomics(int64_t n_addresses, double *rates,
     PSL_HIP(hipEventSynchronize(e1));
     PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
     rates[1] = (double)blocks1 * 4 * 64 / (ms * 1e-3);
+    PSL_HIP(hipEventDestroy(e0));
+    PSL_HIP(hipEventDestroy(e1));
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+extern "C" psl_status psl_bench_atomics_replay(
+    const uint32_t *d_trace, int64_t n_trace, int64_t n_addresses,
+    const int32_t *blocks_per_cu, int32_t n_shapes, int32_t reps,
+    double *rates, void *d_ws, size_t ws_bytes, void *stream) {
+    PSL_REQUIRE(d_trace && blocks_per_cu && rates && d_ws, "NULL argument");
+    PSL_REQUIRE(n_trace >= 1 && n_addresses >= 1 &&
+                    n_addresses < ((int64_t)1 << 32),
+                "empty trace, or address count outside 1..2^32-1");
+    PSL_REQUIRE(n_shapes >= 1 && n_shapes <= 64 && reps >= 1 && reps <= 1000,
+                "n_shapes outside 1..64 or reps outside 1..1000");
+    for (int i = 0; i < n_shapes; ++i)
+        PSL_REQUIRE(blocks_per_cu[i] >= 1 && blocks_per_cu[i] <= 64,
+                    "blocks_per_cu[%d] outside 1..64", i);
+    if (ws_bytes < psl_bench_atomics_workspace_bytes(n_addresses)) {
+        set_error("workspace too small");
+        return PSL_ENOSPC;
+    }
+    if (psl_status s = check_device()) return s;
+    hipStream_t st = (hipStream_t)stream;
+    auto *a = static_cast<unsigned long long *>(d_ws);
+    hipEvent_t e0, e1;
+    PSL_HIP(hipEventCreate(&e0));
+    PSL_HIP(hipEventCreate(&e1));
+    const int cu = device_cu_count();
+    for (int i = 0; i < n_shapes; ++i) {
+        const int blocks = cu * blocks_per_cu[i];
+        float ms = 0.0f;
+        hipLaunchKernelGGL(k_atomic_replay, dim3(blocks), dim3(256), 0, st, a,
+                           (uint32_t)n_addresses, d_trace, n_trace, 1);
+        PSL_HIP(hipEventRecord(e0, st));
+        hipLaunchKernelGGL(k_atomic_replay, dim3(blocks), dim3(256), 0, st, a,
+                           (uint32_t)n_addresses, d_trace, n_trace, reps);
+        PSL_HIP(hipEventRecord(e1, st));
+        PSL_HIP(hipEventSynchronize(e1));
+        PSL_HIP(hipEventElapsedTime(&ms, e0, e1));
+        rates[i] = (double)n_trace * reps / (ms * 1e-3);
+    }
     PSL_HIP(hipEventDestroy(e0));
     PSL_HIP(hipEventDestroy(e1));
     PSL_LAUNCHED();

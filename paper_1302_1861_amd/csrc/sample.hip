@@ -270,96 +270,35 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
             const int64_t p = off[k] + (int64_t)((sk + c + (uint64_t)r) % nk);
             const FieldDev F = fields[f];
             const uint8_t type = ps.type[p];
-            const double px = ps.x[p], py = ps.y[p], pz = geo.z_psl;
-            const double du = ps.u[p], dv = ps.v[p], dw = ps.w[p];
-            int status = 1;  // 0 jaw, 2 fluence, 3 miss, 1 accepted
-            if (F.jaws_on) {
-                if (!(dw > 0.0)) {
-                    status = 0;
-                } else {
-                    double tx = du / dw, ty = dv / dw;
-                    double xj = px + tx * (geo.z_x - pz);
-                    double yj = py + ty * (geo.z_y - pz);
-                    double xlo = F.X1 * geo.z_x / geo.sad;
-                    double xhi = F.X2 * geo.z_x / geo.sad;
-                    double ylo = F.Y1 * geo.z_y / geo.sad;
-                    double yhi = F.Y2 * geo.z_y / geo.sad;
-                    if (!(xj >= xlo && xj <= xhi && yj >= ylo && yj <= yhi))
-                        status = 0;
-                }
-            }
-            double fl = 1.0;
-            if (status == 1 && F.nfx > 0) {
-                if (!(dw > 0.0)) {
-                    status = 2;
-                } else {
-                    double xs = px + (du / dw) * (geo.sad - pz);
-                    double ys = py + (dv / dw) * (geo.sad - pz);
-                    double fx = floor((xs - F.f_x0) / F.f_pix);
-                    double fy = floor((ys - F.f_y0) / F.f_pix);
-                    if (!(fx >= 0.0 && fy >= 0.0 && fx < (double)F.nfx &&
-                          fy < (double)F.nfy))
-                        fl = 0.0;
-                    else
-                        fl = (double)F.fluence[(int64_t)fy * F.nfx +
-                                               (int64_t)fx];
-                    if (!(fl > 0.0)) status = 2;
-                }
-            }
+            double o[7];
+            const int status = beam_model(F, geo, ps.x[p], ps.y[p], ps.u[p],
+                                          ps.v[p], ps.w[p], ps.wt[p], g[idx],
+                                          o);
             if (status == 1) {
-                double wgt = (double)ps.wt[p] * fl * g[idx];
-                double rx = px - geo.iso[0], ry = py - geo.iso[1],
-                       rz = pz - geo.iso[2];
-                double qx = F.cos_g * rx + F.sin_g * rz + geo.iso[0];
-                double qy = ry + geo.iso[1];
-                double qz = -F.sin_g * rx + F.cos_g * rz + geo.iso[2];
-                double eu = F.cos_g * du + F.sin_g * dw;
-                double ev = dv;
-                double ew = -F.sin_g * du + F.cos_g * dw;
-                double pos[3] = {qx, qy, qz}, dir[3] = {eu, ev, ew};
-                double tn = -INFINITY, tf = INFINITY;
-                bool miss = false;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (dir[a] != 0.0) {
-                        double t1 = (geo.lo[a] - pos[a]) / dir[a];
-                        double t2 = (geo.hi[a] - pos[a]) / dir[a];
-                        double l = t1 < t2 ? t1 : t2, u = t1 < t2 ? t2 : t1;
-                        if (l > tn) tn = l;
-                        if (u < tf) tf = u;
-                    } else if (pos[a] < geo.lo[a] || pos[a] > geo.hi[a]) {
-                        miss = true;
-                    }
+                const float oE = ps.E[p];
+                const float owt = (float)o[6];
+                int which = 0;
+                if (type != 0) {
+                    int b = 0;
+                    for (int j = 1; j < qcfg.n_ebuckets; ++j)
+                        if (oE >= s_edges[j]) b = j;
+                    which = 1 + b;
                 }
-                if (miss || tn > tf || tf <= 0.0) {
-                    status = 3;
-                } else {
-                    const double t = tn > 0.0 ? tn : 0.0;
-                    const float oE = ps.E[p];
-                    const float owt = (float)wgt;
-                    int which = 0;
-                    if (type != 0) {
-                        int b = 0;
-                        for (int j = 1; j < qcfg.n_ebuckets; ++j)
-                            if (oE >= s_edges[j]) b = j;
-                        which = 1 + b;
-                    }
-                    const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
-                                         (uint64_t)h0;
-                    slots.p.E[h0] = oE;
-                    slots.p.x[h0] = (float)(pos[0] + t * dir[0]);
-                    slots.p.y[h0] = (float)(pos[1] + t * dir[1]);
-                    slots.p.z[h0] = (float)(pos[2] + t * dir[2]);
-                    slots.p.u[h0] = (float)eu;
-                    slots.p.v[h0] = (float)ev;
-                    slots.p.w[h0] = (float)ew;
-                    slots.p.wt[h0] = owt;
-                    slots.p.uid[h0] = uid;
-                    slots.p.ctr[h0] = which ? kSourceElectronCtr : 0u;
-                    code = (uint8_t)which;
-                    st.add(which ? PSL_STAT(electrons) : PSL_STAT(photons), 1);
-                    st.addf(PSL_STAT(e_in), (double)oE * owt);
-                }
+                const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
+                                     (uint64_t)h0;
+                slots.p.E[h0] = oE;
+                slots.p.x[h0] = (float)o[0];
+                slots.p.y[h0] = (float)o[1];
+                slots.p.z[h0] = (float)o[2];
+                slots.p.u[h0] = (float)o[3];
+                slots.p.v[h0] = (float)o[4];
+                slots.p.w[h0] = (float)o[5];
+                slots.p.wt[h0] = owt;
+                slots.p.uid[h0] = uid;
+                slots.p.ctr[h0] = which ? kSourceElectronCtr : 0u;
+                code = (uint8_t)which;
+                st.add(which ? PSL_STAT(electrons) : PSL_STAT(photons), 1);
+                st.addf(PSL_STAT(e_in), (double)oE * owt);
             }
             if (status == 0) st.add(PSL_STAT(jaw_rejected), 1);
             if (status == 2) st.add(PSL_STAT(fluence_zero), 1);
@@ -518,11 +457,7 @@ psl_status sample_setup(const psl_phsp *sorted, const int64_t *d_offsets,
                     "field %d: jaw X1 > X2 or Y1 > Y2", i);
         PSL_REQUIRE(!f.fluence || (f.nfx > 0 && f.nfy > 0 && f.f_pix > 0),
                     "field %d: bad fluence map", i);
-        double th = f.gantry_deg * (M_PI / 180.0);
-        ctx->fd[i] = FieldDev{f.X1, f.X2, f.Y1, f.Y2, std::cos(th),
-                              std::sin(th), f.MU, f.fluence,
-                              f.fluence ? f.nfx : 0, f.fluence ? f.nfy : 0,
-                              f.jaws_on ? 1 : 0, 0, f.f_x0, f.f_y0, f.f_pix};
+        ctx->fd[i] = make_field_dev(f, f.jaws_on != 0, f.fluence != nullptr);
     }
     ctx->n_keys = 2LL * g->n_e * g->n_x * g->n_y;
     ctx->P = g->n_x * g->n_y;

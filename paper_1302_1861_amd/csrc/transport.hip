@@ -134,11 +134,29 @@ __device__ __forceinline__ float lerp_tab(const float *t, int n, float x) {
     return t[i] + f * (t[i + 1] - t[i]);
 }
 
+// One deposit of e x wt in voxel v.  In PSL_ACC_TRACE mode `scale` holds the
+// trace capacity and the voxel index is recorded instead: the lanes of the
+// wave that deposit here take consecutive entries (one counter update per
+// wave), so the trace keeps the order in which waves issue their deposits.
 template <int MODE>
 __device__ __forceinline__ void tally(void *acc, int64_t v, float e, float wt,
                                       double scale, uint32_t &n_dep) {
     ++n_dep;
-    if (MODE == PSL_ACC_FIXED64) {
+    if (MODE == PSL_ACC_TRACE) {
+        const uint64_t active = __ballot(1);
+        const int lane = (int)__lane_id();
+        const int leader = __ffsll((unsigned long long)active) - 1;
+        const uint32_t rank = (uint32_t)__popcll(
+            active & ((lane ? ~0ull >> (64 - lane) : 0ull)));
+        unsigned long long base = 0;
+        if (lane == leader)
+            base = atomicAdd(reinterpret_cast<unsigned long long *>(acc),
+                             (unsigned long long)__popcll(active));
+        base = __shfl(base, leader);
+        const uint64_t i = base + rank;
+        if (i < (uint64_t)scale)
+            (reinterpret_cast<uint32_t *>(acc) + 2)[i] = (uint32_t)v;
+    } else if (MODE == PSL_ACC_FIXED64) {
         // the product of two floats is exact in double; rounded to the
         // nearest step, ties to even (rounding ties up biased the sum:
         // sub-p_cut photon deposits at weight 1/4 are exact halves half of
@@ -1077,7 +1095,9 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     PSL_REQUIRE(acc->data, "NULL dose accumulator");
     PSL_REQUIRE(acc->mode == PSL_ACC_F64 ||
                     (acc->mode == PSL_ACC_FIXED64 && acc->frac_bits >= 16 &&
-                     acc->frac_bits <= 40),
+                     acc->frac_bits <= 40) ||
+                    (acc->mode == PSL_ACC_TRACE && acc->trace_capacity >= 0 &&
+                     acc->trace_capacity < ((int64_t)1 << 40)),
                 "bad accumulator mode %d / frac_bits %d", acc->mode,
                 acc->frac_bits);
     PSL_REQUIRE(phys->t_cut > 0 && phys->p_cut > 0 && phys->step > 0 &&
@@ -1118,8 +1138,10 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     const int64_t cap_b = q->el.capacity / q->n_ebuckets;
     const float *tab = static_cast<const float *>(d_tables);
     const double scale =
-        acc->mode == PSL_ACC_FIXED64 ? std::ldexp(1.0, acc->frac_bits) : 1.0;
-    const bool fixed = acc->mode == PSL_ACC_FIXED64;
+        acc->mode == PSL_ACC_FIXED64 ? std::ldexp(1.0, acc->frac_bits)
+        : acc->mode == PSL_ACC_TRACE ? (double)acc->trace_capacity
+                                     : 1.0;
+    const int mode = acc->mode;
     dim3 grid((unsigned)blocks), block(kBlock);
     hipLaunchKernelGGL(k_transport_init, dim3(1024), dim3(256), 0, st,
                        w.words, w.n_words,
@@ -1128,12 +1150,16 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
                        w.sec.n_chunks);
     {
         ProfScope prof(PSL_PROF_PHOTONS, st);
-        if (fixed)
+        if (mode == PSL_ACC_FIXED64)
             hipLaunchKernelGGL(k_photons<PSL_ACC_FIXED64>, grid, block, 0, st,
                                q->ph, q->d_counts, w.sec, *q, P, Y, tab, seed,
                                acc->data, scale, work_ph, w.part);
-        else
+        else if (mode == PSL_ACC_F64)
             hipLaunchKernelGGL(k_photons<PSL_ACC_F64>, grid, block, 0, st,
+                               q->ph, q->d_counts, w.sec, *q, P, Y, tab, seed,
+                               acc->data, scale, work_ph, w.part);
+        else
+            hipLaunchKernelGGL(k_photons<PSL_ACC_TRACE>, grid, block, 0, st,
                                q->ph, q->d_counts, w.sec, *q, P, Y, tab, seed,
                                acc->data, scale, work_ph, w.part);
     }
@@ -1155,14 +1181,18 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     {
         ProfScope prof(PSL_PROF_ELECTRONS, st);
         uint64_t *part_el = w.part + (int64_t)blocks * kStatWords;
-        if (fixed)
+        if (mode == PSL_ACC_FIXED64)
             hipLaunchKernelGGL(k_electrons<PSL_ACC_FIXED64>, grid, block, 0,
                                st, ew, P, Y, tab, seed, acc->data, scale,
                                work_el, part_el);
-        else
+        else if (mode == PSL_ACC_F64)
             hipLaunchKernelGGL(k_electrons<PSL_ACC_F64>, grid, block, 0, st,
                                ew, P, Y, tab, seed, acc->data, scale, work_el,
                                part_el);
+        else
+            hipLaunchKernelGGL(k_electrons<PSL_ACC_TRACE>, grid, block, 0,
+                               st, ew, P, Y, tab, seed, acc->data, scale,
+                               work_el, part_el);
     }
     if ((s = stats_reduce(w.part, 2 * blocks, d_stats, st))) return s;
     hipLaunchKernelGGL(k_consume, dim3(1), dim3(64), 0, st, q->d_counts,

@@ -14,13 +14,14 @@ from typing import Dict, List, Optional
 import numpy as np
 
 from . import (PART_KEYS, PHSP_KEYS, PSL_ACC_F64, PSL_ACC_FIXED64,
+               PSL_ACC_TRACE,
                PSL_ALLOC_COUNTS, PSL_MAX_QBUCKETS, PSL_QCOUNTS,
                PSL_TABLE_BYTES, PSL_TALLY_FINALIZE, PSL_TALLY_FOLD, lib,
                make_fields, make_grid, make_particles, make_phantom,
                make_physics, make_phsp, psl_build, psl_dose_acc,
                psl_launch, psl_physics_init, psl_queue, psl_sample,
                psl_sample_cfg, psl_stats, dose_tally, transport_batch,
-               stats_to_dict)
+               stats_to_dict, psl_stream_cfg, psl_stream_sample)
 
 DEFAULT_BUCKET_EDGES = (0.0, 0.3, 0.5, 0.8, 1.2, 1.8, 2.6, 3.8)
 
@@ -66,7 +67,11 @@ class Engine:
                  n_ebuckets=8, bucket_edges=DEFAULT_BUCKET_EDGES,
                  electron_factor=1.5, frac_bits=32, phys_flags=0,
                  launch: Optional[psl_launch] = None, iso=(0.0, 0.0, 100.0),
-                 sad=100.0, z_jaw_x=37.0, z_jaw_y=28.0, seed=None):
+                 sad=100.0, z_jaw_x=37.0, z_jaw_y=28.0, seed=None,
+                 source="psl", bin_capacity=1 << 20):
+        """source: "psl" (Method 3, the PSL source), or "method1" /
+        "method2" (the phase space in file order with on-the-fly bins of
+        bin_capacity particles, psl_stream_sample; one field)."""
         import torch
         self.torch = torch
         self.device = device
@@ -90,7 +95,12 @@ class Engine:
                  device)
         psl_build(raw, self.grid, self.sorted, self.offsets, self.n_dropped,
                   ws)
-        del ws, raw
+        del ws
+        if source not in ("psl", "method1", "method2"):
+            raise ValueError("source must be psl, method1 or method2")
+        self.source = source
+        self.raw = raw if source != "psl" else None
+        del raw
         # fields
         self.fluence = [None if f.fluence is None else
                         torch.from_numpy(np.ascontiguousarray(
@@ -166,6 +176,32 @@ class Engine:
             C.byref(self.queue)), device)
         self.n_kept = None
         self.folded = 0
+        if source != "psl":
+            if len(wl.fields) != 1:
+                raise ValueError("the Method 1/2 source takes one field")
+            self.scfg = psl_stream_cfg()
+            sc = self.scfg
+            sc.seed = self.seed
+            sc.n_histories = self.hpb
+            sc.bin_capacity = int(bin_capacity)
+            sc.method = 1 if source == "method1" else 2
+            self._e_edges = (C.c_float * len(wl.grid.e_edges))(
+                *[float(v) for v in wl.grid.e_edges])
+            sc.n_e = len(wl.grid.e_edges) - 1
+            sc.e_edges = C.cast(self._e_edges, C.c_void_p)
+            sc.weight = float(ps.n) / self.hpb
+            sc.z_plane = wl.grid.z_plane
+            sc.sad, sc.z_jaw_x, sc.z_jaw_y = sad, z_jaw_x, z_jaw_y
+            for a in range(3):
+                sc.iso[a] = iso[a]
+                sc.box_lo[a] = lo[a]
+                sc.box_hi[a] = hi[a]
+            mf = self.hpb // int(bin_capacity) + 2 * sc.n_e
+            self.flushes = torch.zeros((mf, 4), dtype=torch.int64,
+                                       device=device)
+            self.n_flushes = torch.zeros(1, dtype=torch.int64, device=device)
+            self.ws_stream = _ws(lib().psl_stream_workspace_bytes(
+                self.hpb, sc.n_e, int(bin_capacity)), device)
 
     # ------------------------------------------------- swapping inputs --
     def set_phantom(self, ph):
@@ -211,6 +247,12 @@ class Engine:
         return self.n_kept
 
     def sample(self, batch, mask=None, alloc=None):
+        if self.source != "psl":
+            self.scfg.batch = batch
+            psl_stream_sample(self.raw, self.fields, self.scfg, self.queue,
+                              self.flushes, self.n_flushes, self.stats,
+                              self.ws_stream)
+            return
         self.cfg.batch = batch
         psl_sample(self.sorted, self.offsets, self.grid, self.fields,
                    self.cfg, self.queue, self.stats, self.ws_sample,
@@ -237,6 +279,28 @@ class Engine:
         dose_tally(None, self.s1, self.s2, PSL_TALLY_FINALIZE, self.folded,
                    self.phantom, norm, self.dose, self.sigma)
         return self.dose, self.sigma
+
+    def deposit_trace(self, batch, capacity=None):
+        """Samples and transports one batch with the accumulator in trace
+        mode: returns the voxel index of every deposit in issue order
+        (device int32 tensor holding uint32 values) and the deposit count.
+        The dose tallies are not touched."""
+        torch = self.torch
+        cap = int(capacity or 8 * self.hpb)
+        buf = torch.zeros(2 + cap, dtype=torch.int32, device=self.device)
+        acc = psl_dose_acc()
+        acc.mode = PSL_ACC_TRACE
+        acc.data = buf.data_ptr()
+        acc.trace_capacity = cap
+        self.sample(batch)
+        transport_batch(self.queue, self.phantom, self.phys, self.tables,
+                        self.seed, acc, self.stats, self.ws_transport,
+                        self.launch)
+        n = int(buf[:2].cpu().numpy().view(np.uint64)[0])
+        if n > cap:
+            raise ValueError("trace of %d deposits exceeds capacity %d"
+                             % (n, cap))
+        return buf[2:2 + n], n
 
     def reset_tally(self):
         self.s1.zero_()

@@ -207,6 +207,8 @@ class Field:
     f_y0: float = -20.0
     f_pix: float = 1.0
     jaws: bool = True
+    collimator_deg: float = 0.0
+    couch_deg: float = 0.0
 
 
 def square_field(side: float, MU: float = 1.0) -> Field:
@@ -245,6 +247,38 @@ def imrt_plan(seed: int, n_beams: int = 7, n_segments: int = 20,
             mu = float(rng.uniform(1.0, 100.0))
             out.append(Field(cx - wx / 2, cx + wx / 2, cy - wy / 2,
                              cy + wy / 2, gantry_deg=g, MU=mu, fluence=fl))
+    return out
+
+
+def vmat_plan(seed: int, arcs=((0.0, 360.0, 30.0, 0.0),
+                                (90.0, 270.0, 330.0, 90.0)),
+              step_deg: float = 4.0, lim: float = 12.0) -> List[Field]:
+    """Arcs as many control points (Sec. 2.4: one fluence map per beam
+    angle).  Each arc (gantry start, gantry stop, collimator, couch) gets a
+    control point every step_deg degrees of gantry; a control point has
+    jaws that follow a slowly moving aperture (sides 4-16 cm, edges within
+    +-lim), a 40x40 fluence map of its own (a smooth field times U[0.5, 1]
+    noise) and MU ~ U[0.5, 2]."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for g0, g1, coll, couch in arcs:
+        n = int(round((g1 - g0) / step_deg))
+        phase = rng.uniform(0, 2 * np.pi, 4)
+        for k in range(n):
+            g = (g0 + k * step_deg) % 360.0
+            a = 2 * np.pi * k / max(n, 1)
+            wx = 10.0 + 6.0 * np.sin(a + phase[0])
+            wy = 10.0 + 6.0 * np.sin(a + phase[1])
+            cx = (lim - wx / 2) * 0.5 * np.sin(2 * a + phase[2])
+            cy = (lim - wy / 2) * 0.5 * np.sin(2 * a + phase[3])
+            yy, xx = np.mgrid[0:40, 0:40]
+            smooth = 0.5 + 0.5 * np.cos((xx - 20) / 40.0 * np.pi * (1 + k % 3)) \
+                * np.cos((yy - 20) / 40.0 * np.pi)
+            fl = (smooth * rng.uniform(0.5, 1.0, (40, 40))).astype(np.float32)
+            out.append(Field(cx - wx / 2, cx + wx / 2, cy - wy / 2,
+                             cy + wy / 2, gantry_deg=g,
+                             MU=float(rng.uniform(0.5, 2.0)), fluence=fl,
+                             collimator_deg=coll, couch_deg=couch))
     return out
 
 
@@ -315,6 +349,20 @@ def workload_heterogeneous(n_particles: int = 10_000_000,
                                (-nx * voxel / 2, -ny * voxel / 2, SAD), 1003)
     return Workload("heterogeneous-256x256x160", ps, clinical_grid(), ph,
                     [f], histories, batches, True, True, 0, 2003)
+
+
+def workload_vmat(n_particles: int = 10_000_000,
+                  histories: int = 1_000_000_000,
+                  batches: int = 10, step_deg: float = 4.0) -> Workload:
+    """Two arcs as control points on the 128^3 water phantom centred on
+    the isocentre: a coplanar 360-degree arc at collimator 30, and a
+    non-coplanar 180-degree arc at couch 90 and collimator 330 (135 control
+    points at 4 degrees); histories proportional to MU."""
+    ps = phase_space(n_particles, 1002, 20.0, Z_PSL)
+    ph = water_phantom((128, 128, 128), 0.25, (-16.0, -16.0, SAD - 16.0))
+    return Workload("vmat-2arcs-water-128", ps, clinical_grid(), ph,
+                    vmat_plan(1006, step_deg=step_deg), histories, batches,
+                    True, True, 1, 2006)
 
 
 def workload_imrt(n_particles: int = 10_000_000,

@@ -51,12 +51,12 @@ def test_struct_sizes_match_c():
 #include <stdio.h>
 #include "psl.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n",
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n",
     sizeof(psl_phsp), sizeof(psl_grid), sizeof(psl_field),
     sizeof(psl_sample_cfg), sizeof(psl_particles), sizeof(psl_queue),
     sizeof(psl_stats), sizeof(psl_phantom), sizeof(psl_physics),
     sizeof(psl_dose_acc), sizeof(psl_launch), sizeof(psl_tune_result),
-    (size_t)PSL_QCOUNTS);
+    sizeof(psl_stream_cfg), sizeof(psl_flush), (size_t)PSL_QCOUNTS);
   return 0; }
 '''
     with tempfile.TemporaryDirectory() as d:
@@ -69,6 +69,6 @@ int main(void) {
     want = [ctypes.sizeof(s) for s in (
         P.psl_phsp, P.psl_grid, P.psl_field, P.psl_sample_cfg,
         P.psl_particles, P.psl_queue, P.psl_stats, P.psl_phantom,
-        P.psl_physics, P.psl_dose_acc, P.psl_launch, P.psl_tune_result)] + \
-        [P.PSL_QCOUNTS]
+        P.psl_physics, P.psl_dose_acc, P.psl_launch, P.psl_tune_result,
+        P.psl_stream_cfg, P.psl_flush)] + [P.PSL_QCOUNTS]
     assert got == want

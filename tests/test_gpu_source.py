@@ -169,6 +169,14 @@ def test_sample_imrt_plan_mu_allocation_and_rotation():
     _check_sample(wl, 2_000_003, batches=(0, 5), iso=(0.0, 0.0, 100.0))
 
 
+def test_sample_vmat_collimator_and_couch_rotations():
+    """Two arcs of control points (Sec. 2.4), one at collimator 30, one at
+    couch 90 and collimator 330 (Sec. 2.3.3: collimator, gantry and couch
+    rotations of each particle), MU-proportional allocation."""
+    wl = S.workload_vmat(n_particles=1_000_000, step_deg=12.0)
+    _check_sample(wl, 1_500_001, batches=(0, 2), iso=(0.0, 0.0, 100.0))
+
+
 @pytest.mark.parametrize("hpb", [0, 1, 63, 12_345])
 def test_sample_ragged_history_counts(hpb):
     wl = S.workload_clinical(side=10.0, n_particles=200_000)

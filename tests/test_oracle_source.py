@@ -300,3 +300,76 @@ def test_sample_state_rotation_and_projection(oracle_lib):
         # weight: g of the PSL, unit fluence and phase-space weight
         key = smp["key"][ok]
         np.testing.assert_allclose(st[:, 7], g[0, key], rtol=1e-15)
+
+
+def test_sample_collimator_and_couch_rotations(oracle_lib):
+    """Collimator, gantry and couch (Sec. 2.3.3: each particle receives the
+    three rotations of its field), checked against rotation matrices built
+    here: the phase space turns with the collimator about the central axis
+    (so the jaw test is unchanged), then the gantry turns it about +y and
+    the couch turns the patient by +angle about the vertical through the
+    isocentre (the beam by -angle): p' = iso + Rz(-t) Ry(g) Rz(c) (p - iso).
+    The particle lies on the turned ray and on the phantom surface; with all
+    three angles zero the state is the unturned one bit for bit."""
+    ps = S.phase_space(4000, 43, 20.0, S.Z_PSL)
+    grid = S.clinical_grid()
+    ph = S.water_phantom((32, 32, 32), 1.0, (-16.0, -16.0, 84.0))
+    geom = oracle_lib.geometry(ph)
+    perm, off, _ = oracle_lib.build_psl(ps, grid)
+    sps = ps.subset(perm)
+
+    def rz(a):
+        c, s = math.cos(a), math.sin(a)
+        return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1.0]])
+
+    def ry(a):
+        c, s = math.cos(a), math.sin(a)
+        return np.array([[c, 0, s], [0, 1, 0], [-s, 0, c]])
+
+    base = None
+    for gdeg, cdeg, tdeg in ((0, 0, 0), (0, 30, 0), (0, 0, 90), (45, 15, 270),
+                             (200, 330, 10)):
+        f = S.Field(-6, 7, -5, 8, gantry_deg=gdeg, collimator_deg=cdeg,
+                    couch_deg=tdeg)
+        mask = oracle_lib.cull([f], grid, True, geom)
+        N, g, _ = oracle_lib.alloc([f], 0, 3000, off, mask, grid)
+        smp = oracle_lib.sample([f], geom, off, N, g, 0, 3, sps)
+        if base is None:
+            base = smp
+        # the jaw test is in the phase space's own frame: same decisions
+        np.testing.assert_array_equal(smp["status"] == 0,
+                                      base["status"] == 0)
+        ok = smp["status"] == 1
+        st, src = smp["state"][ok], smp["src"][ok]
+        R = rz(-math.radians(tdeg)) @ ry(math.radians(gdeg)) @ \
+            rz(math.radians(cdeg))
+        iso = np.array([0, 0, 100.0])
+        p0 = np.stack([sps.x[src], sps.y[src],
+                       np.full(len(src), 25.0)], 1).astype(np.float64)
+        d0 = np.stack([sps.u[src], sps.v[src], sps.w[src]], 1).astype(
+            np.float64)
+        p1 = (p0 - iso) @ R.T + iso
+        d1 = d0 @ R.T
+        np.testing.assert_allclose(st[:, 4:7], d1, atol=1e-12)
+        dp = st[:, 1:4] - p1
+        t = (dp * d1).sum(1)
+        assert np.all(t >= -1e-9)
+        np.testing.assert_allclose(dp, t[:, None] * d1, atol=1e-9)
+        lo, hi = np.array(geom["box_lo"]), np.array(geom["box_hi"])
+        on = np.isclose(st[:, 1:4], lo, atol=1e-9) | \
+            np.isclose(st[:, 1:4], hi, atol=1e-9)
+        assert np.all(on.any(1))
+    # couch 90 at gantry 0 turns the beam about its own axis: the state is
+    # the unturned particle turned by -90 degrees about z through the
+    # isocentre, exactly on the beam's entry plane
+    f0 = S.Field(-6, 7, -5, 8)
+    f1 = S.Field(-6, 7, -5, 8, couch_deg=90.0)
+    m = oracle_lib.cull([f0], grid, True, geom)
+    N, g, _ = oracle_lib.alloc([f0], 0, 3000, off, m, grid)
+    a = oracle_lib.sample([f0], geom, off, N, g, 1, 3, sps)
+    b = oracle_lib.sample([f1], geom, off, N, g, 1, 3, sps)
+    ok = (a["status"] == 1) & (b["status"] == 1)
+    np.testing.assert_allclose(b["state"][ok, 1], a["state"][ok, 2],
+                               atol=1e-9)
+    np.testing.assert_allclose(b["state"][ok, 2], -a["state"][ok, 1],
+                               atol=1e-9)
