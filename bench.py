@@ -117,10 +117,10 @@ def unet_forward_flops(shape, base=16, in_c=2):
                for l, ci, co in layers)
 
 
-def bench_imrt(P, S, torch, hpb, n_batches):
-    """The batched IMRT plan: 7 beams x 20 segments, MU-proportional
-    histories, autotuned, replayed from a hipGraph."""
-    wl = S.workload_imrt()
+def bench_imrt(P, S, torch, hpb, n_batches, wl=None):
+    """A batched plan (default: the IMRT plan, 7 beams x 20 segments),
+    MU-proportional histories, autotuned, replayed from a hipGraph."""
+    wl = wl or S.workload_imrt()
     # graph capture needs a created stream (not the legacy null stream)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -147,9 +147,9 @@ def bench_imrt(P, S, torch, hpb, n_batches):
     roof = hbm_roofline(groups, st, eng.nvox)
     atom = atomic_roofline(P, eng, groups, st, 0, replay=False)
     plan.destroy()
-    return {"workload": "IMRT-like plan: 7 coplanar beams x 20 segments, "
-                        "MU-proportional, 128^3 water at 2.5 mm, "
-                        "%d batches of %d histories" % (n_batches, hpb),
+    return {"workload": "%s: %d fields, MU-proportional, 128^3 water at "
+                        "2.5 mm, %d batches of %d histories"
+                        % (wl.name, len(wl.fields), n_batches, hpb),
             "histories": n_batches * hpb, "seconds": dt,
             "histories_per_s": n_batches * hpb / dt,
             "ms_per_batch": 1e3 * dt / n_batches, "graph": True,
@@ -370,6 +370,9 @@ def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
         raise SystemExit("queue overflow: batch invalid (%s)" % wl.name)
     d, s = eng.finalize()
     torch.cuda.synchronize()
+    shp = wl.phantom.density.shape
+    ref = P.dose_point(d.view(shp), s.view(shp), eng.phantom,
+                       REF_POINT, REF_RADIUS)
     d = d.cpu().numpy()
     s = s.cpu().numpy()
     sel = d >= 0.5 * d.max()
@@ -387,8 +390,77 @@ def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
                "interactions", "secondaries", "segments", "deposits",
                "photon_deposits", "flights")},
            "mean_rel_sigma_50pct": sbar,
-           "time_to_1pct_s": elapsed * (sbar / 0.01) ** 2}
+           "time_to_1pct_s": elapsed * (sbar / 0.01) ** 2,
+           "reference_point_dose": {"point_cm": list(REF_POINT),
+                                    "radius_cm": REF_RADIUS,
+                                    "gy_per_particle": ref[0],
+                                    "standard_error": ref[1],
+                                    "voxels": ref[2]}}
     return rec, eng
+
+
+# Reference point of the calibration and output factors: 10 cm deep on the
+# central axis (SSD 100 cm), dose averaged over a sphere of 5 mm radius.
+REF_POINT = (0.0, 0.0, 110.0)
+REF_RADIUS = 0.5
+CAL_DOSE_GY_PER_MU = 0.774e-2     # the paper's calibration condition
+
+
+def output_factors(P, recs):
+    """Relative output factors and the calibration factor from the
+    reference-point doses of the open-field runs (records with field_cm)."""
+    ref = {r["field_cm"]: (r["reference_point_dose"]["gy_per_particle"],
+                           r["reference_point_dose"]["standard_error"])
+           for r in recs}
+    rof = P.output_factors(ref, 10.0)
+    cf = P.calibration_factor(ref[10.0][0], CAL_DOSE_GY_PER_MU)
+    return {"reference_point_cm": list(REF_POINT), "radius_cm": REF_RADIUS,
+            "rof": {str(k): {"value": v[0], "standard_error": v[1]}
+                    for k, v in sorted(rof.items())},
+            "calibration_factor_particles_per_mu": cf,
+            "calibration_dose_gy_per_mu": CAL_DOSE_GY_PER_MU,
+            "monitor_backscatter": "none applied (no head model)"}
+
+
+def bench_apr_latent(P, torch, S, n=20_000, recycling=(10, 100),
+                     copies=(0, 16), seeds=8, batches=10):
+    """Latent variance of a small cylindrically symmetric phase space (n
+    particles aimed over a 10 cm disk) against the recycling factor, with
+    and without azimuthal redistribution: for each setting, the per-voxel
+    dose variance across independent phase spaces over the mean batch
+    variance, voxels 2-12 cm deep at or above half the maximum there (32^3
+    water at 1 cm, 10x10 cm field)."""
+    import numpy as np
+    out = []
+    for R in recycling:
+        for k in copies:
+            ds, ss = [], []
+            for sd in range(seeds):
+                ps = S.phase_space(n, 500 + sd, 10.0, S.Z_PSL, aim="disk")
+                wl = S.workload_clinical(side=10.0, n_particles=10)
+                wl.phsp = ps
+                wl.phantom = S.water_phantom((32, 32, 32), 1.0,
+                                             (-16.0, -16.0, 100.0))
+                eng = P.Engine(wl, histories_per_batch=R * n // batches,
+                               apr_copies=k, apr_seed=900 + sd)
+                d, sg = eng.run(batches=batches)
+                torch.cuda.synchronize()
+                ds.append(d.cpu().numpy().astype(np.float64))
+                ss.append(sg.cpu().numpy().astype(np.float64))
+                del eng
+            ds, ss = np.array(ds), np.array(ss)
+            m = ds.mean(0).reshape(32, 32, 32)
+            win = np.zeros((32, 32, 32), bool)
+            win[2:12] = True
+            sel = (win & (m >= 0.5 * m[2:12].max())).ravel()
+            v = float(ds[:, sel].var(0, ddof=1).mean())
+            b = float((ss[:, sel] ** 2).mean())
+            out.append({"recycling": R, "apr_copies": k, "voxels":
+                        int(sel.sum()), "variance_across_phase_spaces": v,
+                        "mean_batch_variance": b, "ratio": v / b})
+            print("apr latent R=%d k=%d ratio %.2f" % (R, k, v / b),
+                  file=sys.stderr, flush=True)
+    return out
 
 
 def bench_methods(P, torch, S, H, steps=10, sides=(4.0, 10.0, 30.0)):
@@ -511,7 +583,7 @@ def main():
     def say(msg):
         print(msg, file=sys.stderr, flush=True)
 
-    def extras(out, eng):
+    def extras(out, eng, main_rec=None):
         nz, ny, nx = eng.wl.phantom.density.shape
         out["denoiser"] = bench_denoiser(P, torch, eng.dose, eng.density,
                                          (nz, ny, nx))
@@ -523,9 +595,15 @@ def main():
             rec, e2 = measure_workload(P, torch,
                                        S.workload_clinical(side=side), H, 10,
                                        2, launch)
+            rec["field_cm"] = side
             out["workloads"].append(rec)
             del e2
             say("field %g done" % side)
+        if args.field == 10.0 and main_rec is not None:
+            main_rec["field_cm"] = 10.0
+            out["output_factors"] = output_factors(
+                P, [main_rec] + [r for r in out["workloads"]
+                                 if "field_cm" in r])
         wl_h = S.workload_heterogeneous()
         rec, e2 = measure_workload(P, torch, wl_h, H,
                                    wl_h.histories // H, 2, launch)
@@ -535,7 +613,11 @@ def main():
         say("heterogeneous done")
         out["imrt_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches)
         say("imrt done")
+        out["vmat_plan"] = bench_imrt(P, S, torch, H, args.imrt_batches,
+                                      wl=S.workload_vmat())
+        say("vmat done")
         out["method2_vs_psl"] = bench_methods(P, torch, S, H)
+        out["apr_latent_variance"] = bench_apr_latent(P, torch, S)
         out["psl_build"] = bench_build(P, torch, S)
         out["time_to_accuracy"] = bench_time_to_accuracy()
 
@@ -584,10 +666,11 @@ def main():
                    "parallelism": "single GPU"},
     }
     for k in ("roofline", "atomic_roofline", "kernel_ms", "batch_stats",
-              "time_to_1pct_s", "mean_rel_sigma_50pct"):
+              "time_to_1pct_s", "mean_rel_sigma_50pct",
+              "reference_point_dose"):
         out[k] = rec[k]
     if not args.no_extras:
-        extras(out, eng)
+        extras(out, eng, rec)
     del eng
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

@@ -82,6 +82,8 @@ typedef struct psl_grid {
  *   in        device SoA of in->n particles (read only); n < 2^31.
  *   out       device SoA with out->n >= in->n; receives the kept particles
  *             in PSL order (entries past the kept count are untouched).
+ * Implemented as an LSD radix sort by key whose passes carry the particle
+ * columns, so no pass gathers from random positions.
  *   d_offsets device int64[2 * n_e * n_x * n_y + 1]: PSL k holds
  *             out[d_offsets[k] .. d_offsets[k+1]).
  *   d_n_dropped device int64[1]: particles of unknown type (> 1), NaN, or
@@ -93,6 +95,31 @@ size_t psl_build_workspace_bytes(int64_t n, const psl_grid *g);
 psl_status psl_build(const psl_phsp *in, const psl_grid *g, psl_phsp *out,
                      int64_t *d_offsets, int64_t *d_n_dropped, void *d_ws,
                      size_t ws_bytes, void *stream);
+
+/*
+ * psl_build_apr - PSL generation with azimuthal particle redistribution
+ * (Sec. 2.3.1), for a cylindrically symmetric phase space: every particle
+ * i is replaced by `copies` copies m = i * copies + j, each turned about
+ * the central axis (x = y = 0) by its own uniform azimuth, position and
+ * direction cosines alike, weight wt / copies, energy, type and w kept;
+ * the PSLs are then built from the copies exactly as psl_build does (so
+ * the bins see the turned positions).  The azimuth of copy m: a point
+ * (a, b) uniform in the unit disk by rejection from the stream
+ * splitmix64(splitmix64(seed ^ m) + t), t = 0, 1, ... (two draws per
+ * attempt, the top 53 bits of each scaled to [-1, 1)), and the turn by
+ * twice its angle: cos = (a^2 - b^2) / r^2, sin = 2ab / r^2 (no copy is
+ * turned after 64 failed attempts, probability < 1e-42).  Double
+ * precision without contraction, rounded to float.
+ *   copies 1 .. 4096, in->n * copies < 2^31; out->n >= in->n * copies;
+ *   workspace psl_build_apr_workspace_bytes(in->n, copies, g).
+ * Errors as psl_build.
+ */
+size_t psl_build_apr_workspace_bytes(int64_t n, int64_t copies,
+                                     const psl_grid *g);
+psl_status psl_build_apr(const psl_phsp *in, const psl_grid *g,
+                         int64_t copies, uint64_t seed, psl_phsp *out,
+                         int64_t *d_offsets, int64_t *d_n_dropped,
+                         void *d_ws, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
 /* Source sampling.                                                          */
@@ -439,6 +466,23 @@ psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
  * d_s1, d_s2: device double [voxels]; d_dose, d_sigma: device float
  * [voxels] (FINALIZE only).
  */
+/*
+ * dose_point - the dose at a reference point, for absolute calibration and
+ * relative output factors (Sec. 2.5): the mean of d_dose over the voxels
+ * whose centres lie within `radius` cm of (x, y, z) (the voxel holding the
+ * point when no centre does), with the standard error of that mean from
+ * d_sigma, sqrt(sum sigma^2) / count.  d_dose, d_sigma: device float
+ * [nz][ny][nx] as dose_tally FINALIZE writes them.  d_out: device double
+ * [3] = {mean dose, its standard error, voxel count} (all 0 when the point
+ * lies outside the phantom and no centre is within the radius).  The sum
+ * runs in a fixed order, so repeated calls agree bit for bit.
+ * Errors: PSL_EINVAL (NULL, bad phantom, negative radius, a sphere over
+ * more than 2^26 voxels).
+ */
+psl_status dose_point(const float *d_dose, const float *d_sigma,
+                      const psl_phantom *ph, double x, double y, double z,
+                      double radius, double *d_out, void *stream);
+
 #define PSL_TALLY_FOLD 0
 #define PSL_TALLY_FINALIZE 1
 psl_status dose_tally(psl_dose_acc *acc, double *d_s1, double *d_s2,

@@ -121,6 +121,10 @@ def _declare(L):
                                 vp, vp, vp, vp, vp, vp, vp, vp,
                                 vp, vp, vp, vp, vp]
     L.oracle_sample.restype = None
+    L.oracle_apr_rotation.argtypes = [u64, u64, C.POINTER(d), C.POINTER(d)]
+    L.oracle_apr_rotation.restype = None
+    L.oracle_apr_expand.argtypes = [i64, i64, u64] + [vp] * 16
+    L.oracle_apr_expand.restype = None
     L.oracle_stream.argtypes = [vp, vp, i32, i64] + [vp] * 8 + \
         [i32, vp, i64, i64, u64, d, i64, vp, vp, vp, vp, vp, vp, vp]
     L.oracle_stream.restype = i64
@@ -285,6 +289,30 @@ def sample(fields, geom, offsets, N, g, batch, seed, ps):
             "type": ps.type[src] if n_hist else np.zeros(0, np.uint8)}
 
 
+def apr_rotation(seed, m):
+    """(cos, sin) of the APR azimuth of copy m (Sec. 2.3.1)."""
+    c, s = C.c_double(), C.c_double()
+    lib().oracle_apr_rotation(C.c_uint64(seed), C.c_uint64(m), C.byref(c),
+                              C.byref(s))
+    return c.value, s.value
+
+
+def apr_expand(ps, copies, seed):
+    """The APR-expanded phase space (Sec. 2.3.1): `copies` azimuthally
+    redistributed copies of every particle, weight wt / copies; the PSLs
+    are then built from it by build_psl."""
+    from psl_synth import PhaseSpace
+    n, k = int(ps.n), int(copies)
+    c = np.ascontiguousarray
+    cols = [c(getattr(ps, f)) for f in ("type", "E", "x", "y", "u", "v", "w",
+                                         "wt")]
+    out = [np.zeros(n * k, np.uint8)] + [np.zeros(n * k, np.float32)
+                                         for _ in range(7)]
+    lib().oracle_apr_expand(n, k, C.c_uint64(seed), *[_p(a) for a in cols],
+                            *[_p(a) for a in out])
+    return PhaseSpace(*out, z_plane=ps.z_plane)
+
+
 def stream_sample(field, geom, ps, e_edges, n_hist, batch, seed, cap,
                   method=2, weight=None):
     """Methods 1 and 2 (Sec. 2.1, 2.2) for one batch: the phase space read
@@ -331,6 +359,33 @@ def stream_sample(field, geom, ps, e_edges, n_hist, batch, seed, cap,
             "flush_bin": fb[:nf], "flush_count": fc[:nf],
             "flush_trigger": ft[:nf], "flush_first": ff[:nf],
             "seq": seq[:n_seq], "weight": g}
+
+
+def dose_point(dose, sigma, phantom, point, radius):
+    """Reference-point dose (Sec. 2.5): mean of the dose over the voxels
+    whose centres lie within `radius` of `point` (the voxel holding the
+    point when none does), standard error sqrt(sum sigma^2) / count.
+    Returns (mean, standard error, count)."""
+    nz, ny, nx = phantom.density.shape
+    dx, dy, dz = phantom.voxel
+    x0, y0, z0 = phantom.origin
+    d = np.asarray(dose, np.float64).reshape(nz, ny, nx)
+    s = np.asarray(sigma, np.float64).reshape(nz, ny, nx)
+    cz = z0 + (np.arange(nz) + 0.5) * dz - point[2]
+    cy = y0 + (np.arange(ny) + 0.5) * dy - point[1]
+    cx = x0 + (np.arange(nx) + 0.5) * dx - point[0]
+    r2 = cz[:, None, None] ** 2 + cy[None, :, None] ** 2 + \
+        cx[None, None, :] ** 2
+    m = r2 <= radius * radius
+    n = int(m.sum())
+    if n == 0:
+        i = math.floor((point[0] - x0) / dx)
+        j = math.floor((point[1] - y0) / dy)
+        k = math.floor((point[2] - z0) / dz)
+        if 0 <= i < nx and 0 <= j < ny and 0 <= k < nz:
+            return float(d[k, j, i]), float(s[k, j, i]), 1
+        return 0.0, 0.0, 0
+    return float(d[m].sum() / n), float(math.sqrt((s[m] ** 2).sum()) / n), n
 
 
 # ---------------------------------------------------------------------------

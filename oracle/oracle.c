@@ -147,6 +147,63 @@ int64_t oracle_build(int64_t n, const uint8_t *type, const float *E,
     return n - dropped;
 }
 
+/* Azimuthal particle redistribution (Sec. 2.3.1).  Copy m of the expanded
+ * phase space turns about the central axis by an azimuth drawn uniformly:
+ * a point (a, b) uniform in the unit disk by rejection from the stream
+ * splitmix64(key + t), key = splitmix64(seed ^ m), two draws per attempt,
+ * each the top 53 bits scaled to [-1, 1); the angle of (a, b) is uniform
+ * and so is twice it, whose cosine and sine are (a^2 - b^2) / r^2 and
+ * 2ab / r^2 (no square root or trigonometry, so the value is exact IEEE
+ * arithmetic on any machine).  After 64 failed attempts (probability
+ * below 1e-42) the copy is not turned. */
+void oracle_apr_rotation(uint64_t seed, uint64_t m, double *c, double *s)
+{
+    const uint64_t key = oracle_splitmix64(seed ^ m);
+    for (uint64_t t = 0; t < 64; ++t) {
+        double a = (double)(oracle_splitmix64(key + 2 * t) >> 11) *
+                   0x1.0p-53 * 2.0 - 1.0;
+        double b = (double)(oracle_splitmix64(key + 2 * t + 1) >> 11) *
+                   0x1.0p-53 * 2.0 - 1.0;
+        double r2 = a * a + b * b;
+        if (r2 > 0.0 && r2 <= 1.0) {
+            *c = (a * a - b * b) / r2;
+            *s = 2.0 * a * b / r2;
+            return;
+        }
+    }
+    *c = 1.0;
+    *s = 0.0;
+}
+
+/* The APR-expanded phase space: particle i gives copies i*k .. i*k+k-1,
+ * each turned about the central axis (x = y = 0) by its own azimuth,
+ * position and direction alike (the direction cosines follow the turn, so
+ * a cylindrically symmetric phase space stays so), with weight wt / k;
+ * type, energy and w are kept.  Arithmetic in double, rounded to float. */
+void oracle_apr_expand(int64_t n, int64_t k, uint64_t seed,
+                       const uint8_t *type, const float *E, const float *x,
+                       const float *y, const float *u, const float *v,
+                       const float *w, const float *wt, uint8_t *otype,
+                       float *oE, float *ox, float *oy, float *ou, float *ov,
+                       float *ow, float *owt)
+{
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < k; ++j) {
+            const int64_t m = i * k + j;
+            double c, s;
+            oracle_apr_rotation(seed, (uint64_t)m, &c, &s);
+            double px = x[i], py = y[i], du = u[i], dv = v[i];
+            otype[m] = type[i];
+            oE[m] = E[i];
+            ox[m] = (float)(c * px - s * py);
+            oy[m] = (float)(s * px + c * py);
+            ou[m] = (float)(c * du - s * dv);
+            ov[m] = (float)(s * du + c * dv);
+            ow[m] = w[i];
+            owt[m] = (float)((double)wt[i] / (double)k);
+        }
+}
+
 /* ------------------------------------------------------------------------ */
 /* ROI selection (Sec. 2.3.3, Fig. 1).                                       */
 /* ------------------------------------------------------------------------ */

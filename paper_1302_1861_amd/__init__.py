@@ -43,7 +43,8 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "unet_adam_step", "dose_denoise",
            "dose_gamma", "psl_sample_noalloc_max_bytes",
            "psl_sample_noalloc", "psl_bench_atomics_replay",
-           "psl_stream_workspace_bytes", "psl_stream_sample"]
+           "psl_stream_workspace_bytes", "psl_stream_sample", "dose_point",
+           "psl_build_apr_workspace_bytes", "psl_build_apr"]
 
 
 class PslError(RuntimeError):
@@ -216,6 +217,12 @@ def lib():
         L.psl_stream_sample.argtypes = [vp, vp, vp, vp, vp, i64, vp, vp, vp,
                                         sz, vp]
         L.psl_stream_sample.restype = i32
+        L.dose_point.argtypes = [vp, vp, vp, d, d, d, d, vp, vp]
+        L.dose_point.restype = i32
+        L.psl_build_apr_workspace_bytes.argtypes = [i64, i64, vp]
+        L.psl_build_apr_workspace_bytes.restype = sz
+        L.psl_build_apr.argtypes = [vp, vp, i64, u64, vp, vp, vp, vp, sz, vp]
+        L.psl_build_apr.restype = i32
         L.psl_physics_init.argtypes = [vp, vp, vp]
         L.psl_physics_init.restype = i32
         L.transport_batch_workspace_bytes.argtypes = [vp]
@@ -378,6 +385,18 @@ def psl_build(in_phsp: Dict, grid: psl_grid, out_phsp: Dict, offsets,
                            ws.numel() * ws.element_size(), _stream(stream)))
 
 
+def psl_build_apr(in_phsp: Dict, grid: psl_grid, copies: int, seed: int,
+                  out_phsp: Dict, offsets, n_dropped, ws, stream=None):
+    """psl_build of `copies` azimuthally redistributed copies of every
+    particle (Sec. 2.3.1); out holds n * copies entries."""
+    i, o = make_phsp(in_phsp), make_phsp(out_phsp)
+    _check(lib().psl_build_apr(C.byref(i), C.byref(grid), int(copies),
+                               C.c_uint64(seed), C.byref(o), _ptr(offsets),
+                               _ptr(n_dropped), _ptr(ws),
+                               ws.numel() * ws.element_size(),
+                               _stream(stream)))
+
+
 def psl_sample(sorted_phsp: Dict, offsets, grid: psl_grid, fields_arr,
                cfg: psl_sample_cfg, queue: psl_queue, stats, ws, mask=None,
                alloc=None, n_sorted=None, stream=None):
@@ -415,6 +434,49 @@ def psl_stream_sample(phsp: Dict, field_arr, cfg: psl_stream_cfg,
                                    _ptr(stats), _ptr(ws),
                                    ws.numel() * ws.element_size(),
                                    _stream(stream)))
+
+
+def dose_point(dose, sigma, phantom: psl_phantom, point, radius,
+               stream=None):
+    """Reference-point dose (Sec. 2.5) of device float tensors dose, sigma:
+    (mean over the voxel centres within radius, its standard error,
+    count)."""
+    import torch
+    out = torch.zeros(3, dtype=torch.float64, device=dose.device)
+    _check(lib().dose_point(_ptr(dose), _ptr(sigma), C.byref(phantom),
+                            float(point[0]), float(point[1]),
+                            float(point[2]), float(radius), _ptr(out),
+                            _stream(stream)))
+    m, se, n = (float(v) for v in out.cpu())
+    return m, se, int(n)
+
+
+def calibration_factor(ref_dose_per_particle, dose_per_mu):
+    """Absolute calibration (Sec. 2.5): particles per MU, the calibration
+    dose (Gy/MU at the reference point under reference conditions) over the
+    computed dose there (Gy per particle).  Dose in Gy for a field of M
+    monitor units is then D x factor x M / (1 + b), b the field's monitor
+    backscatter relative to the reference field."""
+    return dose_per_mu / ref_dose_per_particle
+
+
+def output_factors(ref_doses, reference, backscatter=None):
+    """Relative output factors (Sec. 2.5): the reference-point dose of each
+    field per monitor unit relative to the reference field's, where a
+    field's monitor units per particle grow by (1 + b) with its monitor
+    backscatter b (from a table, the paper's BEAMnrc values; none here
+    unless given).  ref_doses: {field: (dose, standard error)}; returns
+    {field: (ROF, standard error)}."""
+    b = backscatter or {}
+    d0, s0 = ref_doses[reference]
+    k0 = 1.0 + b.get(reference, 0.0)
+    out = {}
+    for f, (d, s) in ref_doses.items():
+        k = 1.0 + b.get(f, 0.0)
+        r = (d / k) / (d0 / k0)
+        rel = math.hypot(s / d, s0 / d0) if f != reference else 0.0
+        out[f] = (r, r * rel)
+    return out
 
 
 def psl_physics_init(phys: psl_physics, tables, stream=None):

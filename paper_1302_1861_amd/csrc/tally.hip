@@ -4,6 +4,8 @@
 // streaming and bound by HBM bandwidth.
 #include "common.hpp"
 
+#include <cmath>
+
 namespace psl {
 namespace {
 
@@ -49,10 +51,119 @@ k_finalize(const double *__restrict__ s1, const double *__restrict__ s2,
     }
 }
 
+// Reference-point dose (Sec. 2.5): one block sums, over the voxels of the
+// sphere's bounding box whose centres lie within the radius, the dose, the
+// squared standard errors and the count, in a fixed order (thread-strided
+// partial sums, then a tree in LDS).
+constexpr int kPointBlock = 256;
+__global__ void __launch_bounds__(kPointBlock)
+k_dose_point(const float *__restrict__ dose, const float *__restrict__ sigma,
+             int nx, int ny, int nz, double x0, double y0, double z0,
+             double dx, double dy, double dz, double px, double py,
+             double pz, double radius, int ilo, int ihi, int jlo, int jhi,
+             int klo, int khi, int fi, int fj, int fk, double *out) {
+#pragma clang fp contract(off)
+    __shared__ double s_d[kPointBlock], s_v[kPointBlock], s_n[kPointBlock];
+    const int64_t wi = ihi - ilo + 1, wj = jhi - jlo + 1, wk = khi - klo + 1;
+    const int64_t m = wi * wj * wk;
+    double sd = 0.0, sv = 0.0, sn = 0.0;
+    const double r2 = radius < 0.0 ? -1.0 : radius * radius;  // < 0: none
+    for (int64_t t = threadIdx.x; t < m; t += kPointBlock) {
+        const int i = ilo + (int)(t % wi);
+        const int j = jlo + (int)((t / wi) % wj);
+        const int k = klo + (int)(t / (wi * wj));
+        const double cx = x0 + ((double)i + 0.5) * dx - px;
+        const double cy = y0 + ((double)j + 0.5) * dy - py;
+        const double cz = z0 + ((double)k + 0.5) * dz - pz;
+        const bool in = cx * cx + cy * cy + cz * cz <= r2;
+        if (in) {
+            const int64_t v = ((int64_t)k * ny + j) * nx + i;
+            const double s = sigma[v];
+            sd += (double)dose[v];
+            sv += s * s;
+            sn += 1.0;
+        }
+    }
+    s_d[threadIdx.x] = sd;
+    s_v[threadIdx.x] = sv;
+    s_n[threadIdx.x] = sn;
+    __syncthreads();
+    for (int h = kPointBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            s_d[threadIdx.x] += s_d[threadIdx.x + h];
+            s_v[threadIdx.x] += s_v[threadIdx.x + h];
+            s_n[threadIdx.x] += s_n[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double d = s_d[0], v = s_v[0], n = s_n[0];
+        if (n == 0.0 && fi >= 0) {
+            // no voxel centre inside the sphere: the voxel holding the point
+            const int64_t c = ((int64_t)fk * ny + fj) * nx + fi;
+            const double s = sigma[c];
+            d = dose[c];
+            v = s * s;
+            n = 1.0;
+        }
+        out[0] = n > 0.0 ? d / n : 0.0;
+        out[1] = n > 0.0 ? sqrt(v) / n : 0.0;
+        out[2] = n;
+    }
+}
+
 }  // namespace
 }  // namespace psl
 
 using namespace psl;
+
+extern "C" psl_status dose_point(const float *d_dose, const float *d_sigma,
+                                 const psl_phantom *ph, double x, double y,
+                                 double z, double radius, double *d_out,
+                                 void *stream) {
+    PSL_REQUIRE(d_dose && d_sigma && ph && d_out, "NULL argument");
+    PSL_REQUIRE(ph->nx > 0 && ph->ny > 0 && ph->nz > 0, "bad phantom");
+    PSL_REQUIRE(ph->dx > 0 && ph->dy > 0 && ph->dz > 0, "bad voxel size");
+    PSL_REQUIRE(radius >= 0 && std::isfinite(radius) && std::isfinite(x) &&
+                    std::isfinite(y) && std::isfinite(z),
+                "bad point or radius");
+    // index range of the voxels whose centres can lie in the sphere
+    auto lo_hi = [](double c, double r, double o, double d, int n, int *lo,
+                    int *hi) {
+        double a = std::ceil((c - r - o) / d - 0.5);
+        double b = std::floor((c + r - o) / d - 0.5);
+        *lo = (int)std::max(0.0, a);
+        *hi = (int)std::min((double)(n - 1), b);
+    };
+    int ilo, ihi, jlo, jhi, klo, khi;
+    lo_hi(x, radius, ph->x0, ph->dx, ph->nx, &ilo, &ihi);
+    lo_hi(y, radius, ph->y0, ph->dy, ph->ny, &jlo, &jhi);
+    lo_hi(z, radius, ph->z0, ph->dz, ph->nz, &klo, &khi);
+    if (ihi < ilo || jhi < jlo || khi < klo) {   // nothing in the box
+        ilo = ihi = jlo = jhi = klo = khi = 0;
+        radius = -1.0;                            // no centre qualifies
+    }
+    PSL_REQUIRE((int64_t)(ihi - ilo + 1) * (jhi - jlo + 1) * (khi - klo + 1) <=
+                    ((int64_t)1 << 26),
+                "radius spans more than 2^26 voxels");
+    // the voxel holding the point, if the point is inside the phantom
+    const double fx = std::floor((x - ph->x0) / ph->dx);
+    const double fy = std::floor((y - ph->y0) / ph->dy);
+    const double fz = std::floor((z - ph->z0) / ph->dz);
+    int fi = -1, fj = -1, fk = -1;
+    if (fx >= 0 && fx < ph->nx && fy >= 0 && fy < ph->ny && fz >= 0 &&
+        fz < ph->nz) {
+        fi = (int)fx; fj = (int)fy; fk = (int)fz;
+    }
+    if (psl_status s = check_device()) return s;
+    hipLaunchKernelGGL(k_dose_point, dim3(1), dim3(kPointBlock), 0,
+                       (hipStream_t)stream, d_dose, d_sigma, ph->nx, ph->ny,
+                       ph->nz, ph->x0, ph->y0, ph->z0, ph->dx, ph->dy, ph->dz,
+                       x, y, z, radius, ilo, ihi, jlo, jhi, klo, khi, fi, fj,
+                       fk, d_out);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
 
 extern "C" psl_status dose_tally(psl_dose_acc *acc, double *d_s1,
                                  double *d_s2, int32_t op, int32_t n_batches,

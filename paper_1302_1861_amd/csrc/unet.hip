@@ -306,9 +306,15 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     constexpr int HVOX = HZ * HY * HX;
     constexpr int G = CC / 8;                  // 16-byte groups per voxel
     constexpr int PITCH = CC + 8;              // LDS voxel pitch (elements)
-    constexpr int SLOTS = 27 * G;
+    // The reduction runs over slots (dz, dx, g): for each, the three taps
+    // dy = 0, 1, 2 of the wave's four consecutive output rows t read halo
+    // rows t + dy, so six A fragments (halo rows 0..5) feed twelve matrix
+    // instructions, tap dy taking weight fragment dy.  Four slots per step,
+    // one per lane quarter.
+    constexpr int SLOTS = 9 * G;
     constexpr int STEPS = (SLOTS + 3) / 4;
     constexpr int ROWS = kBZ * kBY / 4;        // rows (tiles) per wave
+    static_assert(ROWS == 4, "a wave owns four consecutive y rows");
     static_assert(HVOX * PITCH >= 4 * ROWS * 16 * (16 * NB + 8),
                   "the epilogue reuses the halo buffer");
     __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * PITCH];
@@ -323,19 +329,20 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
     const int cb0 = blockIdx.y * NB;
     const int q = lane >> 4, vx = lane & 15;
-    // slot -> (LDS offset of tap o and group g relative to the lane's first
-    // row, weight offset o Cin + 8 g); slots past the last tap point at
-    // tap 0 and are zeroed in the last step
+    // slot -> (LDS offset of (dz, dx, g) at dy = 0 relative to the lane's
+    // first row, weight offset of tap (dz, 0, dx) and group g); slots past
+    // the last point at slot 0 and are zeroed in the last step
     for (int sl = threadIdx.x; sl < STEPS * 4; sl += 256) {
-        const int o = sl < SLOTS ? sl / G : 0, g = sl < SLOTS ? sl % G : 0;
-        const int dz = o / 9, dy = (o / 3) % 3, dx = o % 3;
-        s_tab[sl] = make_int2(((dz * HY + dy) * HX + dx) * PITCH + 8 * g,
-                              o * Cin + 8 * g);
+        const int u = sl < SLOTS ? sl / G : 0, g = sl < SLOTS ? sl % G : 0;
+        const int dz = u / 3, dx = u % 3;
+        s_tab[sl] = make_int2((dz * HY * HX + dx) * PITCH + 8 * g,
+                              (dz * 9 + dx) * Cin + 8 * g);
     }
-    // the lane's A row in the halo: brick row wid ROWS (rz = wid, ry = 0
-    // for 4 x 4 bricks of 4 rows per wave), voxel vx; row t adds t HX PITCH
+    // the lane's A row in the halo: brick row wid ROWS (rz = wid, ry = 0),
+    // voxel vx; halo row r adds r HX PITCH
     const int a_base = ((wid * ROWS / kBY) * HY + (wid * ROWS) % kBY) * HX *
                            PITCH + vx * PITCH;
+    const int dyw = 3 * Cin;                   // weight offset of dy + 1
     const bf16_t *wrow[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c)
@@ -380,35 +387,38 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
                                            (i % G) * 8) = hval[it];
         }
         __syncthreads();
-        // Weights of step j + 1 are loaded while step j computes (two
-        // buffers in turn; the empty asm statements keep each prefetch
-        // ahead of the step that does not use it -- the compiler otherwise
-        // moves the loads next to their use).  Each buffer carries its
-        // step's LDS offset.
-        auto wload = [&](int j, bf16x8 *wv, int &aoff) {
+        // Weights of step j + 1 (three taps dy per channel block) are
+        // loaded while step j computes (two buffers in turn; the empty asm
+        // statements keep each prefetch ahead of the step that does not use
+        // it).  Each buffer carries its step's LDS offset.
+        auto wload = [&](int j, bf16x8 (*wv)[NB], int &aoff) {
             const int2 tb = s_tab[4 * j + q];
             aoff = a_base + tb.x;
 #pragma unroll
-            for (int c = 0; c < NB; ++c)
-                wv[c] = *reinterpret_cast<const bf16x8 *>(wrow[c] + c0 +
-                                                          tb.y);
-        };
-        auto step = [&](const bf16x8 *wv, int aoff, bool ok) {
-            bf16x8 a[ROWS];
-#pragma unroll
-            for (int t = 0; t < ROWS; ++t) {
-                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
-                    s_in + aoff + t * HX * PITCH);
-                a[t] = ok ? v : bf16x8{};
-            }
-#pragma unroll
-            for (int t = 0; t < ROWS; ++t)
+            for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
-                    acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        a[t], wv[c], acc[t][c], 0, 0, 0);
+                    wv[dy][c] = *reinterpret_cast<const bf16x8 *>(
+                        wrow[c] + c0 + tb.y + dy * dyw);
         };
-        bf16x8 wa[NB], wb[NB];
+        auto step = [&](bf16x8 (*wv)[NB], int aoff, bool ok) {
+            bf16x8 a[ROWS + 2];
+#pragma unroll
+            for (int r = 0; r < ROWS + 2; ++r) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
+                    s_in + aoff + r * HX * PITCH);
+                a[r] = ok ? v : bf16x8{};
+            }
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int t = 0; t < ROWS; ++t)
+#pragma unroll
+                    for (int c = 0; c < NB; ++c)
+                        acc[t][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            a[t + dy], wv[dy][c], acc[t][c], 0, 0, 0);
+        };
+        bf16x8 wa[3][NB], wb[3][NB];
         int oa, ob;
         wload(0, wa, oa);
         int j = 0;

@@ -21,7 +21,8 @@ from . import (PART_KEYS, PHSP_KEYS, PSL_ACC_F64, PSL_ACC_FIXED64,
                make_physics, make_phsp, psl_build, psl_dose_acc,
                psl_launch, psl_physics_init, psl_queue, psl_sample,
                psl_sample_cfg, psl_stats, dose_tally, transport_batch,
-               stats_to_dict, psl_stream_cfg, psl_stream_sample)
+               stats_to_dict, psl_stream_cfg, psl_stream_sample,
+               psl_build_apr)
 
 DEFAULT_BUCKET_EDGES = (0.0, 0.3, 0.5, 0.8, 1.2, 1.8, 2.6, 3.8)
 
@@ -68,10 +69,14 @@ class Engine:
                  electron_factor=1.5, frac_bits=32, phys_flags=0,
                  launch: Optional[psl_launch] = None, iso=(0.0, 0.0, 100.0),
                  sad=100.0, z_jaw_x=37.0, z_jaw_y=28.0, seed=None,
-                 source="psl", bin_capacity=1 << 20):
+                 source="psl", bin_capacity=1 << 20, apr_copies=0,
+                 apr_seed=0):
         """source: "psl" (Method 3, the PSL source), or "method1" /
         "method2" (the phase space in file order with on-the-fly bins of
-        bin_capacity particles, psl_stream_sample; one field)."""
+        bin_capacity particles, psl_stream_sample; one field).
+        apr_copies >= 1 builds the PSLs from that many azimuthally
+        redistributed copies of every particle (psl_build_apr, Sec. 2.3.1);
+        the dose stays normalised per original phase-space particle."""
         import torch
         self.torch = torch
         self.device = device
@@ -86,15 +91,23 @@ class Engine:
                               wl.grid.y_edges, wl.grid.z_plane)
         self.n_keys = 2 * self.grid.n_e * self.grid.n_x * self.grid.n_y
         raw = Buffers.phsp_from_numpy(ps, device)
-        self.sorted = Buffers.phsp(ps.n, device)
+        k = int(apr_copies)
+        self.sorted = Buffers.phsp(ps.n * max(k, 1), device)
         self.offsets = torch.zeros(self.n_keys + 1, dtype=torch.int64,
                                    device=device)
         self.n_dropped = torch.zeros(1, dtype=torch.int64, device=device)
         from . import lib as _l
-        ws = _ws(_l().psl_build_workspace_bytes(ps.n, C.byref(self.grid)),
-                 device)
-        psl_build(raw, self.grid, self.sorted, self.offsets, self.n_dropped,
-                  ws)
+        if k >= 1:
+            ws = _ws(_l().psl_build_apr_workspace_bytes(
+                ps.n, k, C.byref(self.grid)), device)
+            psl_build_apr(raw, self.grid, k, apr_seed, self.sorted,
+                          self.offsets, self.n_dropped, ws)
+        else:
+            ws = _ws(_l().psl_build_workspace_bytes(ps.n,
+                                                    C.byref(self.grid)),
+                     device)
+            psl_build(raw, self.grid, self.sorted, self.offsets,
+                      self.n_dropped, ws)
         del ws
         if source not in ("psl", "method1", "method2"):
             raise ValueError("source must be psl, method1 or method2")

@@ -72,13 +72,16 @@ class PhaseSpace:
 def phase_space(n: int, seed: int, half_width: float, z_plane: float,
                 p_electron: float = 0.03, e_min: float = 0.1,
                 e_mode: float = 1.0, e_max: float = 6.0,
-                sigma_src: float = 0.1, z_aim: float = SAD) -> PhaseSpace:
+                sigma_src: float = 0.1, z_aim: float = SAD,
+                aim: str = "square") -> PhaseSpace:
     """Linac-like synthetic phase space.
 
     Particles leave a Gaussian point source (sigma ``sigma_src`` cm in x and
     y) at z = 0, aimed at a point drawn uniformly over the square
-    [-half_width, half_width)^2 at z = ``z_aim``.  Each is recorded where its
-    ray crosses z = ``z_plane``.  A fraction ``p_electron`` are electrons;
+    [-half_width, half_width)^2 at z = ``z_aim`` (aim="square"), or over the
+    disk of radius half_width (aim="disk": a cylindrically symmetric phase
+    space, for azimuthal redistribution).  Each is recorded where its ray
+    crosses z = ``z_plane``.  A fraction ``p_electron`` are electrons;
     energies follow a triangular spectrum (e_min, e_mode, e_max).  Weights
     are 1.
     """
@@ -87,8 +90,13 @@ def phase_space(n: int, seed: int, half_width: float, z_plane: float,
     E = rng.triangular(e_min, e_mode, e_max, n)
     sx = rng.normal(0.0, sigma_src, n)
     sy = rng.normal(0.0, sigma_src, n)
-    ax = rng.uniform(-half_width, half_width, n)
-    ay = rng.uniform(-half_width, half_width, n)
+    if aim == "disk":
+        rad = half_width * np.sqrt(rng.random(n))
+        ang = rng.uniform(0.0, 2.0 * np.pi, n)
+        ax, ay = rad * np.cos(ang), rad * np.sin(ang)
+    else:
+        ax = rng.uniform(-half_width, half_width, n)
+        ay = rng.uniform(-half_width, half_width, n)
     dx, dy, dz = ax - sx, ay - sy, np.full(n, z_aim)
     norm = np.sqrt(dx * dx + dy * dy + dz * dz)
     u, v, w = dx / norm, dy / norm, dz / norm
