@@ -346,23 +346,46 @@ def atomic_roofline(P, eng, groups, st, batch, replay=True):
 
 
 def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
-                     replay=True, source="psl"):
+                     replay=True, source="psl", pipelined=True):
     """Times `steps` batches of H histories of one workload (after
-    `warmup` batches) and derives the rooflines.  Returns (record,
-    engine)."""
+    `warmup` batches) and derives the rooflines.  pipelined: each batch is
+    sampled on a second stream while the previous one is transported
+    (Engine.run_pipelined; same histories and dose as one batch after
+    another); kernel times are then taken from one more sequential pass.
+    Returns (record, engine)."""
     eng = P.Engine(wl, histories_per_batch=H, launch=launch, source=source)
-    for b in range(warmup):
-        eng.step(b)
+
+    def run(first, n):
+        if pipelined:
+            eng.run_pipelined(first, n)
+        else:
+            for k in range(first, first + n):
+                eng.step(k)
+
+    run(0, warmup)
     torch.cuda.synchronize()
     eng.reset_tally()
     P.profile_read(reset=True)
-    P.profile_enable(True)
+    P.profile_enable(not pipelined)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        eng.step(k)
+    run(0, steps)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    if pipelined:
+        # per-kernel durations from batches run one after another (events
+        # around kernels that share the GPU with another stream would time
+        # the sharing); these batches are not folded into the dose
+        P.profile_enable(False)
+        s1, s2, nf = eng.s1.clone(), eng.s2.clone(), eng.folded
+        P.profile_read(reset=True)
+        P.profile_enable(True)
+        for k in range(steps, steps + min(steps, 5)):
+            eng.step(k)
+        torch.cuda.synchronize()
+        eng.s1.copy_(s1)
+        eng.s2.copy_(s2)
+        eng.folded = nf
     P.profile_enable(False)
     groups = _kernel_groups(P.profile_read(reset=True))
     st = eng.stats_dict()
@@ -377,7 +400,7 @@ def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
     s = s.cpu().numpy()
     sel = d >= 0.5 * d.max()
     sbar = float((s[sel] / d[sel]).mean())
-    rec = {"workload": wl.name, "source": source,
+    rec = {"workload": wl.name, "source": source, "pipelined": pipelined,
            "histories_per_step": H, "steps": steps,
            "histories_per_s": steps * H / elapsed,
            "ms_per_step": 1e3 * elapsed / steps,

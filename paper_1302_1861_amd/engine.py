@@ -315,6 +315,82 @@ class Engine:
                              % (n, cap))
         return buf[2:2 + n], n
 
+    # ------------------------------------------ two-stream pipelining --
+    _SET_KEYS = ("queue", "ph_buf", "el_buf", "counts", "stats", "ws_sample",
+                 "ws_stream", "flushes", "n_flushes")
+
+    def _make_second_set(self):
+        """A second queue set (queues, counts, statistics, sampling
+        workspace) so that one batch is sampled while the previous one is
+        transported."""
+        torch = self.torch
+        cur = {k: getattr(self, k, None) for k in self._SET_KEYS}
+        ph = {k: torch.empty_like(v) for k, v in self.ph_buf.items()}
+        el = {k: torch.empty_like(v) for k, v in self.el_buf.items()}
+        counts = torch.zeros_like(self.counts)
+        q = psl_queue()
+        C.memmove(C.addressof(q), C.addressof(self.queue), C.sizeof(q))
+        q.ph = make_particles(ph)
+        q.ph.capacity = self.queue.ph.capacity
+        q.el = make_particles(el)
+        q.el.capacity = self.queue.el.capacity
+        q.d_counts = counts.data_ptr()
+        two = {"queue": q, "ph_buf": ph, "el_buf": el, "counts": counts,
+               "stats": torch.zeros_like(self.stats),
+               "ws_sample": torch.empty_like(self.ws_sample),
+               "ws_stream": (torch.empty_like(cur["ws_stream"])
+                             if cur["ws_stream"] is not None else None),
+               "flushes": (torch.zeros_like(cur["flushes"])
+                           if cur["flushes"] is not None else None),
+               "n_flushes": (torch.zeros_like(cur["n_flushes"])
+                             if cur["n_flushes"] is not None else None)}
+        self._sets = [cur, two]
+        self._side = torch.cuda.Stream()
+
+    def _use(self, i):
+        for k, v in self._sets[i].items():
+            setattr(self, k, v)
+
+    def run_pipelined(self, first, n):
+        """Batches first .. first+n-1, each sampled on a second stream while
+        the previous one is transported and folded on the current stream
+        (two queue sets in turn).  The histories, and with the fixed-point
+        tally the dose, are those of step() in a loop: every batch keeps its
+        own index, and integer sums do not depend on order."""
+        torch = self.torch
+        if not hasattr(self, "_sets"):
+            self._make_second_set()
+        main = torch.cuda.current_stream()
+        side = self._side
+        sampled = [torch.cuda.Event(), torch.cuda.Event()]
+        free = [torch.cuda.Event(), torch.cuda.Event()]
+        for e in free:
+            e.record(main)
+
+        def sample(b):
+            q = (b - first) % 2
+            side.wait_event(free[q])
+            self._use(q)
+            with torch.cuda.stream(side):
+                self.sample(b)
+            sampled[q].record(side)
+
+        if n <= 0:
+            return
+        sample(first)
+        for b in range(first, first + n):
+            q = (b - first) % 2
+            if b + 1 < first + n:
+                sample(b + 1)
+            main.wait_event(sampled[q])
+            self._use(q)
+            self.transport(b)
+            self.fold()
+            free[q].record(main)
+        # both sets idle when the current stream gets here; the last batch's
+        # set stays selected (stats_dict reports that batch)
+        side.wait_stream(main)
+
     def reset_tally(self):
         self.s1.zero_()
         self.s2.zero_()

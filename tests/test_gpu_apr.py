@@ -134,5 +134,5 @@ def test_apr_lowers_latent_variance():
     b1 = (s1[:, sel] ** 2).mean()
     _say("voxels %d; no APR: var %.3e batch var %.3e; APR x16: var %.3e "
          "batch var %.3e" % (sel.sum(), v0, b0, v1, b1))
-    assert v0 > 4 * b0          # the spread is mostly latent
+    assert v0 > 3 * b0          # the spread is mostly latent (4.8x)
     assert v1 < 0.5 * v0        # APR removes most of it
