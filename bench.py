@@ -577,6 +577,9 @@ def main():
     ap.add_argument("--extras-only", action="store_true",
                     help="only the measurements beside the main workload "
                          "(for profiling them apart from it)")
+    ap.add_argument("--denoiser-only", action="store_true",
+                    help="only the denoiser forward timing at 128^3, on a "
+                         "synthetic dose (for profiling the denoiser alone)")
     ap.add_argument("--imrt-batches", type=int, default=100)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="device-to-device copy of this size before the "
@@ -644,6 +647,14 @@ def main():
         out["psl_build"] = bench_build(P, torch, S)
         out["time_to_accuracy"] = bench_time_to_accuracy()
 
+    if args.denoiser_only:
+        shape = (128, 128, 128)
+        g = torch.Generator(device="cuda").manual_seed(5)
+        dose = torch.rand(shape, device="cuda", generator=g) + 0.1
+        rho = torch.rand(shape, device="cuda", generator=g) + 0.5
+        print(json.dumps({"denoiser": bench_denoiser(P, torch, dose, rho,
+                                                     shape)}))
+        return
     wl = S.workload_clinical(side=args.field)
     if args.extras_only:
         eng = P.Engine(wl, histories_per_batch=H, launch=launch)

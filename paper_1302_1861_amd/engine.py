@@ -317,12 +317,14 @@ class Engine:
 
     # ------------------------------------------ two-stream pipelining --
     _SET_KEYS = ("queue", "ph_buf", "el_buf", "counts", "stats", "ws_sample",
-                 "ws_stream", "flushes", "n_flushes")
+                 "ws_stream", "flushes", "n_flushes", "acc_t", "acc",
+                 "ws_transport")
 
     def _make_second_set(self):
-        """A second queue set (queues, counts, statistics, sampling
-        workspace) so that one batch is sampled while the previous one is
-        transported."""
+        """A second set of everything one batch holds from sampling to the
+        fold (queues, counts, statistics, sampling and transport
+        workspaces, the batch accumulator), so that two batches can be in
+        flight at once."""
         torch = self.torch
         cur = {k: getattr(self, k, None) for k in self._SET_KEYS}
         ph = {k: torch.empty_like(v) for k, v in self.ph_buf.items()}
@@ -335,15 +337,23 @@ class Engine:
         q.el = make_particles(el)
         q.el.capacity = self.queue.el.capacity
         q.d_counts = counts.data_ptr()
+        acc_t = torch.zeros_like(self.acc_t)
+        acc = psl_dose_acc()
+        acc.mode, acc.frac_bits = self.acc.mode, self.acc.frac_bits
+        acc.data = acc_t.data_ptr()
+
+        def like(t, zero=False):
+            if t is None:
+                return None
+            return torch.zeros_like(t) if zero else torch.empty_like(t)
         two = {"queue": q, "ph_buf": ph, "el_buf": el, "counts": counts,
                "stats": torch.zeros_like(self.stats),
-               "ws_sample": torch.empty_like(self.ws_sample),
-               "ws_stream": (torch.empty_like(cur["ws_stream"])
-                             if cur["ws_stream"] is not None else None),
-               "flushes": (torch.zeros_like(cur["flushes"])
-                           if cur["flushes"] is not None else None),
-               "n_flushes": (torch.zeros_like(cur["n_flushes"])
-                             if cur["n_flushes"] is not None else None)}
+               "ws_sample": like(self.ws_sample),
+               "ws_stream": like(cur["ws_stream"]),
+               "flushes": like(cur["flushes"], True),
+               "n_flushes": like(cur["n_flushes"], True),
+               "acc_t": acc_t, "acc": acc,
+               "ws_transport": like(self.ws_transport)}
         self._sets = [cur, two]
         self._side = torch.cuda.Stream()
 
@@ -352,49 +362,45 @@ class Engine:
             setattr(self, k, v)
 
     def run_pipelined(self, first, n):
-        """Batches first .. first+n-1, each sampled on a second stream while
-        the previous one is transported and folded on the current stream
-        (two queue sets in turn).  The histories, and with the fixed-point
-        tally the dose, are those of step() in a loop: every batch keeps its
-        own index, and integer sums do not depend on order."""
+        """Batches first .. first+n-1 on two streams in turn, each with its
+        own set of queues, workspaces and accumulator, so that two batches
+        are in flight at once (one batch's sampling or transport tail runs
+        beside the other's transport); the folds into the running sums are
+        chained in batch order.  The histories and, with the fixed-point
+        tally, the dose equal those of step() in a loop: every batch keeps
+        its own index and accumulator, and integer sums do not depend on
+        order."""
         torch = self.torch
+        if n <= 0:
+            return
         if not hasattr(self, "_sets"):
             self._make_second_set()
         main = torch.cuda.current_stream()
-        side = self._side
-        sampled = [torch.cuda.Event(), torch.cuda.Event()]
-        free = [torch.cuda.Event(), torch.cuda.Event()]
-        for e in free:
-            e.record(main)
-
-        def sample(b):
-            q = (b - first) % 2
-            side.wait_event(free[q])
-            self._use(q)
-            with torch.cuda.stream(side):
-                self.sample(b)
-            sampled[q].record(side)
-
-        if n <= 0:
-            return
-        sample(first)
+        streams = [main, self._side]
+        self._side.wait_stream(main)     # inputs and tallies ready
+        folded = torch.cuda.Event()
+        folded.record(main)
+        last = 0
         for b in range(first, first + n):
             q = (b - first) % 2
-            if b + 1 < first + n:
-                sample(b + 1)
-            main.wait_event(sampled[q])
+            st = streams[q]
             self._use(q)
-            self.transport(b)
-            self.fold()
-            free[q].record(main)
-        # both sets idle when the current stream gets here; the last batch's
-        # set stays selected (stats_dict reports that batch)
-        side.wait_stream(main)
+            with torch.cuda.stream(st):
+                self.sample(b)
+                self.transport(b)
+                st.wait_event(folded)
+                self.fold()
+                folded.record(st)
+            last = q
+        main.wait_stream(self._side)
+        self._use(last)                  # stats_dict reports the last batch
 
     def reset_tally(self):
         self.s1.zero_()
         self.s2.zero_()
         self.acc_t.zero_()
+        for st in getattr(self, "_sets", ()):
+            st["acc_t"].zero_()
         self.folded = 0
 
     def run(self, batches=None):
