@@ -319,6 +319,12 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
                   "the epilogue reuses the halo buffer");
     __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * PITCH];
     __shared__ int2 s_tab[STEPS * 4];
+    // 16-channel input, one output block: the chunk's weights are staged
+    // in LDS beside the halo (rows of 27 CC + 8 elements, so the 16 lanes
+    // of a fragment row hit distinct banks), read there at every step
+    constexpr bool WL = CC == 16 && NB == 1;
+    constexpr int WP = 27 * CC + 8;
+    __shared__ __attribute__((aligned(16))) bf16_t s_w[WL ? 16 * WP : 8];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
     int64_t b = blockIdx.x;
@@ -336,13 +342,13 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
         const int u = sl < SLOTS ? sl / G : 0, g = sl < SLOTS ? sl % G : 0;
         const int dz = u / 3, dx = u % 3;
         s_tab[sl] = make_int2((dz * HY * HX + dx) * PITCH + 8 * g,
-                              (dz * 9 + dx) * Cin + 8 * g);
+                              (dz * 9 + dx) * (WL ? CC : Cin) + 8 * g);
     }
     // the lane's A row in the halo: brick row wid ROWS (rz = wid, ry = 0),
     // voxel vx; halo row r adds r HX PITCH
     const int a_base = ((wid * ROWS / kBY) * HY + (wid * ROWS) % kBY) * HX *
                            PITCH + vx * PITCH;
-    const int dyw = 3 * Cin;                   // weight offset of dy + 1
+    const int dyw = 3 * (WL ? CC : Cin);       // weight offset of dy + 1
     const bf16_t *wrow[NB];
 #pragma unroll
     for (int c = 0; c < NB; ++c)
@@ -365,6 +371,20 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
         // halo: voxel (hz, hy, hx) = input (z0+hz-1, y0+hy-1, x0+hx-1); all
         // of a thread's loads are issued before its LDS stores, so their
         // latencies overlap
+        constexpr int NWI = WL ? (16 * 27 * G + 255) / 256 : 1;
+        uint4 wval[NWI];
+        if constexpr (WL) {
+#pragma unroll
+            for (int it = 0; it < NWI; ++it) {
+                const int i = threadIdx.x + 256 * it;
+                const int row = i / (27 * G), o = (i / G) % 27, g = i % G;
+                wval[it] = make_uint4(0, 0, 0, 0);
+                if (i < 16 * 27 * G)
+                    wval[it] = *reinterpret_cast<const uint4 *>(
+                        W + (int64_t)(cb0 * 16 + row) * Kp + o * Cin + c0 +
+                        8 * g);
+            }
+        }
         uint4 hval[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -386,6 +406,16 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
                 *reinterpret_cast<uint4 *>(s_in + (i / G) * PITCH +
                                            (i % G) * 8) = hval[it];
         }
+        if constexpr (WL) {
+#pragma unroll
+            for (int it = 0; it < NWI; ++it) {
+                const int i = threadIdx.x + 256 * it;
+                const int row = i / (27 * G), o = (i / G) % 27, g = i % G;
+                if (i < 16 * 27 * G)
+                    *reinterpret_cast<uint4 *>(s_w + row * WP + o * CC +
+                                               8 * g) = wval[it];
+            }
+        }
         __syncthreads();
         // Weights of step j + 1 (three taps dy per channel block) are
         // loaded while step j computes (two buffers in turn; the empty asm
@@ -398,8 +428,11 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
             for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
                 for (int c = 0; c < NB; ++c)
-                    wv[dy][c] = *reinterpret_cast<const bf16x8 *>(
-                        wrow[c] + c0 + tb.y + dy * dyw);
+                    wv[dy][c] = WL
+                        ? *reinterpret_cast<const bf16x8 *>(
+                              s_w + vx * WP + tb.y + dy * dyw)
+                        : *reinterpret_cast<const bf16x8 *>(
+                              wrow[c] + c0 + tb.y + dy * dyw);
         };
         auto step = [&](bf16x8 (*wv)[NB], int aoff, bool ok) {
             bf16x8 a[ROWS + 2];
