@@ -271,10 +271,23 @@ class Engine:
                    self.cfg, self.queue, self.stats, self.ws_sample,
                    mask=mask, alloc=alloc, n_sorted=self.kept())
 
-    def transport(self, batch):
+    def transport(self, batch, launch=None):
         transport_batch(self.queue, self.phantom, self.phys, self.tables,
                         self.seed, self.acc, self.stats, self.ws_transport,
-                        self.launch)
+                        launch if launch is not None else self.launch)
+
+    def pipeline_launch(self):
+        """The launch shape of each of the two batches in flight: the
+        engine's, with its blocks per CU shared between them (4 -> 2 by
+        default), so that both persistent grids are resident at once
+        instead of the second one waiting for CUs the first one holds.
+        The dose does not depend on the launch shape."""
+        from . import make_launch
+        L = self.launch
+        if L is None:
+            return make_launch(blocks_per_cu=2)
+        return make_launch(blocks_per_cu=max(1, L.blocks_per_cu // 2),
+                           rebucket=L.rebucket, n_cu=L.n_cu, block=L.block)
 
     def fold(self):
         dose_tally(self.acc, self.s1, self.s2, PSL_TALLY_FOLD, 0,
@@ -369,7 +382,7 @@ class Engine:
         chained in batch order.  The histories and, with the fixed-point
         tally, the dose equal those of step() in a loop: every batch keeps
         its own index and accumulator, and integer sums do not depend on
-        order."""
+        order.  Each batch is transported with pipeline_launch()."""
         torch = self.torch
         if n <= 0:
             return
@@ -380,6 +393,7 @@ class Engine:
         self._side.wait_stream(main)     # inputs and tallies ready
         folded = torch.cuda.Event()
         folded.record(main)
+        launch = self.pipeline_launch()
         last = 0
         for b in range(first, first + n):
             q = (b - first) % 2
@@ -387,7 +401,7 @@ class Engine:
             self._use(q)
             with torch.cuda.stream(st):
                 self.sample(b)
-                self.transport(b)
+                self.transport(b, launch)
                 st.wait_event(folded)
                 self.fold()
                 folded.record(st)
