@@ -162,21 +162,22 @@ struct HeadArgs {
 // consecutive channels of one voxel.  The data-gradient mask is applied to
 // those 16 bytes (a value is kept where the mask is > 0).  With yp given
 // (no mask), the brick's 2x2x2 averages go to yp on the half-resolution
-// grid as well, summed in the order and precision of k_pool.
+// grid as well, summed in the order and precision of k_pool.  breg, when
+// given, holds the lane's bias value per channel block (read beforehand).
 template <int ROWS, int NB>
 __device__ __forceinline__ void store_tiles(
     const f32x4 (&acc)[ROWS][NB], bf16_t *s_out, int wid, int lane,
     int64_t bn, int z0, int y0, int x0, Vol V, int cb0,
     const float *__restrict__ bias, int relu, const bf16_t *__restrict__ mask,
     bf16_t *__restrict__ y, int Cout, bf16_t *__restrict__ yp = nullptr,
-    HeadArgs hd = HeadArgs{}) {
+    HeadArgs hd = HeadArgs{}, const float *breg = nullptr) {
     constexpr int OP = 16 * NB + 8;            // LDS pitch per voxel
     const int q = lane >> 4, l16 = lane & 15;
     bf16_t *tile = s_out + wid * ROWS * 16 * OP;
 #pragma unroll
     for (int c = 0; c < NB; ++c) {
         const int ch = c * 16 + l16;
-        const float bv = bias ? bias[cb0 * 16 + ch] : 0.0f;
+        const float bv = breg ? breg[c] : bias ? bias[cb0 * 16 + ch] : 0.0f;
 #pragma unroll
         for (int t = 0; t < ROWS; ++t)
 #pragma unroll
@@ -478,6 +479,195 @@ k_conv3_bk(const bf16_t *__restrict__ x, Vol V, int Cin,
     __syncthreads();                           // the halo is free
     store_tiles<ROWS, NB>(acc, s_in, wid, lane, bn, z0, y0, x0, V, cb0, bias,
                           relu, mask, y, Cout, yp, hd);
+}
+
+// k_conv3_bk for 16 input channels per chunk and one block of 16 output
+// channels per block (blockIdx.y; the finest level), as a loop over bricks: each block walks its share of the
+// bricks (grid = the blocks resident at once) and loads the halo of its next
+// (brick, chunk) into registers while the current one computes, so the
+// latency of those loads hides behind the matrix instructions instead of
+// behind other blocks.  With more bricks than blocks, the blocks of one XCD
+// (blockIdx % 8) take one contiguous eighth of the bricks, so that the
+// halos of neighbouring bricks meet in the same L2.  The weights of a chunk
+// are staged in LDS beside the halo (once when Cin = 16, the case it is
+// launched for).  Same arguments, requirements and sums as
+// k_conv3_bk<16, 1>.
+__global__ void __launch_bounds__(256)
+k_conv3_bk16p(const bf16_t *__restrict__ x, Vol V, int Cin,
+              const bf16_t *W, int Kp,
+              const float *__restrict__ bias, int relu,
+              const bf16_t *__restrict__ mask, bf16_t *__restrict__ y,
+              int Cout, const bf16_t *__restrict__ xc, int cc,
+              bf16_t *__restrict__ yp, HeadArgs hd) {
+    constexpr int CC = 16, G = 2, PITCH = CC + 8;
+    constexpr int HZ = kBZ + 2, HY = kBY + 2, HX = 18;
+    constexpr int HVOX = HZ * HY * HX;
+    constexpr int SLOTS = 9 * G, STEPS = (SLOTS + 3) / 4;
+    constexpr int ROWS = kBZ * kBY / 4;
+    constexpr int WP = 27 * CC + 8;            // LDS weight row (elements)
+    static_assert(ROWS == 4, "a wave owns four consecutive y rows");
+    static_assert(HVOX * PITCH >= 4 * ROWS * 16 * 24,
+                  "the epilogue reuses the halo buffer");
+    __shared__ __attribute__((aligned(16))) bf16_t s_in[HVOX * PITCH];
+    __shared__ __attribute__((aligned(16))) bf16_t s_w[16 * WP];
+    __shared__ int2 s_tab[STEPS * 4];
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
+    const int nbr = nxb * nyb * nzb * V.n;     // < 2^31 (grid limit)
+    int br = blockIdx.x, br_end = nbr, br_step = gridDim.x;
+    if (nbr > (int)gridDim.x && gridDim.x >= 8) {
+        const int k = blockIdx.x & 7, per = (nbr + 7) / 8;
+        br = k * per + (blockIdx.x >> 3);
+        br_end = min(nbr, (k + 1) * per);
+        br_step = ((int)gridDim.x - k + 7) / 8;
+    }
+    if (br >= br_end) return;
+    const int q = lane >> 4, vx = lane & 15;
+    for (int sl = threadIdx.x; sl < STEPS * 4; sl += 256) {
+        const int u = sl < SLOTS ? sl / G : 0, g = sl < SLOTS ? sl % G : 0;
+        const int dz = u / 3, dx = u % 3;
+        s_tab[sl] = make_int2((dz * HY * HX + dx) * PITCH + 8 * g,
+                              (dz * 9 + dx) * CC + 8 * g);
+    }
+    const int a_base = ((wid * ROWS / kBY) * HY + (wid * ROWS) % kBY) * HX *
+                           PITCH + vx * PITCH;
+    const int cb0 = blockIdx.y;                // output channel block
+    const float bv = bias ? bias[cb0 * 16 + vx] : 0.0f;
+    constexpr int NIT = (HVOX * G + 255) / 256;
+    constexpr int NWI = (16 * 27 * G + 255) / 256;
+    uint4 hval[NIT];
+    auto fetch = [&](int bb, int c0) {
+        const int bx = bb % nxb; bb /= nxb;
+        const int by = bb % nyb; bb /= nyb;
+        const int bz = bb % nzb;
+        const int64_t bn = bb / nzb;
+        const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
+        const bool up = xc && c0 < cc;
+        const bf16_t *src = up ? xc : x;
+        const int sC = xc ? (up ? cc : Cin - cc) : Cin;
+        const int sc0 = (xc && !up) ? c0 - cc : c0;
+        const int sh = up ? 1 : 0;
+        const int sd = V.d >> sh, shh = V.h >> sh, sw = V.w >> sh;
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            const int g = i % G, hv = i / G;
+            const int hx = hv % HX, hy = (hv / HX) % HY, hz = hv / (HX * HY);
+            const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+            hval[it] = make_uint4(0, 0, 0, 0);
+            if (i < HVOX * G && (unsigned)zz < (unsigned)V.d &&
+                (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w)
+                hval[it] = *reinterpret_cast<const uint4 *>(
+                    src + (((bn * sd + (zz >> sh)) * shh + (yy >> sh)) * sw +
+                           (xx >> sh)) * sC + sc0 + g * 8);
+        }
+    };
+    f32x4 acc[ROWS];
+    int c0 = 0, wc0 = -1;
+    fetch(br, 0);
+    for (;;) {
+        if (c0 != wc0) {
+            // the chunk's weights: through registers into LDS after the
+            // barrier below
+            uint4 wval[NWI];
+#pragma unroll
+            for (int it = 0; it < NWI; ++it) {
+                const int i = threadIdx.x + 256 * it;
+                const int row = i / (27 * G), o = (i / G) % 27, g = i % G;
+                wval[it] = make_uint4(0, 0, 0, 0);
+                if (i < 16 * 27 * G)
+                    wval[it] = *reinterpret_cast<const uint4 *>(
+                        W + (int64_t)(cb0 * 16 + row) * Kp + o * Cin + c0 +
+                        8 * g);
+            }
+            __syncthreads();   // the last unit's reads of s_in / s_w
+#pragma unroll
+            for (int it = 0; it < NWI; ++it) {
+                const int i = threadIdx.x + 256 * it;
+                const int row = i / (27 * G), o = (i / G) % 27, g = i % G;
+                if (i < 16 * 27 * G)
+                    *reinterpret_cast<uint4 *>(s_w + row * WP + o * CC +
+                                               8 * g) = wval[it];
+            }
+            wc0 = c0;
+        } else {
+            __syncthreads();   // the last unit's reads of s_in
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            if (i < HVOX * G)
+                *reinterpret_cast<uint4 *>(s_in + (i / G) * PITCH +
+                                           (i % G) * 8) = hval[it];
+        }
+        __syncthreads();
+        int nb2 = br, nc0 = c0 + CC;
+        if (nc0 >= Cin) { nc0 = 0; nb2 = br + br_step; }
+        const bool more = nb2 < br_end;
+        if (more) fetch(nb2, nc0);             // in flight during the steps
+        if (c0 == 0) {
+#pragma unroll
+            for (int t = 0; t < ROWS; ++t) acc[t] = f32x4{0, 0, 0, 0};
+        }
+        auto wload = [&](int j, bf16x8 (&wv)[3], int &aoff) {
+            const int2 tb = s_tab[4 * j + q];
+            aoff = a_base + tb.x;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+                wv[dy] = *reinterpret_cast<const bf16x8 *>(
+                    s_w + vx * WP + tb.y + dy * 3 * CC);
+        };
+        auto step = [&](const bf16x8 (&wv)[3], int aoff, bool ok) {
+            bf16x8 a[ROWS + 2];
+#pragma unroll
+            for (int r = 0; r < ROWS + 2; ++r) {
+                const bf16x8 v = *reinterpret_cast<const bf16x8 *>(
+                    s_in + aoff + r * HX * PITCH);
+                a[r] = ok ? v : bf16x8{};
+            }
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int t = 0; t < ROWS; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        a[t + dy], wv[dy], acc[t], 0, 0, 0);
+        };
+        bf16x8 wa[3], wb[3];
+        int oa, ob;
+        wload(0, wa, oa);
+        int j = 0;
+#pragma unroll 1
+        for (; j + 2 < STEPS; j += 2) {
+            wload(j + 1, wb, ob);
+            step(wa, oa, true);
+            wload(j + 2, wa, oa);
+            step(wb, ob, true);
+        }
+        const bool ok_last = (SLOTS % 4 == 0) || 4 * (STEPS - 1) + q < SLOTS;
+        if (j + 1 < STEPS) {
+            wload(j + 1, wb, ob);
+            step(wa, oa, true);
+            step(wb, ob, ok_last);
+        } else {
+            step(wa, oa, ok_last);
+        }
+        if (nc0 == 0) {
+            __syncthreads();                   // the halo is free
+            int bb = br;
+            const int x0 = (bb % nxb) * 16; bb /= nxb;
+            const int y0 = (bb % nyb) * kBY; bb /= nyb;
+            const int z0 = (bb % nzb) * kBZ;
+            const int64_t bn = bb / nzb;
+            f32x4 out[ROWS][1];
+#pragma unroll
+            for (int t = 0; t < ROWS; ++t) out[t][0] = acc[t];
+            store_tiles<ROWS, 1>(out, s_in, wid, lane, bn, z0, y0, x0, V,
+                                 cb0, bias, relu, mask, y, Cout, yp, hd, &bv);
+        }
+        if (!more) break;
+        br = nb2;
+        c0 = nc0;
+    }
 }
 
 // The first layer: of the 16 padded input channels only the first two
@@ -1473,9 +1663,26 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
         if (cin % 32 == 0) {
             if (nbk == 2) PSL_CONV_BK(32, 2);
             else PSL_CONV_BK(32, 1);
+        } else if (nbk == 2) {
+            PSL_CONV_BK(16, 2);
+        } else if (cin != 16) {
+            // several chunks: their weights would be staged once per brick
+            // and chunk, in series with the steps
+            PSL_CONV_BK(16, 1);
         } else {
-            if (nbk == 2) PSL_CONV_BK(16, 2);
-            else PSL_CONV_BK(16, 1);
+            // as many blocks as are resident at once, each walking bricks
+            static const int per_cu = [] {
+                int n = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &n, k_conv3_bk16p, 256, 0) != hipSuccess || n < 1)
+                    n = 1;
+                return n;
+            }();
+            const int64_t cap = (int64_t)per_cu * device_cu_count();
+            const dim3 g2((unsigned)std::min<int64_t>(bricks, cap), grid.y);
+            hipLaunchKernelGGL(k_conv3_bk16p, g2, dim3(256), 0, st, x, V, cin,
+                               W, kp, bias, relu, mask, y, cout, xc, cc, yp,
+                               hd);
         }
 #undef PSL_CONV_BK
         PSL_LAUNCHED();
