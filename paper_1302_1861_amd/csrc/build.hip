@@ -248,6 +248,121 @@ k_radix_scatter(const uint32_t *__restrict__ keys_in, M mv, int64_t n,
     }
 }
 
+// The same stable pass for the particle columns, with the tile put in
+// order in LDS first: the ranking of k_radix_scatter, started from the
+// tile's own digit offsets, gives every item its place in the tile sorted
+// by digit; the keys and then each column go through LDS into that order
+// and leave it by consecutive threads, so equal digits are written as
+// contiguous runs (on average kTile / 256 items) instead of one item per
+// round.  tile_off is the exclusive scan over (digit, tile) of the tile
+// histograms: a tile's count of digit d is the next entry minus its own.
+__global__ void __launch_bounds__(kRadixBlock)
+k_radix_scatter_lds(const uint32_t *__restrict__ keys_in, Cols7 in,
+                    Cols7 out, int64_t n, int shift,
+                    const uint32_t *__restrict__ tile_off, int64_t n_tiles,
+                    uint32_t *__restrict__ keys_out, uint32_t skip_key) {
+    constexpr int NW = kRadixBlock / 64, R = kRadixItems;
+    __shared__ uint32_t s_buf[kTile];      // keys, then one column at a time
+    __shared__ uint32_t s_base[256];       // running local base per digit
+    __shared__ uint32_t s_glob[256];       // global offset - local start
+    __shared__ uint32_t s_w[NW][256];
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int m = (int)std::min<int64_t>(kTile, n - base);   // items here
+    {
+        const int64_t e = (int64_t)tid * n_tiles + blockIdx.x;
+        const uint32_t g0 = tile_off[e];
+        const uint32_t g1 =
+            e + 1 < 256 * n_tiles ? tile_off[e + 1] : (uint32_t)n;
+        // exclusive scan of the tile's digit counts: per wave, then waves
+        uint32_t c = g1 - g0, incl = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        if (lane == 63) s_w[0][wid] = incl;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wid; ++w) before += s_w[0][w];
+        const uint32_t lstart = before + incl - c;
+        s_base[tid] = lstart;
+        s_glob[tid] = g0 - lstart;
+        __syncthreads();
+    }
+    uint32_t lp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (r) __syncthreads();            // the last round's reads of s_w
+#pragma unroll
+        for (int w = 0; w < NW; ++w) s_w[w][tid] = 0;
+        __syncthreads();
+        const int li = r * kRadixBlock + tid;
+        const bool valid = li < m;
+        const uint32_t key = valid ? keys_in[base + li] : 0u;
+        const uint32_t d = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bb : ~bb;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        if (valid && rank == 0) s_w[wid][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        {
+            uint32_t run = s_base[tid];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                const uint32_t c = s_w[w][tid];
+                s_w[w][tid] = run;
+                run += c;
+            }
+            s_base[tid] = run;
+        }
+        __syncthreads();
+        lp[r] = valid ? s_w[wid][d] + rank : 0u;
+        if (valid) s_buf[lp[r]] = key;
+    }
+    __syncthreads();
+    // the keys in tile order: destinations, and which items carry payload
+    uint32_t dst[R];
+    uint32_t keep = 0;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int p = j * kRadixBlock + tid;
+        dst[j] = 0;
+        if (p < m) {
+            const uint32_t key = s_buf[p];
+            dst[j] = s_glob[(key >> shift) & 255u] + (uint32_t)p;
+            if (dst[j] < (uint64_t)n) {        // always, for consistent offsets
+                keys_out[dst[j]] = key;
+                if (key != skip_key) keep |= 1u << j;
+            }
+        }
+    }
+#pragma unroll 1
+    for (int k = 0; k < 7; ++k) {
+        const float *src = in.c[k];
+        float v[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = r * kRadixBlock + tid;
+            v[r] = li < m ? src[base + li] : 0.0f;
+        }
+        __syncthreads();                   // the last reads of s_buf
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r * kRadixBlock + tid < m) s_buf[lp[r]] = __float_as_uint(v[r]);
+        __syncthreads();
+        float *o = out.c[k];
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+            if ((keep >> j) & 1u)
+                o[dst[j]] = __uint_as_float(s_buf[j * kRadixBlock + tid]);
+    }
+}
+
 // Sorted keys -> PSL offsets (offsets[k] = items with key < k, for k = 0
 // .. n_keys; the sentinel n_keys marks dropped particles and sorts last),
 // the type column from the key, and the dropped count.
@@ -448,10 +563,10 @@ psl_status build_impl(const psl_phsp *in, const psl_grid *g, bool apr_on,
                                    0, st, ki, MoveApr{apr, po}, n, 8 * p,
                                    w.tile, n_tiles, ko, skip);
             else
-                hipLaunchKernelGGL(k_radix_scatter<MovePay>,
+                hipLaunchKernelGGL(k_radix_scatter_lds,
                                    dim3((unsigned)n_tiles), dim3(kRadixBlock),
-                                   0, st, ki, MovePay{pi, po}, n, 8 * p,
-                                   w.tile, n_tiles, ko, skip);
+                                   0, st, ki, pi, po, n, 8 * p, w.tile,
+                                   n_tiles, ko, skip);
             std::swap(ki, ko);
             pi = po;
         }
