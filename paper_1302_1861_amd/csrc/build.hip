@@ -21,7 +21,7 @@ namespace psl {
 namespace {
 
 constexpr int kRadixBlock = 256;
-constexpr int kRadixItems = 16;
+constexpr int kRadixItems = 32;
 constexpr int kTile = kRadixBlock * kRadixItems;
 
 // Largest k with v >= e[k], top edge closed; -1 outside [e[0], e[n]] or NaN.
@@ -73,9 +73,10 @@ k_tile_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
     tile_hist[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = s[threadIdx.x];
 }
 
-// What a scatter pass moves besides the key: an index (the stable
-// partition of the Method 1/2 source) or the seven float columns of a
-// particle (psl_build).
+// What a k_radix_scatter pass moves besides the key: an index (the stable
+// partition of the Method 1/2 source) or the seven float columns of the
+// azimuthally turned copies (the first pass of an APR build; the other
+// psl_build passes use k_radix_scatter_lds).
 struct MoveIdx {
     const uint32_t *in;
     uint32_t *out;
@@ -85,20 +86,6 @@ struct MoveIdx {
 };
 
 struct Cols7 { float *c[7]; };
-struct MovePay {
-    Cols7 in, out;
-    struct V { float c[7]; };
-    __device__ V load(int64_t i) const {
-        V v;
-#pragma unroll
-        for (int k = 0; k < 7; ++k) v.c[k] = in.c[k][i];
-        return v;
-    }
-    __device__ void store(int64_t d, const V &v) const {
-#pragma unroll
-        for (int k = 0; k < 7; ++k) out.c[k][d] = v.c[k];
-    }
-};
 
 // Azimuthal particle redistribution (Sec. 2.3.1): the turn of copy m, a
 // point uniform in the unit disk by rejection from the counter-based
