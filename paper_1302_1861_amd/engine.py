@@ -276,17 +276,15 @@ class Engine:
                         self.seed, self.acc, self.stats, self.ws_transport,
                         launch if launch is not None else self.launch)
 
-    def pipeline_launch(self):
-        """The launch shape of each of the two batches in flight: the
-        engine's, with its blocks per CU shared between them (4 -> 2 by
-        default), so that both persistent grids are resident at once
-        instead of the second one waiting for CUs the first one holds.
-        The dose does not depend on the launch shape."""
+    def pipeline_launch(self, depth=2):
+        """The launch shape of each of the `depth` batches in flight: the
+        engine's, with its blocks per CU shared between them (4 -> 2 for
+        two by default), so that all the persistent grids are resident at
+        once instead of one waiting for CUs another holds.  The dose does
+        not depend on the launch shape."""
         from . import make_launch
-        L = self.launch
-        if L is None:
-            return make_launch(blocks_per_cu=2)
-        return make_launch(blocks_per_cu=max(1, L.blocks_per_cu // 2),
+        L = self.launch if self.launch is not None else make_launch()
+        return make_launch(blocks_per_cu=max(1, L.blocks_per_cu // depth),
                            rebucket=L.rebucket, n_cu=L.n_cu, block=L.block)
 
     def fold(self):
@@ -333,13 +331,22 @@ class Engine:
                  "ws_stream", "flushes", "n_flushes", "acc_t", "acc",
                  "ws_transport")
 
-    def _make_second_set(self):
-        """A second set of everything one batch holds from sampling to the
-        fold (queues, counts, statistics, sampling and transport
-        workspaces, the batch accumulator), so that two batches can be in
-        flight at once."""
+    def _make_sets(self, depth):
+        """Up to `depth` sets of everything one batch holds from sampling
+        to the fold (queues, counts, statistics, sampling and transport
+        workspaces, the batch accumulator), each with its own stream, so
+        that `depth` batches can be in flight at once."""
         torch = self.torch
-        cur = {k: getattr(self, k, None) for k in self._SET_KEYS}
+        if not hasattr(self, "_sets"):
+            self._sets = [{k: getattr(self, k, None)
+                           for k in self._SET_KEYS}]
+            self._streams = [None]       # set 0: the caller's stream
+        while len(self._sets) < depth:
+            self._sets.append(self._new_set(self._sets[0]))
+            self._streams.append(torch.cuda.Stream())
+
+    def _new_set(self, cur):
+        torch = self.torch
         ph = {k: torch.empty_like(v) for k, v in self.ph_buf.items()}
         el = {k: torch.empty_like(v) for k, v in self.el_buf.items()}
         counts = torch.zeros_like(self.counts)
@@ -367,36 +374,38 @@ class Engine:
                "n_flushes": like(cur["n_flushes"], True),
                "acc_t": acc_t, "acc": acc,
                "ws_transport": like(self.ws_transport)}
-        self._sets = [cur, two]
-        self._side = torch.cuda.Stream()
+        return two
 
     def _use(self, i):
         for k, v in self._sets[i].items():
             setattr(self, k, v)
 
-    def run_pipelined(self, first, n):
-        """Batches first .. first+n-1 on two streams in turn, each with its
-        own set of queues, workspaces and accumulator, so that two batches
-        are in flight at once (one batch's sampling or transport tail runs
-        beside the other's transport); the folds into the running sums are
-        chained in batch order.  The histories and, with the fixed-point
-        tally, the dose equal those of step() in a loop: every batch keeps
-        its own index and accumulator, and integer sums do not depend on
-        order.  Each batch is transported with pipeline_launch()."""
+    def run_pipelined(self, first, n, depth=2):
+        """Batches first .. first+n-1 on `depth` streams in turn, each with
+        its own set of queues, workspaces and accumulator, so that `depth`
+        batches are in flight at once (one batch's sampling or transport
+        tail runs beside the others' transport); the folds into the running
+        sums are chained in batch order.  The histories and, with the
+        fixed-point tally, the dose equal those of step() in a loop: every
+        batch keeps its own index and accumulator, and integer sums do not
+        depend on order.  Each batch is transported with
+        pipeline_launch(depth)."""
         torch = self.torch
         if n <= 0:
             return
-        if not hasattr(self, "_sets"):
-            self._make_second_set()
+        if depth < 1:
+            raise ValueError("depth must be >= 1")
+        self._make_sets(depth)
         main = torch.cuda.current_stream()
-        streams = [main, self._side]
-        self._side.wait_stream(main)     # inputs and tallies ready
+        streams = [main] + self._streams[1:depth]
+        for st in streams[1:]:
+            st.wait_stream(main)         # inputs and tallies ready
         folded = torch.cuda.Event()
         folded.record(main)
-        launch = self.pipeline_launch()
+        launch = self.pipeline_launch(depth)
         last = 0
         for b in range(first, first + n):
-            q = (b - first) % 2
+            q = (b - first) % depth
             st = streams[q]
             self._use(q)
             with torch.cuda.stream(st):
@@ -406,7 +415,8 @@ class Engine:
                 self.fold()
                 folded.record(st)
             last = q
-        main.wait_stream(self._side)
+        for st in streams[1:]:
+            main.wait_stream(st)
         self._use(last)                  # stats_dict reports the last batch
 
     def reset_tally(self):
