@@ -577,6 +577,9 @@ def main():
     ap.add_argument("--extras-only", action="store_true",
                     help="only the measurements beside the main workload "
                          "(for profiling them apart from it)")
+    ap.add_argument("--build-only", action="store_true",
+                    help="time psl_build alone (1e7, 1e8, 5e8 particles) "
+                         "and print its JSON record")
     ap.add_argument("--denoiser-only", action="store_true",
                     help="only the denoiser forward timing at 128^3, on a "
                          "synthetic dose (for profiling the denoiser alone)")
@@ -654,6 +657,9 @@ def main():
         rho = torch.rand(shape, device="cuda", generator=g) + 0.5
         print(json.dumps({"denoiser": bench_denoiser(P, torch, dose, rho,
                                                      shape)}))
+        return
+    if args.build_only:
+        print(json.dumps({"psl_build": bench_build(P, torch, S)}))
         return
     wl = S.workload_clinical(side=args.field)
     if args.extras_only:

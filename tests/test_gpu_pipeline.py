@@ -1,7 +1,7 @@
 """Sampling of batch b+1 on a second stream while batch b is transported
-(two queue sets in turn) gives exactly the dose of the batches run one
-after another: the histories are keyed by batch and history, and the
-fixed-point tally sums integers."""
+(two queue sets in turn, or more) gives exactly the dose of the batches
+run one after another: the histories are keyed by batch and history, and
+the fixed-point tally sums integers."""
 import numpy as np
 import pytest
 
@@ -10,8 +10,9 @@ import psl_synth as S
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("source", ["psl", "method2"])
-def test_pipelined_batches_equal_sequential(source):
+@pytest.mark.parametrize("source,depth", [("psl", 2), ("method2", 2),
+                                          ("psl", 3)])
+def test_pipelined_batches_equal_sequential(source, depth):
     import torch
     import paper_1302_1861_amd as P
     wl = S.workload_clinical(side=10.0, n_particles=1_000_000)
@@ -20,7 +21,7 @@ def test_pipelined_batches_equal_sequential(source):
     b = P.Engine(wl, histories_per_batch=700_001, source=source)
     for k in range(5):
         a.step(k)
-    b.run_pipelined(0, 5)
+    b.run_pipelined(0, 5, depth)
     torch.cuda.synchronize()
     assert a.folded == b.folded == 5
     assert np.array_equal(a.s1.cpu().numpy(), b.s1.cpu().numpy())
@@ -37,7 +38,7 @@ def test_pipelined_batches_equal_sequential(source):
     # and again, continuing from batch 5 with the sets already made
     for k in range(5, 8):
         a.step(k)
-    b.run_pipelined(5, 3)
+    b.run_pipelined(5, 3, depth)
     torch.cuda.synchronize()
     assert np.array_equal(a.s1.cpu().numpy(), b.s1.cpu().numpy())
     assert a.s1.abs().sum().item() > 0
