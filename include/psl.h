@@ -652,6 +652,13 @@ psl_status unet_backward(const psl_unet *u, const float *d_dose,
 psl_status unet_adam_step(psl_unet *u, float *d_grads, float *d_m, float *d_v,
                           float lr, float beta1, float beta2, float eps,
                           int32_t step, void *stream);
+/* Caps the grid of the finest-level convolution (16 -> 16 channels), which
+ * runs as a loop over 16x4x4-voxel bricks: at most max_blocks blocks, each
+ * walking its share of the bricks, instead of as many as are resident at
+ * once (max_blocks = 0, the default).  Process-wide; the results do not
+ * depend on it (tests use it to put many bricks on each block at small
+ * volumes).  PSL_EINVAL for max_blocks < 0. */
+psl_status unet_set_brick_blocks(int32_t max_blocks);
 /* dose_denoise - one volume through the trained network (unet_forward with
  * n = 1); plain Monte Carlo stays the reference the result is judged by. */
 psl_status dose_denoise(const float *d_dose, const float *d_density,

@@ -40,7 +40,7 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_plan_run", "psl_autotune", "psl_plan_get", "psl_plan_destroy",
            "unet_param_count", "unet_workspace_bytes", "unet_init",
            "unet_set_params", "unet_forward", "unet_backward",
-           "unet_adam_step", "dose_denoise",
+           "unet_adam_step", "unet_set_brick_blocks", "dose_denoise",
            "dose_gamma", "psl_sample_noalloc_max_bytes",
            "psl_sample_noalloc", "psl_bench_atomics_replay",
            "psl_stream_workspace_bytes", "psl_stream_sample", "dose_point",
@@ -261,6 +261,8 @@ def lib():
         L.unet_init.restype = i32
         L.unet_set_params.argtypes = [vp, vp]
         L.unet_set_params.restype = i32
+        L.unet_set_brick_blocks.argtypes = [i32]
+        L.unet_set_brick_blocks.restype = i32
         L.unet_forward.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp, vp, sz,
                                    vp]
         L.unet_forward.restype = i32
@@ -562,6 +564,12 @@ def dose_gamma(ref, ev, voxel, dose_crit=0.02, dta=0.2, threshold=0.1,
                             _ptr(counts), _stream()))
     n_eval, n_pass = (int(v) for v in counts.cpu())
     return (n_pass / n_eval if n_eval else 1.0), n_eval
+
+
+def unet_set_brick_blocks(max_blocks=0):
+    """Caps the grid of the finest-level brick-loop convolution (0: as many
+    blocks as are resident); the results do not depend on it."""
+    _check(lib().unet_set_brick_blocks(int(max_blocks)))
 
 
 class Denoiser:

@@ -19,6 +19,7 @@
 
 #include <hip/hip_bf16.h>
 
+#include <atomic>
 #include <cmath>
 #include <vector>
 
@@ -1624,6 +1625,9 @@ void launch_conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
 constexpr int64_t kConvWaves = 2048;
 
 // xc, cc: see k_conv3_bk (brick volumes only; brick_ok tells)
+// unet_set_brick_blocks: 0 = as many blocks as are resident at once
+std::atomic<int> g_brick_blocks{0};
+
 bool brick_ok(Vol V, int cin) {
     return cin % 16 == 0 && V.w % 16 == 0 && V.h % kBY == 0 &&
            V.d % kBZ == 0;
@@ -1678,7 +1682,9 @@ psl_status conv(const bf16_t *x, Vol V, int cin, const bf16_t *W, int kp,
                     n = 1;
                 return n;
             }();
-            const int64_t cap = (int64_t)per_cu * device_cu_count();
+            int64_t cap = (int64_t)per_cu * device_cu_count();
+            const int lim = g_brick_blocks.load(std::memory_order_relaxed);
+            if (lim > 0) cap = std::min<int64_t>(cap, lim);
             const dim3 g2((unsigned)std::min<int64_t>(bricks, cap), grid.y);
             hipLaunchKernelGGL(k_conv3_bk16p, g2, dim3(256), 0, st, x, V, cin,
                                W, kp, bias, relu, mask, y, cout, xc, cc, yp,
@@ -1993,6 +1999,12 @@ extern "C" psl_status unet_init(psl_unet *u, uint64_t seed, void *stream) {
     hipLaunchKernelGGL(k_to_bf16, dim3(nblk(net.n_params)), dim3(256), 0, st,
                        u->params, net.n_params, u->params_bf16);
     PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+extern "C" psl_status unet_set_brick_blocks(int32_t max_blocks) {
+    PSL_REQUIRE(max_blocks >= 0, "max_blocks = %d < 0", max_blocks);
+    g_brick_blocks.store(max_blocks, std::memory_order_relaxed);
     return PSL_OK;
 }
 

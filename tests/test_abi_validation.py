@@ -145,3 +145,11 @@ def test_unet_sizes_and_shape_checks():
     net.n_params = n - 1
     assert L.unet_forward(C.byref(net), DUMMY, DUMMY, 1, 16, 16, 16, DUMMY,
                           DUMMY, 1 << 30, None) == P.PSL_EINVAL
+
+
+def test_brick_blocks_cap_rejects_negative_and_restores_default():
+    P = _P()
+    assert P.lib().unet_set_brick_blocks(-1) == P.PSL_EINVAL
+    assert "max_blocks" in _err(P)
+    assert P.lib().unet_set_brick_blocks(5) == 0
+    assert P.lib().unet_set_brick_blocks(0) == 0

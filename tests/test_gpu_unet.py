@@ -55,13 +55,32 @@ def _setup(n=2, size=16, seed=5, shape=None):
 # per wave, several 32-channel stages).
 # The last case is not a cube: bricks whose counts differ per axis at the
 # finest level, direct gathers below.
-@pytest.mark.parametrize("size,n,shape", [(16, 2, None), (32, 2, None),
-                                          (64, 1, None), (0, 1, (24, 40, 48))])
-def test_forward_matches_reference(size, n, shape):
+# The finest level's 16 -> 16 convolutions run as a loop over bricks, each
+# block walking its share with the next halo prefetched: blocks=None keeps
+# the default grid (more bricks than resident blocks only at 64^3); a small
+# cap puts several bricks on each block at 16^3 (13 blocks: eight XCD
+# ranges of unequal length; 3: fewer blocks than XCDs, plain striding).
+BLOCKS = [None, None, None, None, 13, 3]
+CASES = [(16, 2, None), (32, 2, None), (64, 1, None), (0, 1, (24, 40, 48)),
+         (16, 2, None), (16, 2, None)]
+
+
+def _capped(blocks):
+    import paper_1302_1861_amd as P
+    P.unet_set_brick_blocks(blocks or 0)
+
+
+@pytest.mark.parametrize("size,n,shape,blocks",
+                         [c + (b,) for c, b in zip(CASES, BLOCKS)])
+def test_forward_matches_reference(size, n, shape, blocks):
     import torch
     net, ref, dose, rho, tgt, T = _setup(n=n, size=size, shape=shape)
-    out = net.forward(T(dose), T(rho))
-    torch.cuda.synchronize()
+    _capped(blocks)
+    try:
+        out = net.forward(T(dose), T(rho))
+        torch.cuda.synchronize()
+    finally:
+        _capped(0)
     got = out.cpu().numpy().astype(np.float64)
     want = U.forward(ref, dose.astype(np.float64), rho.astype(np.float64))
     # The kernels keep activations in bf16 (relative rounding <= 2^-9 per
@@ -100,15 +119,21 @@ def test_forward_matches_reference(size, n, shape):
         int(ratio.argmax()), ratio.shape))
 
 
-@pytest.mark.parametrize("size,n,shape", [(16, 2, None), (32, 2, None),
-                                          (0, 1, (16, 24, 32))])
-def test_gradients_match_reference(size, n, shape):
+@pytest.mark.parametrize("size,n,shape,blocks",
+                         [(16, 2, None, None), (32, 2, None, None),
+                          (0, 1, (16, 24, 32), None), (16, 2, None, 13),
+                          (16, 2, None, 3)])
+def test_gradients_match_reference(size, n, shape, blocks):
     import torch
     net, ref, dose, rho, tgt, T = _setup(n=n, size=size, shape=shape)
     net.loss.zero_()
     net.grads.zero_()
-    net.backward(T(dose), T(rho), T(tgt))
-    torch.cuda.synchronize()
+    _capped(blocks)
+    try:
+        net.backward(T(dose), T(rho), T(tgt))
+        torch.cuda.synchronize()
+    finally:
+        _capped(0)
     g = net.grads.cpu().numpy().astype(np.float64)
     L, G = U.loss_and_grads(ref, dose.astype(np.float64),
                             rho.astype(np.float64), tgt.astype(np.float64))
