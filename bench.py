@@ -119,22 +119,34 @@ def unet_forward_flops(shape, base=16, in_c=2):
 
 def bench_imrt(P, S, torch, hpb, n_batches, wl=None):
     """A batched plan (default: the IMRT plan, 7 beams x 20 segments),
-    MU-proportional histories, autotuned, replayed from a hipGraph."""
+    MU-proportional histories, autotuned, replayed from a hipGraph: two
+    plans of the plan's fields with two batches in flight
+    (psl_plan_run_pair), and one plan alone for comparison."""
     wl = wl or S.workload_imrt()
     # graph capture needs a created stream (not the legacy null stream)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         eng = P.Engine(wl, histories_per_batch=hpb)   # isocentre at SAD
-        plan = eng.make_plan(stream)
-        r = plan.autotune(trials=1)
-        plan.run(0, 2, use_graph=True)
+        pair = eng.make_plan_pair(stream)
+        plan = pair.a
+        r = pair.autotune(trials=1)
+        pair.run(0, 2, use_graph=True)
         stream.synchronize()
         eng.reset_tally()
+        stream.synchronize()
+        # two batches in flight: the pair's graph replayed n / 2 times
+        t0 = time.perf_counter()
+        pair.run(0, n_batches, use_graph=True)
+        stream.synchronize()
+        dt = time.perf_counter() - t0
+        # one plan's own graph, one batch after another
+        eng.reset_tally()
+        plan.run(0, 2, use_graph=True)
         stream.synchronize()
         t0 = time.perf_counter()
         plan.run(0, n_batches, use_graph=True)
         stream.synchronize()
-        dt = time.perf_counter() - t0
+        dt_single = time.perf_counter() - t0
         # kernel times of one batch run eagerly (the graph replays the same
         # launches; events are not recorded inside a captured graph)
         P.profile_read(reset=True)
@@ -146,13 +158,16 @@ def bench_imrt(P, S, torch, hpb, n_batches, wl=None):
     st = eng.stats_dict()
     roof = hbm_roofline(groups, st, eng.nvox)
     atom = atomic_roofline(P, eng, groups, st, 0, replay=False)
-    plan.destroy()
+    pair.destroy()
     return {"workload": "%s: %d fields, MU-proportional, 128^3 water at "
                         "2.5 mm, %d batches of %d histories"
                         % (wl.name, len(wl.fields), n_batches, hpb),
             "histories": n_batches * hpb, "seconds": dt,
             "histories_per_s": n_batches * hpb / dt,
             "ms_per_batch": 1e3 * dt / n_batches, "graph": True,
+            "in_flight": 2,
+            "single_plan": {"histories_per_s": n_batches * hpb / dt_single,
+                            "ms_per_batch": 1e3 * dt_single / n_batches},
             "tuned": {"blocks_per_cu": r.launch.blocks_per_cu,
                       "rebucket": r.launch.rebucket,
                       "n_ebuckets": r.n_ebuckets,

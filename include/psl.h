@@ -600,6 +600,28 @@ psl_status psl_autotune(psl_plan *p, int32_t trials, psl_tune_result *out,
                         void *stream);
 /* Current queue layout and launch shape of a plan (after tuning). */
 psl_status psl_plan_get(const psl_plan *p, psl_queue *q, psl_launch *launch);
+/*
+ * psl_plan_run_pair - batches first_batch .. first_batch + n_batches - 1 of
+ * one plan split over two plans a and b of the same fields (Sec. 2.3.3,
+ * 2.4: many fields sharing one phase space, batch after batch) that fold
+ * into the same d_s1/d_s2 but each own their queues, accumulator,
+ * statistics and workspace: batches first + 2k run on a, first + 2k + 1 on
+ * b, the two of a pair in flight at once (b's on a stream a holds, each
+ * plan's transport with half its blocks per CU), a's fold before b's.
+ * With an odd count the last batch runs on a alone.  The histories and,
+ * with the fixed-point tally, the sums equal those of psl_plan_run of
+ * either plan over the same batches.  use_graph != 0 captures one pair into
+ * a hipGraph (kept by a, captured again when b's tuning changes) and
+ * replays it.  PSL_EINVAL if the plans share buffers they must not share
+ * or fold into different sums.  Calls on one pair must not overlap.
+ */
+psl_status psl_plan_run_pair(psl_plan *a, psl_plan *b, int64_t first_batch,
+                             int32_t n_batches, int32_t use_graph,
+                             void *stream);
+/* Gives dst the transport launch shape and electron bucketing of src (for
+ * example after psl_autotune on src), so that two plans of a pair run the
+ * same configuration. */
+psl_status psl_plan_copy_tuning(psl_plan *dst, const psl_plan *src);
 psl_status psl_plan_destroy(psl_plan *p);
 
 /* ------------------------------------------------------------------------ */

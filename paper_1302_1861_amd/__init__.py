@@ -38,6 +38,7 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_profile_read", "psl_bench_atomics_workspace_bytes",
            "psl_bench_atomics", "psl_plan_workspace_bytes", "psl_plan_create",
            "psl_plan_run", "psl_autotune", "psl_plan_get", "psl_plan_destroy",
+           "psl_plan_run_pair", "psl_plan_copy_tuning",
            "unet_param_count", "unet_workspace_bytes", "unet_init",
            "unet_set_params", "unet_forward", "unet_backward",
            "unet_adam_step", "unet_set_brick_blocks", "dose_denoise",
@@ -251,6 +252,10 @@ def lib():
         L.psl_autotune.restype = i32
         L.psl_plan_get.argtypes = [vp, vp, vp]
         L.psl_plan_get.restype = i32
+        L.psl_plan_run_pair.argtypes = [vp, vp, i64, i32, i32, vp]
+        L.psl_plan_run_pair.restype = i32
+        L.psl_plan_copy_tuning.argtypes = [vp, vp]
+        L.psl_plan_copy_tuning.restype = i32
         L.psl_plan_destroy.argtypes = [vp]
         L.psl_plan_destroy.restype = i32
         L.unet_param_count.argtypes = [i32, i32]
@@ -531,6 +536,10 @@ class Plan:
         _check(lib().psl_plan_get(self.handle, C.byref(q), C.byref(L)))
         return q, L
 
+    def copy_tuning(self, src):
+        """This plan takes src's launch shape and electron bucketing."""
+        _check(lib().psl_plan_copy_tuning(self.handle, src.handle))
+
     def destroy(self):
         if self.handle:
             _check(lib().psl_plan_destroy(self.handle))
@@ -541,6 +550,31 @@ class Plan:
             self.destroy()
         except Exception:
             pass
+
+
+class PlanPair:
+    """Two plans of the same fields and sums with their own queues,
+    accumulators, statistics and workspaces: batches alternate between
+    them, two in flight at once (psl_plan_run_pair)."""
+
+    def __init__(self, a, b):
+        self.a, self.b = a, b
+        self.stream = a.stream
+
+    def autotune(self, trials=2, stream=None):
+        """Tunes the first plan and gives the second its configuration."""
+        r = self.a.autotune(trials, stream)
+        self.b.copy_tuning(self.a)
+        return r
+
+    def run(self, first_batch, n_batches, use_graph=True, stream=None):
+        _check(lib().psl_plan_run_pair(
+            self.a.handle, self.b.handle, int(first_batch), int(n_batches),
+            1 if use_graph else 0, _stream(stream or self.stream)))
+
+    def destroy(self):
+        self.a.destroy()
+        self.b.destroy()
 
 
 def dose_gamma(ref, ev, voxel, dose_crit=0.02, dta=0.2, threshold=0.1,

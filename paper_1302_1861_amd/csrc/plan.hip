@@ -7,6 +7,7 @@
 #include "common.hpp"
 #include "sample.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -27,32 +28,85 @@ struct psl_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t graph_stream = nullptr;
+    // psl_plan_run_pair (held by the pair's first plan): the second plan's
+    // stream, the events that order the folds and join the streams, and
+    // the graph of one pair of batches
+    hipStream_t side = nullptr;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_fork = nullptr;
+    hipGraph_t pair_graph = nullptr;
+    hipGraphExec_t pair_exec = nullptr;
+    hipStream_t pair_stream = nullptr;
+    const psl_plan *pair_with = nullptr;
+    uint64_t pair_with_version = 0;
+    uint64_t version = 0;       // + 1 whenever a captured graph is dropped
 };
 
 namespace psl {
 namespace {
 
 void drop_graph(psl_plan *p) {
+    ++p->version;
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     p->exec = nullptr;
     p->graph = nullptr;
     p->graph_stream = nullptr;
+    if (p->pair_exec) (void)hipGraphExecDestroy(p->pair_exec);
+    if (p->pair_graph) (void)hipGraphDestroy(p->pair_graph);
+    p->pair_exec = nullptr;
+    p->pair_graph = nullptr;
+    p->pair_stream = nullptr;
+    p->pair_with = nullptr;
+}
+
+// Sampling and transport of one batch (index read from *d_batch).
+psl_status enqueue_transport(psl_plan *p, const psl_launch *launch,
+                             hipStream_t st) {
+    psl_status s;
+    p->sc.q = p->q;
+    if ((s = sample_batch(p->sc, p->d_batch, st))) return s;
+    return transport_batch(&p->q, &p->ph, &p->phys, p->tables, p->seed,
+                           &p->acc, p->stats, launch, p->tws, p->tws_bytes,
+                           st);
+}
+
+// The fold into the running sums, then the batch index + stride.
+psl_status enqueue_fold(psl_plan *p, int64_t stride, hipStream_t st) {
+    psl_status s;
+    if ((s = dose_tally(&p->acc, p->s1, p->s2, PSL_TALLY_FOLD, 0, &p->ph, 1.0,
+                        nullptr, nullptr, st)))
+        return s;
+    return add_i64(p->d_batch, stride, st);
 }
 
 // One batch: sampling, transport, fold, batch index + 1.  Kernels only.
 psl_status enqueue_batch(psl_plan *p, hipStream_t st) {
     psl_status s;
-    p->sc.q = p->q;
-    if ((s = sample_batch(p->sc, p->d_batch, st))) return s;
-    if ((s = transport_batch(&p->q, &p->ph, &p->phys, p->tables, p->seed,
-                             &p->acc, p->stats, &p->launch, p->tws,
-                             p->tws_bytes, st)))
-        return s;
-    if ((s = dose_tally(&p->acc, p->s1, p->s2, PSL_TALLY_FOLD, 0, &p->ph, 1.0,
-                        nullptr, nullptr, st)))
-        return s;
-    return inc_i64(p->d_batch, st);
+    if ((s = enqueue_transport(p, &p->launch, st))) return s;
+    return enqueue_fold(p, 1, st);
+}
+
+// Two batches in flight: a's on st, b's on the side stream, each plan's
+// transport with half its blocks per CU so that both persistent grids are
+// resident; a's fold, then b's (after a's), then st joins the side stream.
+// The caller has made st's earlier work visible to the side stream.
+psl_status enqueue_pair(psl_plan *a, psl_plan *b, hipStream_t st) {
+    psl_status s;
+    hipStream_t sb = a->side;
+    psl_launch la = a->launch, lb = b->launch;
+    la.blocks_per_cu = std::max(1, la.blocks_per_cu / 2);
+    lb.blocks_per_cu = std::max(1, lb.blocks_per_cu / 2);
+    PSL_HIP(hipEventRecord(a->ev_fork, st));
+    PSL_HIP(hipStreamWaitEvent(sb, a->ev_fork, 0));
+    if ((s = enqueue_transport(a, &la, st))) return s;
+    if ((s = enqueue_transport(b, &lb, sb))) return s;
+    if ((s = enqueue_fold(a, 2, st))) return s;
+    PSL_HIP(hipEventRecord(a->ev_a, st));
+    PSL_HIP(hipStreamWaitEvent(sb, a->ev_a, 0));
+    if ((s = enqueue_fold(b, 2, sb))) return s;
+    PSL_HIP(hipEventRecord(a->ev_b, sb));
+    PSL_HIP(hipStreamWaitEvent(st, a->ev_b, 0));
+    return PSL_OK;
 }
 
 __global__ void k_zero_u64(uint64_t *a, int64_t n) {
@@ -185,9 +239,102 @@ extern "C" psl_status psl_plan_run(psl_plan *p, int64_t first_batch,
     return PSL_OK;
 }
 
+extern "C" psl_status psl_plan_run_pair(psl_plan *a, psl_plan *b,
+                                        int64_t first_batch,
+                                        int32_t n_batches, int32_t use_graph,
+                                        void *stream) {
+    PSL_REQUIRE(a && b && a != b, "need two distinct plans");
+    PSL_REQUIRE(first_batch >= 0 && n_batches >= 0, "bad batch range");
+    PSL_REQUIRE(a->s1 == b->s1 && a->s2 == b->s2,
+                "the plans of a pair fold into the same sums");
+    PSL_REQUIRE(a->acc.data != b->acc.data && a->stats != b->stats &&
+                    a->q.d_counts != b->q.d_counts && a->tws != b->tws &&
+                    a->q.ph.E != b->q.ph.E && a->q.el.E != b->q.el.E,
+                "the plans of a pair need their own queues, accumulators, "
+                "statistics and workspaces");
+    PSL_REQUIRE(a->acc.mode == b->acc.mode &&
+                    a->acc.frac_bits == b->acc.frac_bits,
+                "the plans of a pair need the same accumulator mode");
+    hipStream_t st = (hipStream_t)stream;
+    PSL_REQUIRE(!use_graph || st != nullptr,
+                "graph capture needs a created stream, not the null stream");
+    psl_status s;
+    if (!a->side) {
+        PSL_HIP(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking));
+        PSL_HIP(hipEventCreateWithFlags(&a->ev_a, hipEventDisableTiming));
+        PSL_HIP(hipEventCreateWithFlags(&a->ev_b, hipEventDisableTiming));
+        PSL_HIP(hipEventCreateWithFlags(&a->ev_fork, hipEventDisableTiming));
+    }
+    if ((s = set_i64(a->d_batch, first_batch, st))) return s;
+    if ((s = set_i64(b->d_batch, first_batch + 1, st))) return s;
+    const int32_t pairs = n_batches / 2;
+    if (pairs > 0) {
+        if (!use_graph) {
+            for (int k = 0; k < pairs; ++k)
+                if ((s = enqueue_pair(a, b, st))) return s;
+        } else {
+            if (!a->pair_exec || a->pair_stream != st || a->pair_with != b ||
+                a->pair_with_version != b->version) {
+                if (a->pair_exec) (void)hipGraphExecDestroy(a->pair_exec);
+                if (a->pair_graph) (void)hipGraphDestroy(a->pair_graph);
+                a->pair_exec = nullptr;
+                a->pair_graph = nullptr;
+                PSL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                s = enqueue_pair(a, b, st);
+                hipGraph_t gr = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &gr);
+                if (s) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return s;
+                }
+                if (e != hipSuccess) {
+                    set_error("graph capture failed: %s",
+                              hipGetErrorString(e));
+                    return PSL_EHIP;
+                }
+                a->pair_graph = gr;
+                e = hipGraphInstantiate(&a->pair_exec, gr, nullptr, nullptr,
+                                        0);
+                if (e != hipSuccess) {
+                    (void)hipGraphDestroy(gr);
+                    a->pair_graph = nullptr;
+                    set_error("graph instantiation failed: %s",
+                              hipGetErrorString(e));
+                    return PSL_EHIP;
+                }
+                a->pair_stream = st;
+                a->pair_with = b;
+                a->pair_with_version = b->version;
+            }
+            for (int k = 0; k < pairs; ++k)
+                PSL_HIP(hipGraphLaunch(a->pair_exec, st));
+        }
+    }
+    if (n_batches % 2) {
+        // the last batch on a alone (its index is first + 2 pairs)
+        if ((s = enqueue_batch(a, st))) return s;
+    }
+    return PSL_OK;
+}
+
+extern "C" psl_status psl_plan_copy_tuning(psl_plan *dst,
+                                           const psl_plan *src) {
+    PSL_REQUIRE(dst && src, "NULL plan");
+    dst->launch = src->launch;
+    dst->q.n_ebuckets = src->q.n_ebuckets;
+    for (int b = 0; b <= src->q.n_ebuckets; ++b)
+        dst->q.e_bucket_edges[b] = src->q.e_bucket_edges[b];
+    drop_graph(dst);
+    return PSL_OK;
+}
+
 extern "C" psl_status psl_plan_destroy(psl_plan *p) {
     if (!p) return PSL_OK;
     drop_graph(p);
+    if (p->ev_a) (void)hipEventDestroy(p->ev_a);
+    if (p->ev_b) (void)hipEventDestroy(p->ev_b);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->side) (void)hipStreamDestroy(p->side);
     delete p;
     return PSL_OK;
 }

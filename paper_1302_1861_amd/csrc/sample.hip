@@ -323,6 +323,7 @@ psl_status validate_particles(const psl_particles &p, const char *name) {
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 __global__ void k_inc_i64(int64_t *p) { *p += 1; }
+__global__ void k_add_i64(int64_t *p, int64_t v) { *p += v; }
 
 }  // namespace
 
@@ -370,6 +371,12 @@ psl_status set_i64(int64_t *p, int64_t v, hipStream_t st) {
 
 psl_status inc_i64(int64_t *p, hipStream_t st) {
     hipLaunchKernelGGL(k_inc_i64, dim3(1), dim3(1), 0, st, p);
+    PSL_LAUNCHED();
+    return PSL_OK;
+}
+
+psl_status add_i64(int64_t *p, int64_t v, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(1), 0, st, p, v);
     PSL_LAUNCHED();
     return PSL_OK;
 }

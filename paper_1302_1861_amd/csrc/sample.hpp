@@ -181,9 +181,10 @@ psl_status sample_alloc(const SampleCtx &ctx, hipStream_t st);
 // the per-history kernel, compaction into the queues.
 psl_status sample_batch(const SampleCtx &ctx, const int64_t *d_batch,
                         hipStream_t st);
-// Writes v into *p / adds 1 to *p (device int64), as kernels.
+// Writes v into *p / adds 1 / adds v to *p (device int64), as kernels.
 psl_status set_i64(int64_t *p, int64_t v, hipStream_t st);
 psl_status inc_i64(int64_t *p, hipStream_t st);
+psl_status add_i64(int64_t *p, int64_t v, hipStream_t st);
 
 psl_status validate_queue(const psl_queue *q);
 

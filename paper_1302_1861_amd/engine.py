@@ -454,6 +454,23 @@ class Engine:
             _ptr(ws), ws.numel(), _stream(stream)))
         return Plan(h, ws, stream)
 
+    def make_plan_pair(self, stream=None):
+        """Two psl_plans over this engine's fields and running sums, on the
+        engine's first two sets of queues, accumulators, statistics (and
+        their own plan workspaces), for psl_plan_run_pair."""
+        from . import PlanPair
+        self._make_sets(2)
+        cur = {k: getattr(self, k, None) for k in self._SET_KEYS}
+        try:
+            self._use(0)
+            a = self.make_plan(stream)
+            self._use(1)
+            b = self.make_plan(stream)
+        finally:
+            for k, v in cur.items():
+                setattr(self, k, v)
+        return PlanPair(a, b)
+
     def stats_dict(self):
         """Batch statistics; `lost` includes entries a full queue region
         could not take."""

@@ -105,3 +105,61 @@ def test_autotune_choice_keeps_the_dose():
     assert q.n_ebuckets == r.n_ebuckets and L.rebucket == r.launch.rebucket
     plan.destroy()
     p_r.destroy()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_plan_pair_equals_single_plan(use_graph):
+    """Two plans of one engine, batches alternating between them with two
+    in flight: the sums equal one plan's over the same batches, for odd and
+    even counts, replay after replay, also after the pair's tuning
+    changed."""
+    import torch
+    wl = _imrt()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ref = _engine(wl, 250_000)
+        p_r = ref.make_plan()
+        eng = _engine(wl, 250_000)
+        pair = eng.make_plan_pair()
+        p_r.run(0, 5, use_graph=False)
+        pair.run(0, 5, use_graph=use_graph)
+        torch.cuda.current_stream().synchronize()
+        want = ref.s1.cpu().numpy()
+        got = eng.s1.cpu().numpy()
+        _say("pair", use_graph, float(got.sum()), float(want.sum()))
+        assert got.any() and np.array_equal(got, want)
+        assert np.array_equal(eng.s2.cpu().numpy(), ref.s2.cpu().numpy())
+        # eager torch work between calls, then four more batches
+        x = torch.randn(1 << 20, device="cuda")
+        float((x * 3.0).sum())
+        p_r.run(5, 4, use_graph=False)
+        pair.run(5, 4, use_graph=use_graph)
+        torch.cuda.current_stream().synchronize()
+        assert np.array_equal(eng.s1.cpu().numpy(), ref.s1.cpu().numpy())
+        # tuned (the first plan timed, the second given its configuration;
+        # the pair's graph is captured again): the same sums
+        r = pair.autotune(trials=1)
+        qa, la = pair.a.layout()
+        qb, lb = pair.b.layout()
+        assert (la.blocks_per_cu, la.rebucket, qa.n_ebuckets) == \
+            (lb.blocks_per_cu, lb.rebucket, qb.n_ebuckets) == \
+            (r.launch.blocks_per_cu, r.launch.rebucket, r.n_ebuckets)
+        p_r.run(9, 3, use_graph=False)
+        pair.run(9, 3, use_graph=use_graph)
+        torch.cuda.current_stream().synchronize()
+        assert np.array_equal(eng.s1.cpu().numpy(), ref.s1.cpu().numpy())
+    pair.destroy()
+    p_r.destroy()
+
+
+def test_plan_pair_rejects_shared_buffers():
+    import paper_1302_1861_amd as P
+    wl = _imrt(n_particles=100_000)
+    eng = _engine(wl, 50_000)
+    a = eng.make_plan()
+    b = eng.make_plan()          # same queues, accumulator and statistics
+    st = P.lib().psl_plan_run_pair(a.handle, b.handle, 0, 2, 0, None)
+    assert st == P.PSL_EINVAL
+    assert "own queues" in P.lib().psl_last_error().decode()
+    a.destroy()
+    b.destroy()
