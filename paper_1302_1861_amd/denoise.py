@@ -108,13 +108,13 @@ class PairMaker:
         return eng
 
     def run(self, eng, seed, batches=10):
-        """Sampling, transport and tally of a prepared engine: dose (Gy per
-        phase-space particle), its batch sigma and the density, device
-        float32 [nz,ny,nx]."""
+        """Sampling, transport and tally of a prepared engine, two batches
+        in flight (Engine.run_pipelined: the dose of the batches run one
+        after another): dose (Gy per phase-space particle), its batch sigma
+        and the density, device float32 [nz,ny,nx]."""
         eng.reset_tally()
         eng.set_seed(seed)
-        for b in range(batches):
-            eng.step(b)
+        eng.run_pipelined(0, batches)
         d, s = eng.finalize()
         nx, ny, nz = self.shape
         return (d.view(nz, ny, nx).clone(), s.view(nz, ny, nx).clone(),
