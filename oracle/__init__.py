@@ -474,7 +474,8 @@ def finalize(s1, s2, n_batches, phantom, norm):
     B = n_batches
     rho = phantom.density.reshape(-1).astype(np.float64)
     V = float(np.prod(phantom.voxel))
-    c = np.where(rho > 0, MEV_PER_G_TO_GY / (rho * V), 0.0) * norm
+    with np.errstate(divide="ignore"):
+        c = np.where(rho > 0, MEV_PER_G_TO_GY / (rho * V), 0.0) * norm
     mean = s1 / B
     var = np.maximum(s2 - s1 * s1 / B, 0.0) / (B - 1) if B > 1 else \
         np.zeros_like(s1)

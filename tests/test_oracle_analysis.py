@@ -45,3 +45,15 @@ def test_zscore():
     assert abs(z["mean"]) < 0.05 and 0.95 < z["sd"] < 1.05
     zb = analysis.zscore_stats(a + 1.0, sa, b, np.full(20000, 0.4))
     assert zb["mean"] > 1.5
+
+
+def test_time_to_uncertainty_worked_example():
+    """T_1% = T_run (sigma_bar / 1%)^2 with sigma_bar the mean relative
+    uncertainty at or above half the maximum: relative uncertainties 2% and
+    4% on the two voxels above half the maximum give sigma_bar = 3%, so a
+    1 s run needs 9 s; the voxel below half the maximum does not count."""
+    dose = np.array([1.0, 0.8, 0.3])
+    sigma = np.array([0.02, 0.032, 0.3])
+    t, s = analysis.time_to_uncertainty(1.0, dose, sigma)
+    assert s == pytest.approx(0.03, rel=1e-12)
+    assert t == pytest.approx(9.0, rel=1e-12)

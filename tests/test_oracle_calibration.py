@@ -62,3 +62,41 @@ def test_point_closed_forms(oracle_lib):
     # outside the phantom with no centre in reach: nothing
     assert oracle_lib.dose_point(d, s, ph, (9.0, 0.0, 90.0), 0.5) == \
         (0.0, 0.0, 0)
+
+
+def test_point_radius_is_closed(oracle_lib):
+    """Voxel centres at exactly the radius belong to the set: about a voxel
+    centre with the radius one voxel, the centre and its six face
+    neighbours (all distances exact in binary)."""
+    ph = S.water_phantom((8, 8, 8), 0.5, (-2.0, -2.0, 100.0))
+    d = np.arange(512, dtype=np.float64).reshape(8, 8, 8)
+    s = np.full((8, 8, 8), 0.1)
+    m, se, n = oracle_lib.dose_point(d, s, ph, (0.25, 0.25, 102.25), 0.5)
+    nb = [(4, 4, 4), (3, 4, 4), (5, 4, 4), (4, 3, 4), (4, 5, 4), (4, 4, 3),
+          (4, 4, 5)]
+    assert n == 7
+    assert m == _approx(np.mean([d[v] for v in nb]))
+    assert se == _approx(math.sqrt(7 * 0.01) / 7)
+
+
+def test_batch_mean_standard_error_and_dose_worked_example(oracle_lib):
+    """Eq. (5) and the batch uncertainty on numbers worked by hand: batch
+    energies 1, 2, 3 and 6 MeV in a voxel give the mean 3, the sample
+    variance (4 + 1 + 0 + 9) / 3 = 14/3 and the standard error of the mean
+    sqrt(14/3 / 4) = sqrt(7/6); the dose is energy x 1.602176634e-10 Gy per
+    MeV/g over the voxel mass rho V (here 0.5 g/cm^3 x 8 cm^3), times the
+    normalisation; a voxel of density 0 has no dose."""
+    ph = S.water_phantom((2, 1, 1), 2.0, (0.0, 0.0, 0.0))
+    ph.density[0, 0, :] = [0.5, 0.0]
+    # (the finaliser divides by rho V before masking the rho = 0 voxel)
+    s1 = np.zeros(2)
+    s2 = np.zeros(2)
+    for e in (1.0, 2.0, 3.0, 6.0):
+        oracle_lib.fold(np.array([e, e]), s1, s2)
+    assert list(s1) == [12.0, 12.0] and list(s2) == [50.0, 50.0]
+    norm = 1e-3
+    dose, se = oracle_lib.finalize(s1, s2, 4, ph, norm)
+    c = 1.602176634e-10 / (0.5 * 8.0) * norm
+    assert dose[0] == pytest.approx(3.0 * c, rel=1e-15, abs=0)
+    assert se[0] == pytest.approx(math.sqrt(7.0 / 6.0) * c, rel=1e-15, abs=0)
+    assert dose[1] == 0.0 and se[1] == 0.0

@@ -331,3 +331,123 @@ def test_first_collision_dose_closed_form(oracle_lib):
     mass = 1.0 * vox ** 3
     np.testing.assert_allclose(
         dose, acc * 1.602176634e-10 / mass / n, rtol=1e-15)
+
+
+# ------------------------------------- weights, densities, cut-offs ------
+def test_deposits_carry_the_particle_weight(oracle_lib):
+    """Every deposit is energy x weight: the weighted tally of a history is
+    its weight times its (unweighted) deposited energy, for photons with
+    their recoil electrons and for electrons alike."""
+    ph = S.heterogeneous_phantom((16, 16, 16), 0.5, (-4.0, -4.0, 100.0), 6)
+    rng = np.random.default_rng(11)
+    n = 400
+    st = np.zeros((n, 8))
+    st[:, 0] = rng.uniform(0.3, 6.0, n)
+    st[:, 1] = rng.uniform(-3, 3, n)
+    st[:, 2] = rng.uniform(-3, 3, n)
+    st[:, 3] = 100.0
+    st[:, 6] = 1.0
+    st[:, 7] = rng.uniform(0.1, 3.0, n)
+    types = (np.arange(n) % 2).astype(np.uint8)
+    hits = {0: 0, 1: 0}
+    for i in range(0, n, 13):      # one history at a time
+        acc, _, led, _ = oracle_lib.transport(
+            types[i:i + 1], st[i:i + 1], np.array([i], np.uint64), 4, ph,
+            ledger=True)
+        assert acc.sum() == pytest.approx(st[i, 7] * led[0, 1], rel=1e-12)
+        hits[int(types[i])] += led[0, 1] > 0
+    assert hits[0] >= 3 and hits[1] >= 10   # photons may cross unscattered
+
+
+@pytest.mark.parametrize("rho", [0.26, 1.85])
+def test_attenuation_scales_with_density(oracle_lib, rho):
+    """The interaction coefficient is rho n_e sigma_KN: in a uniform slab
+    of density rho the first-interaction depths follow exp(-rho mu z)."""
+    E = 1.25
+    ph = S.water_phantom((4, 4, 60), 1.0, (-2.0, -2.0, 100.0))
+    ph.density[:] = rho
+    n = 30_000
+    _, _, _, tr = _pencil(oracle_lib, E, n, ph,
+                          oracle_lib.FLAG_FIRST_COLLISION)
+    mu = rho * NE * oracle_lib.kn_sigma(E)
+    d = tr[:, 0] - 100.0
+    hit = ~np.isnan(d)
+    p = 1 - math.exp(-mu * 60.0)
+    assert abs(hit.mean() - p) < 4 * math.sqrt(p * (1 - p) / n)
+    assert stats.kstest(d[hit], lambda z: (1 - np.exp(-mu * z)) / p
+                        ).pvalue > 1e-3
+
+
+def test_low_energy_photons_deposit_everything_in_a_large_medium(
+        oracle_lib):
+    """0.3 MeV photons (every recoil below the electron cut-off: the
+    largest recoil energy is E 2k / (1 + 2k) = 0.16 MeV) started at the
+    centre of a 4 m water cube: nothing escapes (the chance to cross 2 m is
+    below 1e-8), so the recoils that stay under the cut-off and the photon
+    that ends under its own cut-off deposit where they are, and the
+    deposited energy is the photon's energy, history by history."""
+    E = 0.3
+    k = E / ME
+    assert E * 2 * k / (1 + 2 * k) < TCUT
+    ph = S.water_phantom((4, 4, 4), 100.0, (-200.0, -200.0, 0.0))
+    n = 300
+    rng = np.random.default_rng(12)
+    st = np.zeros((n, 8))
+    st[:, 0] = E
+    st[:, 1:4] = [1e-3, 2e-3, 200.0]
+    d = rng.normal(size=(n, 3))
+    st[:, 4:7] = d / np.linalg.norm(d, axis=1)[:, None]
+    st[:, 7] = 1.0
+    acc, cnt, led, _ = oracle_lib.transport(
+        np.zeros(n, np.uint8), st, np.arange(n, dtype=np.uint64), 8, ph,
+        ledger=True)
+    assert cnt[0] > 5 * n                  # several Compton events each
+    np.testing.assert_allclose(led[:, 1], E, rtol=1e-12)
+    assert np.all(led[:, 2] == 0.0) and np.all(led[:, 3] == 0.0)
+    assert acc.sum() == pytest.approx(n * E, rel=1e-12)
+
+
+def test_particle_on_the_far_face_enters_the_last_voxel(oracle_lib):
+    """A point on the box surface belongs to the voxel inside: an electron
+    started exactly on the far x face, moving inward with a range shorter
+    than a voxel, deposits all its energy in the last voxel of its row."""
+    ph = S.water_phantom((4, 4, 4), 1.0, (0.0, 0.0, 0.0))
+    T = 0.5                                # CSDA range about 0.18 cm
+    # inward across the face, and along it (parallel to the face: the
+    # electron stays in the last voxel of the row)
+    for d, vox in (((-1.0, 0.0, 0.0), (2, 1, 3)), ((0.0, -1.0, 0.0),
+                                                   (2, 2, 3))):
+        st = np.array([[T, 4.0, 2.5 if d[1] else 1.5, 2.5, *d, 1.0]])
+        acc, _, led, _ = oracle_lib.transport(
+            np.ones(1, np.uint8), st, np.zeros(1, np.uint64), 2, ph,
+            oracle_lib.ophys(flags=oracle_lib.FLAG_NO_MSC), ledger=True)
+        assert led[0, 1] == pytest.approx(T, rel=1e-12)
+        assert led[0, 2] == 0.0
+        assert acc.reshape(4, 4, 4)[vox] == pytest.approx(T, rel=1e-12)
+
+
+def test_electron_energy_never_falls_below_the_cut_off_in_flight(
+        oracle_lib):
+    """CSDA steps end at the cut-off: along a straight track (no
+    scattering) through 1 mm voxels, the energy lost in each voxel before
+    the last equals T_in - T_out from the CSDA energy-range relation and
+    the last voxel receives what is left, down from at least the cut-off;
+    so every deposit but the last is below T0 - T_cut and their sum never
+    exceeds it."""
+    ph = S.water_phantom((4, 4, 60), 0.1, (-0.2, -0.2, 0.0))
+    T0 = 2.0
+    st = np.array([[T0, 1e-3, 2e-3, 0.0, 0.0, 0.0, 1.0, 1.0]])
+    acc, _, led, _ = oracle_lib.transport(
+        np.ones(1, np.uint8), st, np.zeros(1, np.uint64), 2, ph,
+        oracle_lib.ophys(flags=oracle_lib.FLAG_NO_MSC), ledger=True)
+    col = acc.reshape(60, 4, 4)[:, 2, 2]
+    nz = np.nonzero(col)[0]
+    last = nz[-1]
+    assert col[:last].sum() <= T0 - TCUT + 1e-12
+    # the residual range above the cut-off fixes the depth of the last
+    # deposit: r(T0) - r(T_cut) of water, to the voxel
+    r = oracle_lib.csda_range(TCUT, T0)
+    assert last == int(r / 0.1)
+    # and the final deposit is at least the cut-off energy
+    assert col[last] >= TCUT - 1e-12
+    assert led[0, 1] == pytest.approx(T0, rel=1e-12)

@@ -373,3 +373,95 @@ def test_sample_collimator_and_couch_rotations(oracle_lib):
                                atol=1e-9)
     np.testing.assert_allclose(b["state"][ok, 2], -a["state"][ok, 1],
                                atol=1e-9)
+
+
+# ------------------------------------------------ boundary readings ------
+def test_cull_excludes_bins_that_only_touch_the_roi(oracle_lib):
+    """A position bin is kept when it overlaps the ROI with positive area:
+    with the PSL plane at the jaw plane (magnification 1) a symmetric 6 cm
+    field has its ROI at exactly +-1.5 cm, and the bins [1.5, 2] and
+    [-2, -1.5] that only touch it are culled."""
+    edges = np.arange(-2.0, 2.01, 0.5).astype(np.float32)
+    grid = S.Grid(S.log_edges(0.1, 6.0, 4), edges, edges, 50.0)
+    geom = {"sad": 100.0, "z_x": 50.0, "z_y": 50.0}
+    lo, hi = oracle_lib.roi(-3.0, 3.0, 50.0, 100.0, 50.0)
+    assert (lo, hi) == (-1.5, 1.5)
+    m = oracle_lib.cull([S.Field(-3, 3, -3, 3)], grid, True, geom)
+    m = m.reshape(grid.n_y, grid.n_x)
+    inner = np.array([0, 1, 1, 1, 1, 1, 1, 0], np.uint8)
+    np.testing.assert_array_equal(m, np.outer(inner, inner))
+
+
+def _edge_setup(oracle_lib, xs, ys, gantry=0.0, origin_z=100.0):
+    from gpu_util import phase_space_arrays
+    n = len(xs)
+    one = np.ones(n)
+    ps = phase_space_arrays(np.zeros(n), one, xs, ys, 0 * one, 0 * one, one,
+                            50.0)
+    ph = S.water_phantom((16, 16, 16), 1.0, (-8.0, -8.0, origin_z))
+    geom = oracle_lib.geometry(ph, z_x=50.0, z_y=50.0, z_psl=50.0)
+    return ps, geom
+
+
+def test_jaw_edges_are_closed(oracle_lib):
+    """The jaws are perfect collimators whose edges belong to the opening:
+    a particle travelling along the beam axis exactly through the jaw
+    edge (here at +-1.5 cm: 3 cm at SAD x 50/100) passes, the next float
+    outside it is stopped."""
+    e = np.float32(1.5)
+    out = np.nextafter(e, np.float32(2.0))
+    xs = [-e, e, 0.0, 0.0, -out, out, 0.0, 0.0]
+    ys = [0.0, 0.0, -e, e, 0.0, 0.0, -out, out]
+    ps, geom = _edge_setup(oracle_lib, xs, ys)
+    f = S.Field(-3, 3, -3, 3)
+    r = oracle_lib.stream_sample(f, geom, ps, S.log_edges(0.1, 6.0, 2),
+                                 len(xs), 0, 0, 100, method=2)
+    src = r["src"]
+    status = dict(zip(src.tolist(), r["status"].tolist()))
+    assert [status[i] for i in range(8)] == [1, 1, 1, 1, 0, 0, 0, 0]
+
+
+def test_particle_starting_inside_the_phantom_is_not_moved(oracle_lib):
+    """The move to the phantom is along the ray only when the particle
+    starts outside: one already inside the box (here the PSL plane at
+    z = 50 inside a box from z = 40) keeps its position."""
+    xs = [0.25, -1.0, 2.5]
+    ys = [0.5, 1.0, -3.0]
+    ps, geom = _edge_setup(oracle_lib, xs, ys, origin_z=40.0)
+    f = S.Field(-10, 10, -10, 10)
+    r = oracle_lib.stream_sample(f, geom, ps, S.log_edges(0.1, 6.0, 2), 3,
+                                 0, 0, 100, method=2)
+    assert np.all(r["status"] == 1)
+    st, src = r["state"], r["src"]
+    np.testing.assert_array_equal(st[:, 1], np.float32(xs)[src])
+    np.testing.assert_array_equal(st[:, 2], np.float32(ys)[src])
+    np.testing.assert_array_equal(st[:, 3], 50.0)
+
+
+def test_fluence_value_multiplies_the_weight(oracle_lib):
+    """w' = wt x fluence x g (Sec. 2.4 with Eq. 4): with a map of
+    non-uniform values the accepted weight is the product with the value
+    of the pixel the ray crosses at the SAD plane (nearest pixel, found by
+    exact arithmetic here)."""
+    ps = S.phase_space(3000, 77, 20.0, S.Z_PSL)
+    rng = np.random.default_rng(3)
+    ps.wt[:] = rng.uniform(0.5, 2.0, ps.n).astype(np.float32)
+    ph = S.water_phantom((16, 16, 16), 4.0, (-32.0, -32.0, 100.0))
+    geom = oracle_lib.geometry(ph, z_psl=S.Z_PSL)
+    fl = rng.uniform(0.05, 1.0, (20, 20)).astype(np.float32)
+    f = S.Field(-10, 10, -10, 10, fluence=fl)
+    r = oracle_lib.stream_sample(f, geom, ps, S.log_edges(0.1, 6.0, 2),
+                                 2000, 0, 5, 100, method=2)
+    ok = r["status"] == 1
+    assert ok.sum() > 80
+    zp, sad = Fr(S.Z_PSL), Fr(100.0)
+    g = ps.n / 2000
+    for st, p in zip(r["state"][ok], r["src"][ok]):
+        xs = Fr(float(ps.x[p])) + Fr(float(ps.u[p])) / Fr(float(ps.w[p])) \
+            * (sad - zp)
+        ys = Fr(float(ps.y[p])) + Fr(float(ps.v[p])) / Fr(float(ps.w[p])) \
+            * (sad - zp)
+        ix = math.floor((xs - Fr(f.f_x0)) / Fr(f.f_pix))
+        iy = math.floor((ys - Fr(f.f_y0)) / Fr(f.f_pix))
+        want = float(ps.wt[p]) * float(fl[iy, ix]) * g
+        assert st[7] == want

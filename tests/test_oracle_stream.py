@@ -215,3 +215,20 @@ def test_stream_weight_and_state_geometry(oracle_lib):
         tt = (dp * d1).sum(1)
         assert np.all(tt >= -1e-9)
         np.testing.assert_allclose(dp, tt[:, None] * d1, atol=1e-9)
+
+
+def test_stream_energy_on_an_edge_joins_the_upper_bin(oracle_lib):
+    """Energy bins are closed below: a particle whose energy equals an
+    interior edge e_k joins bin k (the largest k with E >= e_k)."""
+    ps, geom = _setup(oracle_lib, n=800, seed=53)
+    e_edges = S.log_edges(0.1, 6.0, 5)
+    ps.E[:] = e_edges[1:5][np.arange(ps.n) % 4]
+    out = oracle_lib.stream_sample(S.square_field(30.0), geom, ps, e_edges,
+                                   ps.n, 0, 2, 10 ** 6, method=1)
+    seq, E, t = out["seq"], out["state"][:, 0], out["type"]
+    assert len(seq) == ps.n
+    n_e = len(e_edges) - 1
+    for b, c, _, first in _flush_list(out):
+        part = seq[first:first + c]
+        assert np.all(t[part] == b // n_e)
+        assert np.all(E[part].astype(np.float32) == e_edges[b % n_e])

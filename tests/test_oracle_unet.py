@@ -103,3 +103,24 @@ def test_layout_roundtrip_and_size():
         L.unet_param_count.restype = ctypes.c_int64
         L.unet_param_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
         assert L.unet_param_count(4, 16) == blob.size
+
+
+def test_forward_with_zero_kernels_is_residual_plus_head():
+    """With every convolution kernel zero each layer outputs ReLU of its
+    bias, whatever its input, so the network's output is the input dose
+    plus the head applied to ReLU(b_dec0b), in the units of the dose
+    normalised by its maximum (per sample) and scaled back: out = dose +
+    max(dose) (relu(b_dec0b) . w_head + b_head)."""
+    rng = np.random.default_rng(7)
+    P = {}
+    for name, (ci, co) in U.layer_shapes().items():
+        P[name] = (np.zeros((co, 27, ci)), rng.normal(0, 1.0, co))
+    wh, bh = rng.normal(0, 0.3, 16), 0.05
+    P["head"] = (wh, bh)
+    dose = rng.random((2, 8, 8, 8)) * np.array([3.0, 0.5])[:, None, None,
+                                                            None] + 0.01
+    rho = rng.uniform(0.2, 1.9, dose.shape)
+    out = U.forward(P, dose, rho)
+    mx = dose.reshape(2, -1).max(1)[:, None, None, None]
+    want = dose + mx * (np.maximum(P["dec0b"][1], 0.0) @ wh + bh)
+    np.testing.assert_allclose(out, want, rtol=1e-13, atol=1e-15)
