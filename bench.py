@@ -724,6 +724,10 @@ def main():
               "time_to_1pct_s", "mean_rel_sigma_50pct",
               "reference_point_dose"):
         out[k] = rec[k]
+    # histories that passed the jaws and reached the phantom, per second
+    bs = rec["batch_stats"]
+    out["accepted_histories_per_s"] = rec["histories_per_s"] * (
+        bs["photons"] + bs["electrons"]) / max(1, bs["histories"])
     if not args.no_extras:
         extras(out, eng, rec)
     del eng
