@@ -233,8 +233,20 @@ __device__ __forceinline__ bool claim_items(uint32_t *ctr, int64_t n,
 // energy bucket and tags each chunk it claims with that bucket, so the
 // secondaries arrive already bucketed: listing the chunks of each bucket
 // replaces moving the particles.
+// A secondary in the pool: one 48-byte record, written with three 16-byte
+// stores by the lane that creates it and read back the same way, so that
+// the lines of a partly filled chunk hold whole records instead of a few
+// values of ten separate columns.
+struct alignas(16) SecRec {
+    float E, x, y, z, u, v, w, wt;
+    uint64_t uid;
+    uint32_t ctr, pad;
+};
+static_assert(sizeof(SecRec) == 48, "three 16-byte stores");
+
 struct SecStream {
-    Slots s;
+    Slots s;                 // s.code and s.p.capacity (records in rec)
+    SecRec *rec;
     int64_t n_chunks;
     uint32_t *chunk_ctr;     // kParts counters, kPartStride apart
     uint32_t *chunks_used;   // number of chunks claimed (max index + 1),
@@ -495,12 +507,14 @@ k_photons(psl_particles ph, const uint32_t *__restrict__ counts,
             sec_reserve(sec, cb, cf, sec_part, sec_tried, push_e, b);
         if (push_e) {
             if (slot >= 0) {
-                const Slots &S = sec.s;
-                S.p.E[slot] = Te; S.p.x[slot] = x; S.p.y[slot] = y;
-                S.p.z[slot] = z; S.p.u[slot] = eu; S.p.v[slot] = ev;
-                S.p.w[slot] = ew; S.p.wt[slot] = wt; S.p.uid[slot] = uid;
-                S.p.ctr[slot] = birth;
-                S.code[slot] = (uint8_t)(1 + b);
+                SecRec r;
+                r.E = Te; r.x = x; r.y = y; r.z = z;
+                r.u = eu; r.v = ev; r.w = ew; r.wt = wt;
+                r.uid = uid; r.ctr = birth; r.pad = 0u;
+                const uint4 *q = reinterpret_cast<const uint4 *>(&r);
+                uint4 *d = reinterpret_cast<uint4 *>(sec.rec + slot);
+                d[0] = q[0]; d[1] = q[1]; d[2] = q[2];
+                sec.s.code[slot] = (uint8_t)(1 + b);
                 ++c_sec;
             } else {
                 ++c_lost;
@@ -529,6 +543,7 @@ struct ElWork {
     int64_t cap_b;
     const uint32_t *counts;
     Slots sec;                  // secondary chunk pool (code kEmpty: hole)
+    const SecRec *rec;          // its records
     const uint32_t *sec_chunks; // chunks used in the pool
     // bucketed: per bucket, the pool chunks tagged with it (list_off[b],
     // list_cnt[b] into list); otherwise the pool in claim order
@@ -626,16 +641,21 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                 int64_t t = it;
                 int sgi = 0;
                 while (t >= s_cnt[sgi]) { t -= s_cnt[sgi]; ++sgi; }
-                const psl_particles *src;
                 int64_t i;
                 bool ok = true;
+                uint64_t p_uid = 0;
+                uint32_t p_ctr = 0;
                 const bool dense = W.bucketed ? sgi % 2 == 0 : sgi < W.n_b;
                 if (dense) {
                     const int b = W.n_b - 1 - (W.bucketed ? sgi / 2 : sgi);
-                    src = &W.el;
                     i = (int64_t)b * W.cap_b + t;
+                    T = W.el.E[i];
+                    x = W.el.x[i]; y = W.el.y[i]; z = W.el.z[i];
+                    u = W.el.u[i]; v = W.el.v[i]; w = W.el.w[i];
+                    wt = W.el.wt[i];
+                    p_uid = W.el.uid[i];
+                    p_ctr = W.el.ctr[i];
                 } else {
-                    src = &W.sec.p;
                     if (W.bucketed) {
                         const int b = W.n_b - 1 - sgi / 2;
                         i = (int64_t)W.list[W.list_off[b] + t / 64] * 64 +
@@ -644,12 +664,23 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                         i = t;
                     }
                     ok = W.sec.code[i] != kEmpty;
+                    if (ok) {
+                        const uint4 *q =
+                            reinterpret_cast<const uint4 *>(W.rec + i);
+                        const uint4 a = q[0], bq = q[1], cq = q[2];
+                        T = __uint_as_float(a.x);
+                        x = __uint_as_float(a.y);
+                        y = __uint_as_float(a.z);
+                        z = __uint_as_float(a.w);
+                        u = __uint_as_float(bq.x);
+                        v = __uint_as_float(bq.y);
+                        w = __uint_as_float(bq.z);
+                        wt = __uint_as_float(bq.w);
+                        p_uid = (uint64_t)cq.x | ((uint64_t)cq.y << 32);
+                        p_ctr = cq.z;
+                    }
                 }
                 if (ok) {
-                    T = src->E[i];
-                    x = src->x[i]; y = src->y[i]; z = src->z[i];
-                    u = src->u[i]; v = src->v[i]; w = src->w[i];
-                    wt = src->wt[i];
                     // entry voxel; a point on the box surface belongs to
                     // the voxel inside
                     ix = (int)floorf((x - P.x0) * P.ix_);
@@ -667,8 +698,7 @@ k_electrons(ElWork W, PhDev P, PhysDev Y, const float *__restrict__ tables,
                         if (T <= Y.t_cut) {
                             tally<MODE>(acc, vox, T, wt, scale, c_dep);
                         } else {
-                            rng.init(seed, src->uid[i], src->ctr[i],
-                                     kElectronTag, 0u);
+                            rng.init(seed, p_uid, p_ctr, kElectronTag, 0u);
                             r = lerp_tab(s_rng, kTabRange,
                                          (__logf(T) - H.rng_lnT0) *
                                              H.rng_inv_dlnT);
@@ -962,17 +992,9 @@ TransportWs carve_transport(void *base, int64_t ph_cap) {
                            (int64_t)kMaxGridBlocks * (kBlock / 64);
     const int64_t n = chunks * 64;
     w.sec.n_chunks = chunks;
+    w.sec.s.p = psl_particles{};
     w.sec.s.p.capacity = n;
-    w.sec.s.p.E = c.take<float>(n);
-    w.sec.s.p.x = c.take<float>(n);
-    w.sec.s.p.y = c.take<float>(n);
-    w.sec.s.p.z = c.take<float>(n);
-    w.sec.s.p.u = c.take<float>(n);
-    w.sec.s.p.v = c.take<float>(n);
-    w.sec.s.p.w = c.take<float>(n);
-    w.sec.s.p.wt = c.take<float>(n);
-    w.sec.s.p.uid = c.take<uint64_t>(n);
-    w.sec.s.p.ctr = c.take<uint32_t>(n);
+    w.sec.rec = c.take<SecRec>(n);
     w.sec.s.code = c.take<uint8_t>(n);   // n is a multiple of 64
     w.sec.chunk_bucket = c.take<uint8_t>(chunks);
     w.list = c.take<int32_t>(chunks);
@@ -1166,8 +1188,8 @@ extern "C" psl_status transport_batch(psl_queue *q, const psl_phantom *ph,
     hipLaunchKernelGGL(k_chunks_used, dim3(1), dim3(kParts), 0, st,
                        w.sec.chunk_ctr, w.sec.n_chunks, w.sec.chunks_used);
     ElWork ew{q->el,   q->n_ebuckets, cap_b,      q->d_counts, w.sec.s,
-              w.sec.chunks_used, L.rebucket, w.list, w.list_off,
-              w.list_cnt};
+              w.sec.rec, w.sec.chunks_used, L.rebucket, w.list,
+              w.list_off, w.list_cnt};
     if (L.rebucket) {
         ProfScope prof(PSL_PROF_REBUCKET, st);
         hipLaunchKernelGGL(k_bucket_count, dim3(kParts), dim3(256), 0, st,
