@@ -229,8 +229,11 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
     // lanes search on their own only where a chunk straddles ranges.
     const int lane = __lane_id();
     const int64_t n_waves = (int64_t)gridDim.x * (kSampleBlock / 64);
+    // the wave index, and so the chunk bounds, the range search and all
+    // that depends on a chunk's range alone, are wave-uniform (scalar
+    // registers and scalar loads)
     const int64_t wave_g = (int64_t)blockIdx.x * (kSampleBlock / 64) +
-                           (threadIdx.x >> 6);
+                           __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t n_chunks = (n_slots + 63) / 64;
     const int64_t per_wave = (n_chunks + n_waves - 1) / n_waves;
     const int64_t ch_end = min(n_chunks, (wave_g + 1) * per_wave);
@@ -248,9 +251,34 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
         uint8_t code = kEmpty;
         if (h0 < h_total) {
             st.add(PSL_STAT(histories), 1);
-            // range containing h0: last idx with H[idx] <= h0
-            int64_t idx = lo;
-            if (hi != lo) {
+            // range containing h0 (last idx with H[idx] <= h0) and the
+            // particle it reads: p = off[k] + (s_k + c + r) mod n_k with
+            // r = h0 - H[idx], c = batch * T[k] + before[idx]
+            int64_t idx, p;
+            if (hi == lo) {
+                // one range for the whole chunk: r advances by one per
+                // lane from the chunk's first history, so the residue is
+                // taken once and each lane adds its offset
+                idx = lo;
+                const int64_t k = lo % n_keys;
+                const int64_t o0 = off[k];
+                const uint64_t nk = (uint64_t)(off[k + 1] - o0);
+                const uint64_t s0 = splitmix64(seed ^ (uint64_t)k) % nk +
+                                    (uint64_t)batch * (uint64_t)T[k] +
+                                    (uint64_t)before[lo] +
+                                    (uint64_t)(hf - H[lo]);
+                const uint64_t l = (uint64_t)lane;
+                uint64_t j;
+                if (s0 > ~0ull - 63) {            // the sum wraps 2^64
+                    j = (s0 + l) % nk;
+                } else if (nk >= 64) {
+                    j = s0 % nk + l;
+                    if (j >= nk) j -= nk;
+                } else {
+                    j = (uint32_t)(s0 % nk + l) % (uint32_t)nk;
+                }
+                p = o0 + (int64_t)j;
+            } else {
                 // H[a0] <= h0 < H[b0] (b0 <= n_ranges; only H[mid], mid <
                 // b0, is read)
                 int64_t a0 = lo, b0 = hi + 1;
@@ -259,24 +287,35 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
                     if (H[mid] <= h0) a0 = mid; else b0 = mid;
                 }
                 idx = a0;
+                const int64_t k = idx % n_keys;
+                const int64_t r = h0 - H[idx];
+                const uint64_t nk = (uint64_t)(off[k + 1] - off[k]);
+                const uint64_t sk = splitmix64(seed ^ (uint64_t)k) % nk;
+                const uint64_t c = (uint64_t)batch * (uint64_t)T[k] +
+                                   (uint64_t)before[idx];
+                p = off[k] + (int64_t)((sk + c + (uint64_t)r) % nk);
             }
             const int f = (int)(idx / n_keys);
-            const int64_t k = idx % n_keys;
-            const int64_t r = h0 - H[idx];
-            const uint64_t nk = (uint64_t)(off[k + 1] - off[k]);
-            const uint64_t sk = splitmix64(seed ^ (uint64_t)k) % nk;
-            const uint64_t c = (uint64_t)batch * (uint64_t)T[k] +
-                               (uint64_t)before[idx];
-            const int64_t p = off[k] + (int64_t)((sk + c + (uint64_t)r) % nk);
-            const FieldDev F = fields[f];
             const uint8_t type = ps.type[p];
-            double o[7];
-            const int status = beam_model(F, geo, ps.x[p], ps.y[p], ps.u[p],
-                                          ps.v[p], ps.w[p], ps.wt[p], g[idx],
-                                          o);
+            const float px = ps.x[p], py = ps.y[p], pu = ps.u[p],
+                        pv = ps.v[p], pw = ps.w[p], pwt = ps.wt[p];
+            const double gi = g[idx];
+            // the beam model with its field's constants in scalar
+            // registers, once per distinct field among the lanes (one,
+            // except where a chunk crosses into the next field)
+            float o[7];
+            int status = 0;
+            for (uint64_t pend = __ballot(1); pend;) {
+                const int fl = __builtin_amdgcn_readlane(
+                    f, (int)__builtin_ctzll(pend));
+                if (f == fl)
+                    status = beam_model(fields[fl], geo, px, py, pu, pv, pw,
+                                        pwt, gi, o);
+                pend &= ~__ballot(f == fl);
+            }
             if (status == 1) {
                 const float oE = ps.E[p];
-                const float owt = (float)o[6];
+                const float owt = o[6];
                 int which = 0;
                 if (type != 0) {
                     int b = 0;
@@ -287,12 +326,12 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
                 const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
                                      (uint64_t)h0;
                 slots.p.E[h0] = oE;
-                slots.p.x[h0] = (float)o[0];
-                slots.p.y[h0] = (float)o[1];
-                slots.p.z[h0] = (float)o[2];
-                slots.p.u[h0] = (float)o[3];
-                slots.p.v[h0] = (float)o[4];
-                slots.p.w[h0] = (float)o[5];
+                slots.p.x[h0] = o[0];
+                slots.p.y[h0] = o[1];
+                slots.p.z[h0] = o[2];
+                slots.p.u[h0] = o[3];
+                slots.p.v[h0] = o[4];
+                slots.p.w[h0] = o[5];
                 slots.p.wt[h0] = owt;
                 slots.p.uid[h0] = uid;
                 slots.p.ctr[h0] = which ? kSourceElectronCtr : 0u;

@@ -48,12 +48,13 @@ struct Geo {
 // the map or zero rejects), w' = wt * fluence * g, the gantry rotation about
 // +y through the isocentre and the straight move onto the phantom box.
 // Returns 0 jaw-rejected, 1 accepted, 2 zero fluence, 3 misses the phantom;
-// on acceptance o = x y z u v w w'.  Double precision, no contraction, so
-// every decision is reproducible operation by operation.
+// on acceptance o = x y z u v w w', each rounded to float from its double
+// value.  Double precision, no contraction, so every decision is
+// reproducible operation by operation.
 __device__ __forceinline__ int beam_model(const FieldDev &F, const Geo &geo,
                                           float fx_, float fy_, float fu,
                                           float fv, float fw, float fwt,
-                                          double g, double o[7]) {
+                                          double g, float o[7]) {
 #pragma clang fp contract(off)
     const double px = fx_, py = fy_, pz = geo.z_psl;
     const double du = fu, dv = fv, dw = fw;
@@ -127,13 +128,13 @@ __device__ __forceinline__ int beam_model(const FieldDev &F, const Geo &geo,
     }
     if (miss || tn > tf || tf <= 0.0) return 3;
     const double t = tn > 0.0 ? tn : 0.0;
-    o[0] = pos[0] + t * dir[0];
-    o[1] = pos[1] + t * dir[1];
-    o[2] = pos[2] + t * dir[2];
-    o[3] = eu;
-    o[4] = ev;
-    o[5] = ew;
-    o[6] = wgt;
+    o[0] = (float)(pos[0] + t * dir[0]);
+    o[1] = (float)(pos[1] + t * dir[1]);
+    o[2] = (float)(pos[2] + t * dir[2]);
+    o[3] = (float)eu;
+    o[4] = (float)ev;
+    o[5] = (float)ew;
+    o[6] = (float)wgt;
     return 1;
 }
 

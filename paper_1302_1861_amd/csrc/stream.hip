@@ -103,7 +103,7 @@ k_stream_classify(StreamArgs A, const float *__restrict__ e_edges,
         if (type > 1u || E != E) {
             st.add(PSL_STAT(dropped), 1);
         } else {
-            double o[7];
+            float o[7];
             const int status = beam_model(A.F, A.geo, A.ps.x[p], A.ps.y[p],
                                           A.ps.u[p], A.ps.v[p], A.ps.w[p],
                                           A.ps.wt[p], A.g, o);
@@ -111,7 +111,7 @@ k_stream_classify(StreamArgs A, const float *__restrict__ e_edges,
                 code = type * (uint32_t)A.n_e +
                        (uint32_t)energy_bin(E, s_e, A.n_e);
                 st.add(type ? PSL_STAT(electrons) : PSL_STAT(photons), 1);
-                st.addf(PSL_STAT(e_in), (double)E * (double)(float)o[6]);
+                st.addf(PSL_STAT(e_in), (double)E * (double)o[6]);
             } else if (status == 0) {
                 st.add(PSL_STAT(jaw_rejected), 1);
             } else if (status == 2) {
@@ -244,7 +244,7 @@ k_stream_place(StreamArgs A, const uint32_t *__restrict__ keys,
         const int64_t seq = first[f] + rank % cap;
         const uint32_t r = idx[j];
         const int64_t p = file_pos(A, r);
-        double o[7];
+        float o[7];
         (void)beam_model(A.F, A.geo, A.ps.x[p], A.ps.y[p], A.ps.u[p],
                          A.ps.v[p], A.ps.w[p], A.ps.wt[p], A.g, o);
         const float E = A.ps.E[p];
@@ -256,13 +256,13 @@ k_stream_place(StreamArgs A, const uint32_t *__restrict__ keys,
             which = 1 + q;
         }
         slots.p.E[seq] = E;
-        slots.p.x[seq] = (float)o[0];
-        slots.p.y[seq] = (float)o[1];
-        slots.p.z[seq] = (float)o[2];
-        slots.p.u[seq] = (float)o[3];
-        slots.p.v[seq] = (float)o[4];
-        slots.p.w[seq] = (float)o[5];
-        slots.p.wt[seq] = (float)o[6];
+        slots.p.x[seq] = o[0];
+        slots.p.y[seq] = o[1];
+        slots.p.z[seq] = o[2];
+        slots.p.u[seq] = o[3];
+        slots.p.v[seq] = o[4];
+        slots.p.w[seq] = o[5];
+        slots.p.wt[seq] = o[6];
         slots.p.uid[seq] = uid0 + r;
         slots.p.ctr[seq] = which ? kSourceElectronCtr : 0u;
         slots.code[seq] = (uint8_t)which;

@@ -130,7 +130,7 @@ def _check_sample_engine(eng, wl, hpb, batches=(0,), iso=(0.0, 0.0, 100.0)):
         assert st["electrons"] == len(want_el) == len(el["E"])
         for q, want, ctr in ((ph, want_ph, 0), (el, want_el, 0xFFFFFFFF)):
             uid = q["uid"].view(np.uint64)
-            h = uid - np.uint64(b) * np.uint64(n_hist)
+            h = uid - np.uint64((b * n_hist) % 2 ** 64)
             order = np.argsort(h)
             h = h[order]
             np.testing.assert_array_equal(h.astype(np.int64), want)
@@ -202,6 +202,17 @@ def test_sample_empty_first_range_with_dirty_workspace(fill):
     eng = P.Engine(wl, histories_per_batch=n)
     eng.ws_sample.fill_(fill)
     _check_sample_engine(eng, wl, n, (0, 1))
+
+
+def test_sample_batch_indices_where_the_read_offset_wraps():
+    """Batch indices near 2^62 and 2^63: the count of particles read before
+    (batch * T_k + before) and the history uid wrap modulo 2^64 on both
+    sides; ranges that fill whole 64-history chunks and chunks that
+    straddle ranges and fields (a two-field plan) both read through it."""
+    wl = S.workload_imrt(n_particles=300_000)
+    wl.fields = wl.fields[:2]
+    _check_sample(wl, 700_001, batches=(2 ** 62 + 12_345, 2 ** 63 - 2),
+                  iso=(0.0, 0.0, 100.0))
 
 
 def test_sample_full_clinical_batch():
