@@ -680,7 +680,9 @@ k_conv3_bk16p(const bf16_t *__restrict__ x, Vol V, int Cin,
 // DIRECT: the words are made here from the fp32 dose (times the sample's
 // scale) and density, rounded exactly as k_pack_input rounds them, so the
 // padded input need not be written at all (inference); otherwise they are
-// read from the padded input x.
+// read from the padded input x.  Each block walks bricks as k_conv3_bk16p
+// does (the blocks of one XCD on one contiguous share of them), with the
+// next brick's halo loaded into registers while the current one computes.
 template <bool DIRECT>
 __global__ void __launch_bounds__(256)
 k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
@@ -696,12 +698,15 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
     __shared__ __attribute__((aligned(16))) bf16_t s_out[4 * ROWS * 16 * 24];
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const int nxb = V.w / 16, nyb = V.h / kBY, nzb = V.d / kBZ;
-    int64_t b = blockIdx.x;
-    const int bx = (int)(b % nxb); b /= nxb;
-    const int by = (int)(b % nyb); b /= nyb;
-    const int bz = (int)(b % nzb);
-    const int64_t bn = b / nzb;
-    const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
+    const int nbr = nxb * nyb * nzb * V.n;     // < 2^31 (grid limit)
+    int br = blockIdx.x, br_end = nbr, br_step = gridDim.x;
+    if (nbr > (int)gridDim.x && gridDim.x >= 8) {
+        const int k = blockIdx.x & 7, per = (nbr + 7) / 8;
+        br = k * per + (blockIdx.x >> 3);
+        br_end = min(nbr, (k + 1) * per);
+        br_step = ((int)gridDim.x - k + 7) / 8;
+    }
+    if (br >= br_end) return;
     const int q = lane >> 4, vx = lane & 15;
     for (int i = threadIdx.x; i < C * KS; i += 256) {
         const int co = i / KS, k = i % KS;
@@ -709,59 +714,90 @@ k_conv3_first(const bf16_t *__restrict__ x, const float *__restrict__ dose,
                         : (bf16_t)0;
     }
     constexpr int NIT = (HVOX + 255) / 256;
+    // the prefetched halo as loaded (DIRECT: dose and density, rounded
+    // when staged, so that no conversion waits for the loads in flight)
     uint32_t hval[NIT];
+    float hdose[NIT], hrho[NIT], hsc = 0.0f;
+    auto fetch = [&](int bb) {
+        const int bx = bb % nxb; bb /= nxb;
+        const int by = bb % nyb; bb /= nyb;
+        const int bz = bb % nzb;
+        const int64_t bn = bb / nzb;
+        const int x0 = bx * 16, y0 = by * kBY, z0 = bz * kBZ;
+        if (DIRECT) hsc = scale[bn];
 #pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int i = threadIdx.x + 256 * it;
-        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
-        hval[it] = 0u;
-        if (i < HVOX && (unsigned)zz < (unsigned)V.d &&
-            (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w) {
-            const int64_t v = ((bn * V.d + zz) * V.h + yy) * V.w + xx;
-            if (DIRECT)
-                hval[it] = (uint32_t)f2bf(dose[v] * scale[bn]) |
-                           ((uint32_t)f2bf(rho[v]) << 16);
-            else
-                hval[it] = *reinterpret_cast<const uint32_t *>(x + v * Cin);
-        }
-    }
-#pragma unroll
-    for (int it = 0; it < NIT; ++it) {
-        const int i = threadIdx.x + 256 * it;
-        if (i < HVOX) s_in[i] = hval[it];
-    }
-    __syncthreads();
-    f32x4 acc[ROWS][1];
-#pragma unroll
-    for (int t = 0; t < ROWS; ++t) acc[t][0] = f32x4{0, 0, 0, 0};
-#pragma unroll
-    for (int st = 0; st < 2; ++st) {
-        const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
-            s_w + vx * KS + 32 * st + 8 * q);
-#pragma unroll
-        for (int t = 0; t < ROWS; ++t) {
-            const int row = wid * ROWS + t;
-            const int rz = row / kBY, ry = row % kBY;
-            uint32_t w4[4];
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-                const int o = 16 * st + 4 * q + jj;
-                const int oc = o < 27 ? o : 0;
-                const int dz = oc / 9, dy = (oc / 3) % 3, dx = oc % 3;
-                const uint32_t v =
-                    s_in[((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)];
-                w4[jj] = o < 27 ? v : 0u;
+        for (int it = 0; it < NIT; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+            const int zz = z0 + hz - 1, yy = y0 + hy - 1, xx = x0 + hx - 1;
+            hval[it] = 0u;
+            hdose[it] = 0.0f;
+            hrho[it] = 0.0f;
+            if (i < HVOX && (unsigned)zz < (unsigned)V.d &&
+                (unsigned)yy < (unsigned)V.h && (unsigned)xx < (unsigned)V.w) {
+                const int64_t v = ((bn * V.d + zz) * V.h + yy) * V.w + xx;
+                if (DIRECT) {
+                    hdose[it] = dose[v];
+                    hrho[it] = rho[v];
+                } else {
+                    hval[it] =
+                        *reinterpret_cast<const uint32_t *>(x + v * Cin);
+                }
             }
-            const bf16x8 a = __builtin_bit_cast(
-                bf16x8, make_uint4(w4[0], w4[1], w4[2], w4[3]));
-            acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                a, wv, acc[t][0], 0, 0, 0);
         }
+    };
+    fetch(br);
+    for (;;) {
+        __syncthreads();   // the last brick's reads of s_in are done
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = threadIdx.x + 256 * it;
+            if (i < HVOX)
+                s_in[i] = DIRECT ? (uint32_t)f2bf(hdose[it] * hsc) |
+                                       ((uint32_t)f2bf(hrho[it]) << 16)
+                                 : hval[it];
+        }
+        __syncthreads();
+        const int nb2 = br + br_step;
+        const bool more = nb2 < br_end;
+        if (more) fetch(nb2);                  // in flight during the steps
+        f32x4 acc[ROWS][1];
+#pragma unroll
+        for (int t = 0; t < ROWS; ++t) acc[t][0] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const bf16x8 wv = *reinterpret_cast<const bf16x8 *>(
+                s_w + vx * KS + 32 * st + 8 * q);
+#pragma unroll
+            for (int t = 0; t < ROWS; ++t) {
+                const int row = wid * ROWS + t;
+                const int rz = row / kBY, ry = row % kBY;
+                uint32_t w4[4];
+#pragma unroll
+                for (int jj = 0; jj < 4; ++jj) {
+                    const int o = 16 * st + 4 * q + jj;
+                    const int oc = o < 27 ? o : 0;
+                    const int dz = oc / 9, dy = (oc / 3) % 3, dx = oc % 3;
+                    const uint32_t v =
+                        s_in[((rz + dz) * HY + (ry + dy)) * HX + (vx + dx)];
+                    w4[jj] = o < 27 ? v : 0u;
+                }
+                const bf16x8 a = __builtin_bit_cast(
+                    bf16x8, make_uint4(w4[0], w4[1], w4[2], w4[3]));
+                acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a, wv, acc[t][0], 0, 0, 0);
+            }
+        }
+        int bb = br;
+        const int x0 = (bb % nxb) * 16; bb /= nxb;
+        const int y0 = (bb % nyb) * kBY; bb /= nyb;
+        const int z0 = (bb % nzb) * kBZ;
+        const int64_t bn = bb / nzb;
+        store_tiles<ROWS, 1>(acc, s_out, wid, lane, bn, z0, y0, x0, V, 0,
+                             bias, 1, nullptr, y, C);
+        if (!more) break;
+        br = nb2;
     }
-    __syncthreads();                           // the tables are free
-    store_tiles<ROWS, 1>(acc, s_out, wid, lane, bn, z0, y0, x0, V, 0, bias,
-                         1, nullptr, y, C);
 }
 
 // W'[ci][o'][co] = W[co][26 - o'][ci]: the weights of the transposed
@@ -1758,8 +1794,21 @@ psl_status forward(const Ctx &c, const Acts &a, const float *dose,
     for (int l = 0; l < 4; ++l) {
         const ConvL &la = L[2 * l], &lb = L[2 * l + 1];
         if (l == 0 && first_bk) {
-            // the input's two real channels only
-            const dim3 grid((unsigned)(V[0].voxels() / (16 * kBY * kBZ)));
+            // the input's two real channels only; as many blocks as are
+            // resident at once, each walking bricks
+            static const int per_cu = [] {
+                int n = 0;
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &n, k_conv3_first<true>, 256, 0) != hipSuccess ||
+                    n < 1)
+                    n = 1;
+                return n;
+            }();
+            int64_t cap = (int64_t)per_cu * device_cu_count();
+            const int lim = g_brick_blocks.load(std::memory_order_relaxed);
+            if (lim > 0) cap = std::min<int64_t>(cap, lim);
+            const dim3 grid((unsigned)std::min<int64_t>(
+                V[0].voxels() / (16 * kBY * kBZ), cap));
             if (train)
                 hipLaunchKernelGGL(k_conv3_first<false>, grid, dim3(256), 0,
                                    c.st, ins[0], dose, rho, a.scale, V[0],
