@@ -85,16 +85,6 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).
 struct u32x4 { uint32_t x, y, z, w; };
 
-// High 32 bits of a 32 x 32-bit product (the host build serves the
-// known-answer test of the generator).
-__host__ __device__ __forceinline__ uint32_t mulhi32(uint32_t a, uint32_t b) {
-#if defined(__HIP_DEVICE_COMPILE__)
-    return __umulhi(a, b);
-#else
-    return (uint32_t)(((uint64_t)a * b) >> 32);
-#endif
-}
-
 __host__ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c,
                                                         uint32_t k0,
                                                         uint32_t k1) {
@@ -102,10 +92,11 @@ __host__ __device__ __forceinline__ u32x4 philox4x32_10(u32x4 c,
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        // separate high and low multiplies: one 64-bit multiply-add per
-        // product measured slower in the photon kernel
-        const uint32_t hi0 = mulhi32(M0, c.x), lo0 = M0 * c.x;
-        const uint32_t hi1 = mulhi32(M1, c.z), lo1 = M1 * c.z;
+        // each 32 x 32 -> 64-bit product as one multiply-add instruction
+        // (both halves) instead of separate high and low multiplies
+        const uint64_t p0 = (uint64_t)M0 * c.x, p1 = (uint64_t)M1 * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
         k0 += W0;
         k1 += W1;
