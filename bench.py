@@ -363,10 +363,11 @@ def atomic_roofline(P, eng, groups, st, batch, replay=True):
 def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
                      replay=True, source="psl", pipelined=True):
     """Times `steps` batches of H histories of one workload (after
-    `warmup` batches) and derives the rooflines.  pipelined: each batch is
-    sampled on a second stream while the previous one is transported
-    (Engine.run_pipelined; same histories and dose as one batch after
-    another); kernel times are then taken from one more sequential pass.
+    `warmup` batches) and derives the rooflines.  pipelined: three batches
+    in flight on three streams, one batch sampled while the others are
+    transported (Engine.run_pipelined; same histories and dose as one
+    batch after another); kernel times are then taken from one more
+    sequential pass.
     Returns (record, engine)."""
     eng = P.Engine(wl, histories_per_batch=H, launch=launch, source=source)
 
@@ -416,6 +417,7 @@ def measure_workload(P, torch, wl, H, steps, warmup, launch=None,
     sel = d >= 0.5 * d.max()
     sbar = float((s[sel] / d[sel]).mean())
     rec = {"workload": wl.name, "source": source, "pipelined": pipelined,
+           "batches_in_flight": eng.pipeline_depth if pipelined else 1,
            "histories_per_step": H, "steps": steps,
            "histories_per_s": steps * H / elapsed,
            "ms_per_step": 1e3 * elapsed / steps,
@@ -575,8 +577,8 @@ def bench_build(P, torch, S, sizes=(10_000_000, 100_000_000, 500_000_000),
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=6)
     ap.add_argument("--field", type=float, default=10.0)
     ap.add_argument("--histories-per-step", type=int, default=10_000_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)

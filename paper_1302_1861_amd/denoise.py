@@ -108,10 +108,10 @@ class PairMaker:
         return eng
 
     def run(self, eng, seed, batches=10):
-        """Sampling, transport and tally of a prepared engine, two batches
-        in flight (Engine.run_pipelined: the dose of the batches run one
-        after another): dose (Gy per phase-space particle), its batch sigma
-        and the density, device float32 [nz,ny,nx]."""
+        """Sampling, transport and tally of a prepared engine, three
+        batches in flight (Engine.run_pipelined: the dose of the batches run
+        one after another): dose (Gy per phase-space particle), its batch
+        sigma and the density, device float32 [nz,ny,nx]."""
         eng.reset_tally()
         eng.set_seed(seed)
         eng.run_pipelined(0, batches)

@@ -11,7 +11,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("source,depth", [("psl", 2), ("method2", 2),
-                                          ("psl", 3)])
+                                          ("psl", 3), ("method2", 3),
+                                          ("psl", 4)])
 def test_pipelined_batches_equal_sequential(source, depth):
     import torch
     import paper_1302_1861_amd as P
