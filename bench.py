@@ -119,34 +119,35 @@ def unet_forward_flops(shape, base=16, in_c=2):
 
 def bench_imrt(P, S, torch, hpb, n_batches, wl=None):
     """A batched plan (default: the IMRT plan, 7 beams x 20 segments),
-    MU-proportional histories, autotuned, replayed from a hipGraph: two
-    plans of the plan's fields with two batches in flight
-    (psl_plan_run_pair), and one plan alone for comparison."""
+    MU-proportional histories, autotuned: three plans of the plan's fields
+    with three batches in flight on three streams (psl_plan_run_set), and
+    for comparison two of them replaying a pair's hipGraph
+    (psl_plan_run_pair) and one plan's own hipGraph, one batch after
+    another."""
     wl = wl or S.workload_imrt()
     # graph capture needs a created stream (not the legacy null stream)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         eng = P.Engine(wl, histories_per_batch=hpb)   # isocentre at SAD
-        pair = eng.make_plan_pair(stream)
-        plan = pair.a
-        r = pair.autotune(trials=1)
-        pair.run(0, 2, use_graph=True)
-        stream.synchronize()
-        eng.reset_tally()
-        stream.synchronize()
-        # two batches in flight: the pair's graph replayed n / 2 times
-        t0 = time.perf_counter()
-        pair.run(0, n_batches, use_graph=True)
-        stream.synchronize()
-        dt = time.perf_counter() - t0
-        # one plan's own graph, one batch after another
-        eng.reset_tally()
-        plan.run(0, 2, use_graph=True)
-        stream.synchronize()
-        t0 = time.perf_counter()
-        plan.run(0, n_batches, use_graph=True)
-        stream.synchronize()
-        dt_single = time.perf_counter() - t0
+        pset = eng.make_plan_set(3, stream)
+        plan = pset.plans[0]
+        pair = P.PlanPair(pset.plans[0], pset.plans[1])
+        r = pset.autotune(trials=1)
+
+        def timed(run):
+            eng.reset_tally()
+            run(0, 3)
+            stream.synchronize()
+            eng.reset_tally()
+            stream.synchronize()
+            t0 = time.perf_counter()
+            run(0, n_batches)
+            stream.synchronize()
+            return time.perf_counter() - t0
+
+        dt = timed(lambda f, n: pset.run(f, n))
+        dt_pair = timed(lambda f, n: pair.run(f, n, use_graph=True))
+        dt_single = timed(lambda f, n: plan.run(f, n, use_graph=True))
         # kernel times of one batch run eagerly (the graph replays the same
         # launches; events are not recorded inside a captured graph)
         P.profile_read(reset=True)
@@ -158,16 +159,20 @@ def bench_imrt(P, S, torch, hpb, n_batches, wl=None):
     st = eng.stats_dict()
     roof = hbm_roofline(groups, st, eng.nvox)
     atom = atomic_roofline(P, eng, groups, st, 0, replay=False)
-    pair.destroy()
+    pset.destroy()
     return {"workload": "%s: %d fields, MU-proportional, 128^3 water at "
                         "2.5 mm, %d batches of %d histories"
                         % (wl.name, len(wl.fields), n_batches, hpb),
             "histories": n_batches * hpb, "seconds": dt,
             "histories_per_s": n_batches * hpb / dt,
-            "ms_per_batch": 1e3 * dt / n_batches, "graph": True,
-            "in_flight": 2,
+            "ms_per_batch": 1e3 * dt / n_batches, "graph": False,
+            "in_flight": 3,
+            "pair_graph": {"histories_per_s": n_batches * hpb / dt_pair,
+                           "ms_per_batch": 1e3 * dt_pair / n_batches,
+                           "in_flight": 2},
             "single_plan": {"histories_per_s": n_batches * hpb / dt_single,
-                            "ms_per_batch": 1e3 * dt_single / n_batches},
+                            "ms_per_batch": 1e3 * dt_single / n_batches,
+                            "graph": True},
             "tuned": {"blocks_per_cu": r.launch.blocks_per_cu,
                       "rebucket": r.launch.rebucket,
                       "n_ebuckets": r.n_ebuckets,

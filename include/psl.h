@@ -618,6 +618,27 @@ psl_status psl_plan_get(const psl_plan *p, psl_queue *q, psl_launch *launch);
 psl_status psl_plan_run_pair(psl_plan *a, psl_plan *b, int64_t first_batch,
                              int32_t n_batches, int32_t use_graph,
                              void *stream);
+/*
+ * psl_plan_run_set - batches first_batch .. first_batch + n_batches - 1 of
+ * one job (Sec. 2.3.3, 2.4: many fields sharing one phase space, batch
+ * after batch) over n_plans plans of the same fields, 1 <= n_plans <= 8,
+ * any two of which meet psl_plan_run_pair's requirements (the same
+ * d_s1/d_s2 and accumulator mode, their own queues, accumulator,
+ * statistics and workspace): batch first + i runs on plans[i mod n_plans],
+ * plans[0] on `stream` and each other plan on a stream it holds, so that
+ * n_plans batches are in flight at once (one sampled while others are
+ * transported); with more than one plan each transport runs with half its
+ * plan's blocks per CU.  The folds keep batch order.  Enqueued eagerly (no
+ * graph); `stream` waits for every plan's stream before the call returns,
+ * so work enqueued on it afterwards sees the sums.  The histories and,
+ * with the fixed-point tally, the sums equal those of psl_plan_run over the
+ * same batches.  PSL_EINVAL for a NULL or repeated plan, a count outside
+ * 1..8 or buffers the plans must not share.  Calls on plans of one set
+ * must not overlap.
+ */
+psl_status psl_plan_run_set(psl_plan *const *plans, int32_t n_plans,
+                            int64_t first_batch, int32_t n_batches,
+                            void *stream);
 /* Gives dst the transport launch shape and electron bucketing of src (for
  * example after psl_autotune on src), so that two plans of a pair run the
  * same configuration. */

@@ -38,7 +38,7 @@ EXPORTS = ["psl_last_error", "psl_version", "psl_build_workspace_bytes",
            "psl_profile_read", "psl_bench_atomics_workspace_bytes",
            "psl_bench_atomics", "psl_plan_workspace_bytes", "psl_plan_create",
            "psl_plan_run", "psl_autotune", "psl_plan_get", "psl_plan_destroy",
-           "psl_plan_run_pair", "psl_plan_copy_tuning",
+           "psl_plan_run_pair", "psl_plan_run_set", "psl_plan_copy_tuning",
            "unet_param_count", "unet_workspace_bytes", "unet_init",
            "unet_set_params", "unet_forward", "unet_backward",
            "unet_adam_step", "unet_set_brick_blocks", "dose_denoise",
@@ -254,6 +254,8 @@ def lib():
         L.psl_plan_get.restype = i32
         L.psl_plan_run_pair.argtypes = [vp, vp, i64, i32, i32, vp]
         L.psl_plan_run_pair.restype = i32
+        L.psl_plan_run_set.argtypes = [C.POINTER(vp), i32, i64, i32, vp]
+        L.psl_plan_run_set.restype = i32
         L.psl_plan_copy_tuning.argtypes = [vp, vp]
         L.psl_plan_copy_tuning.restype = i32
         L.psl_plan_destroy.argtypes = [vp]
@@ -575,6 +577,33 @@ class PlanPair:
     def destroy(self):
         self.a.destroy()
         self.b.destroy()
+
+
+class PlanSet:
+    """Plans of the same fields and sums, each with its own queues,
+    accumulator, statistics and workspace: batch i runs on plan i mod n,
+    n batches in flight at once (psl_plan_run_set)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        self.stream = self.plans[0].stream
+
+    def autotune(self, trials=2, stream=None):
+        """Tunes the first plan and gives the others its configuration."""
+        r = self.plans[0].autotune(trials, stream)
+        for p in self.plans[1:]:
+            p.copy_tuning(self.plans[0])
+        return r
+
+    def run(self, first_batch, n_batches, stream=None):
+        h = (C.c_void_p * len(self.plans))(*[p.handle for p in self.plans])
+        _check(lib().psl_plan_run_set(h, len(self.plans), int(first_batch),
+                                      int(n_batches),
+                                      _stream(stream or self.stream)))
+
+    def destroy(self):
+        for p in self.plans:
+            p.destroy()
 
 
 def dose_gamma(ref, ev, voxel, dose_crit=0.02, dta=0.2, threshold=0.1,

@@ -30,7 +30,8 @@ struct psl_plan {
     hipStream_t graph_stream = nullptr;
     // psl_plan_run_pair (held by the pair's first plan): the second plan's
     // stream, the events that order the folds and join the streams, and
-    // the graph of one pair of batches
+    // the graph of one pair of batches; psl_plan_run_set: the plan's own
+    // stream and events
     hipStream_t side = nullptr;
     hipEvent_t ev_a = nullptr, ev_b = nullptr, ev_fork = nullptr;
     hipGraph_t pair_graph = nullptr;
@@ -43,6 +44,8 @@ struct psl_plan {
 
 namespace psl {
 namespace {
+
+constexpr int kMaxPlanSet = 8;   // plans of one psl_plan_run_set
 
 void drop_graph(psl_plan *p) {
     ++p->version;
@@ -106,6 +109,35 @@ psl_status enqueue_pair(psl_plan *a, psl_plan *b, hipStream_t st) {
     if ((s = enqueue_fold(b, 2, sb))) return s;
     PSL_HIP(hipEventRecord(a->ev_b, sb));
     PSL_HIP(hipStreamWaitEvent(st, a->ev_b, 0));
+    return PSL_OK;
+}
+
+// Two plans that run batches of one job side by side: the same sums and
+// accumulator mode, their own queues, accumulators, statistics and
+// workspaces.
+psl_status check_side_by_side(const psl_plan *a, const psl_plan *b) {
+    PSL_REQUIRE(a && b && a != b, "need distinct plans");
+    PSL_REQUIRE(a->s1 == b->s1 && a->s2 == b->s2,
+                "the plans of a pair fold into the same sums");
+    PSL_REQUIRE(a->acc.data != b->acc.data && a->stats != b->stats &&
+                    a->q.d_counts != b->q.d_counts && a->tws != b->tws &&
+                    a->q.ph.E != b->q.ph.E && a->q.el.E != b->q.el.E,
+                "the plans of a pair need their own queues, accumulators, "
+                "statistics and workspaces");
+    PSL_REQUIRE(a->acc.mode == b->acc.mode &&
+                    a->acc.frac_bits == b->acc.frac_bits,
+                "the plans of a pair need the same accumulator mode");
+    return PSL_OK;
+}
+
+// The plan's own stream (default priority) and events, made on first use.
+psl_status ensure_side(psl_plan *a) {
+    if (!a->side) {
+        PSL_HIP(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking));
+        PSL_HIP(hipEventCreateWithFlags(&a->ev_a, hipEventDisableTiming));
+        PSL_HIP(hipEventCreateWithFlags(&a->ev_b, hipEventDisableTiming));
+        PSL_HIP(hipEventCreateWithFlags(&a->ev_fork, hipEventDisableTiming));
+    }
     return PSL_OK;
 }
 
@@ -245,26 +277,12 @@ extern "C" psl_status psl_plan_run_pair(psl_plan *a, psl_plan *b,
                                         void *stream) {
     PSL_REQUIRE(a && b && a != b, "need two distinct plans");
     PSL_REQUIRE(first_batch >= 0 && n_batches >= 0, "bad batch range");
-    PSL_REQUIRE(a->s1 == b->s1 && a->s2 == b->s2,
-                "the plans of a pair fold into the same sums");
-    PSL_REQUIRE(a->acc.data != b->acc.data && a->stats != b->stats &&
-                    a->q.d_counts != b->q.d_counts && a->tws != b->tws &&
-                    a->q.ph.E != b->q.ph.E && a->q.el.E != b->q.el.E,
-                "the plans of a pair need their own queues, accumulators, "
-                "statistics and workspaces");
-    PSL_REQUIRE(a->acc.mode == b->acc.mode &&
-                    a->acc.frac_bits == b->acc.frac_bits,
-                "the plans of a pair need the same accumulator mode");
+    psl_status s;
+    if ((s = check_side_by_side(a, b))) return s;
     hipStream_t st = (hipStream_t)stream;
     PSL_REQUIRE(!use_graph || st != nullptr,
                 "graph capture needs a created stream, not the null stream");
-    psl_status s;
-    if (!a->side) {
-        PSL_HIP(hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking));
-        PSL_HIP(hipEventCreateWithFlags(&a->ev_a, hipEventDisableTiming));
-        PSL_HIP(hipEventCreateWithFlags(&a->ev_b, hipEventDisableTiming));
-        PSL_HIP(hipEventCreateWithFlags(&a->ev_fork, hipEventDisableTiming));
-    }
+    if ((s = ensure_side(a))) return s;
     if ((s = set_i64(a->d_batch, first_batch, st))) return s;
     if ((s = set_i64(b->d_batch, first_batch + 1, st))) return s;
     const int32_t pairs = n_batches / 2;
@@ -313,6 +331,53 @@ extern "C" psl_status psl_plan_run_pair(psl_plan *a, psl_plan *b,
     if (n_batches % 2) {
         // the last batch on a alone (its index is first + 2 pairs)
         if ((s = enqueue_batch(a, st))) return s;
+    }
+    return PSL_OK;
+}
+
+extern "C" psl_status psl_plan_run_set(psl_plan *const *plans,
+                                       int32_t n_plans, int64_t first_batch,
+                                       int32_t n_batches, void *stream) {
+    PSL_REQUIRE(plans, "NULL plan array");
+    PSL_REQUIRE(n_plans >= 1 && n_plans <= kMaxPlanSet,
+                "n_plans outside 1..%d", kMaxPlanSet);
+    PSL_REQUIRE(first_batch >= 0 && n_batches >= 0, "bad batch range");
+    psl_status s;
+    for (int i = 0; i < n_plans; ++i) {
+        PSL_REQUIRE(plans[i], "NULL plan %d", i);
+        for (int j = 0; j < i; ++j)
+            if ((s = check_side_by_side(plans[j], plans[i]))) return s;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipStream_t sq[kMaxPlanSet];
+    for (int i = 0; i < n_plans; ++i) {
+        if ((s = ensure_side(plans[i]))) return s;
+        sq[i] = i == 0 ? st : plans[i]->side;
+    }
+    // the plan streams start after the caller's earlier work on `stream`
+    PSL_HIP(hipEventRecord(plans[0]->ev_fork, st));
+    for (int i = 1; i < n_plans; ++i)
+        PSL_HIP(hipStreamWaitEvent(sq[i], plans[0]->ev_fork, 0));
+    for (int i = 0; i < n_plans; ++i)
+        if ((s = set_i64(plans[i]->d_batch, first_batch + i, sq[i])))
+            return s;
+    for (int32_t k = 0; k < n_batches; ++k) {
+        const int q = k % n_plans;
+        psl_plan *p = plans[q];
+        psl_launch L = p->launch;
+        if (n_plans > 1) L.blocks_per_cu = std::max(1, L.blocks_per_cu / 2);
+        if ((s = enqueue_transport(p, &L, sq[q]))) return s;
+        // folds in batch order: after the previous batch's fold
+        if (k > 0)
+            PSL_HIP(hipStreamWaitEvent(
+                sq[q], plans[(k - 1) % n_plans]->ev_a, 0));
+        if ((s = enqueue_fold(p, n_plans, sq[q]))) return s;
+        PSL_HIP(hipEventRecord(p->ev_a, sq[q]));
+    }
+    // `stream` joins the plan streams
+    for (int i = 1; i < n_plans; ++i) {
+        PSL_HIP(hipEventRecord(plans[i]->ev_b, sq[i]));
+        PSL_HIP(hipStreamWaitEvent(st, plans[i]->ev_b, 0));
     }
     return PSL_OK;
 }

@@ -480,6 +480,23 @@ class Engine:
                 setattr(self, k, v)
         return PlanPair(a, b)
 
+    def make_plan_set(self, n, stream=None):
+        """n psl_plans over this engine's fields and running sums, on the
+        engine's first n sets of queues, accumulators, statistics (and
+        their own plan workspaces), for psl_plan_run_set."""
+        from . import PlanSet
+        self._make_sets(n)
+        cur = {k: getattr(self, k, None) for k in self._SET_KEYS}
+        plans = []
+        try:
+            for q in range(n):
+                self._use(q)
+                plans.append(self.make_plan(stream))
+        finally:
+            for k, v in cur.items():
+                setattr(self, k, v)
+        return PlanSet(plans)
+
     def stats_dict(self):
         """Batch statistics; `lost` includes entries a full queue region
         could not take."""

@@ -163,3 +163,58 @@ def test_plan_pair_rejects_shared_buffers():
     assert "own queues" in P.lib().psl_last_error().decode()
     a.destroy()
     b.destroy()
+
+
+@pytest.mark.parametrize("n_plans,n_batches", [(3, 7), (2, 5), (1, 3),
+                                               (4, 2)])
+def test_plan_set_equals_single_plan(n_plans, n_batches):
+    """n plans of one engine, batch i on plan i mod n, n batches in flight
+    on n streams: the sums equal one plan's over the same batches (counts
+    below, equal to and above n), and again after eager torch work and the
+    set's tuning."""
+    import torch
+    wl = _imrt()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ref = _engine(wl, 250_000)
+        p_r = ref.make_plan()
+        eng = _engine(wl, 250_000)
+        ps = eng.make_plan_set(n_plans)
+        _say("case plan set n_plans=%d n_batches=%d" % (n_plans, n_batches))
+        p_r.run(0, n_batches, use_graph=False)
+        ps.run(0, n_batches)
+        torch.cuda.current_stream().synchronize()
+        want = ref.s1.cpu().numpy()
+        got = eng.s1.cpu().numpy()
+        assert got.any() and np.array_equal(got, want)
+        assert np.array_equal(eng.s2.cpu().numpy(), ref.s2.cpu().numpy())
+        x = torch.randn(1 << 20, device="cuda")
+        float((x * 3.0).sum())
+        ps.autotune(trials=1)
+        p_r.run(n_batches, 4, use_graph=False)
+        ps.run(n_batches, 4)
+        torch.cuda.current_stream().synchronize()
+        assert np.array_equal(eng.s1.cpu().numpy(), ref.s1.cpu().numpy())
+        assert np.array_equal(eng.s2.cpu().numpy(), ref.s2.cpu().numpy())
+    ps.destroy()
+    p_r.destroy()
+
+
+def test_plan_set_rejects_bad_sets():
+    import ctypes as C
+    import paper_1302_1861_amd as P
+    wl = _imrt(n_particles=100_000)
+    eng = _engine(wl, 50_000)
+    a = eng.make_plan()
+    b = eng.make_plan()          # same queues, accumulator and statistics
+    h = (C.c_void_p * 2)(a.handle, b.handle)
+    assert P.lib().psl_plan_run_set(h, 2, 0, 2, None) == P.PSL_EINVAL
+    assert "own queues" in P.lib().psl_last_error().decode()
+    h = (C.c_void_p * 2)(a.handle, a.handle)
+    assert P.lib().psl_plan_run_set(h, 2, 0, 2, None) == P.PSL_EINVAL
+    h = (C.c_void_p * 1)(a.handle)
+    assert P.lib().psl_plan_run_set(h, 9, 0, 2, None) == P.PSL_EINVAL
+    assert P.lib().psl_plan_run_set(h, 0, 0, 2, None) == P.PSL_EINVAL
+    assert P.lib().psl_plan_run_set(h, 1, -1, 2, None) == P.PSL_EINVAL
+    a.destroy()
+    b.destroy()
