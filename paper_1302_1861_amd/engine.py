@@ -289,7 +289,7 @@ class Engine:
         a third grid starts as CUs free up.  The dose does not depend on
         the launch shape."""
         from . import make_launch
-        depth = depth or self.pipeline_depth
+        depth = self.pipeline_depth if depth is None else depth
         L = self.launch if self.launch is not None else make_launch()
         return make_launch(
             blocks_per_cu=max(1, L.blocks_per_cu // min(depth, 2)),
@@ -401,7 +401,7 @@ class Engine:
         torch = self.torch
         if n <= 0:
             return
-        depth = depth or self.pipeline_depth
+        depth = self.pipeline_depth if depth is None else depth
         if depth < 1:
             raise ValueError("depth must be >= 1")
         self._make_sets(depth)
