@@ -292,7 +292,7 @@ class Engine:
         depth = self.pipeline_depth if depth is None else depth
         L = self.launch if self.launch is not None else make_launch()
         return make_launch(
-            blocks_per_cu=max(1, L.blocks_per_cu // min(depth, 2)),
+            blocks_per_cu=max(1, L.blocks_per_cu // min(max(depth, 1), 2)),
             rebucket=L.rebucket, n_cu=L.n_cu, block=L.block)
 
     def fold(self):
