@@ -153,3 +153,19 @@ def test_brick_blocks_cap_rejects_negative_and_restores_default():
     assert "max_blocks" in _err(P)
     assert P.lib().unet_set_brick_blocks(5) == 0
     assert P.lib().unet_set_brick_blocks(0) == 0
+
+
+def test_plan_set_rejects_null_and_bad_counts():
+    P = _P()
+    L = P.lib()
+    assert L.psl_plan_run_set(None, 1, 0, 1, None) == P.PSL_EINVAL
+    assert "plan array" in _err(P)
+    arr = (C.c_void_p * 2)(None, None)
+    for n in (0, 9, -1):
+        assert L.psl_plan_run_set(arr, n, 0, 1, None) == P.PSL_EINVAL
+        assert "n_plans" in _err(P)
+    assert L.psl_plan_run_set(arr, 1, 0, 1, None) == P.PSL_EINVAL
+    assert "NULL plan 0" in _err(P)
+    assert L.psl_plan_run_set(arr, 2, -1, 1, None) == P.PSL_EINVAL
+    assert "batch range" in _err(P)
+    assert L.psl_plan_run_set(arr, 2, 0, -3, None) == P.PSL_EINVAL
