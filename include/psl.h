@@ -564,7 +564,8 @@ typedef struct psl_tune_result {
  * dose_tally(FOLD) into d_s1/d_s2, all in one persistent launch per kernel
  * whatever the number of segments.  Buffers are as for the individual
  * calls; d_ws holds psl_plan_workspace_bytes() and is owned by the plan
- * until psl_plan_destroy.  *out receives a host handle.
+ * until psl_plan_destroy.  launch NULL: 256-thread blocks, 4 per CU,
+ * re-bucketing on.  *out receives a host handle.
  */
 size_t psl_plan_workspace_bytes(const psl_grid *g, int32_t n_fields,
                                 int64_t n_histories, const psl_queue *q);

@@ -213,7 +213,7 @@ extern "C" psl_status psl_plan_create(
     p->s1 = d_s1;
     p->s2 = d_s2;
     p->stats = d_stats;
-    p->launch = launch ? *launch : psl_launch{256, 8, 0, 1};
+    p->launch = launch ? *launch : psl_launch{256, 4, 0, 1};
     p->tws = base + a;
     p->tws_bytes = ws_bytes - a - 256;
     p->d_batch = reinterpret_cast<int64_t *>(base + ws_bytes - 256);
