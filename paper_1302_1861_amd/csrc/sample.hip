@@ -248,7 +248,12 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
             hi = range_at(H, n_ranges, h_total, lo, hl);
         }
         if (h0 >= n_slots) continue;
-        uint8_t code = kEmpty;
+        // the lane's accepted particle, written below
+        bool acc_ok = false;
+        float rE = 0.0f, rwt = 0.0f;
+        float ro[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        uint64_t ruid = 0;
+        uint8_t rcode = kEmpty;
         if (h0 < h_total) {
             st.add(PSL_STAT(histories), 1);
             // range containing h0 (last idx with H[idx] <= h0) and the
@@ -323,19 +328,13 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
                         if (oE >= s_edges[j]) b = j;
                     which = 1 + b;
                 }
-                const uint64_t uid = (uint64_t)batch * (uint64_t)h_total +
-                                     (uint64_t)h0;
-                slots.p.E[h0] = oE;
-                slots.p.x[h0] = o[0];
-                slots.p.y[h0] = o[1];
-                slots.p.z[h0] = o[2];
-                slots.p.u[h0] = o[3];
-                slots.p.v[h0] = o[4];
-                slots.p.w[h0] = o[5];
-                slots.p.wt[h0] = owt;
-                slots.p.uid[h0] = uid;
-                slots.p.ctr[h0] = which ? kSourceElectronCtr : 0u;
-                code = (uint8_t)which;
+                acc_ok = true;
+                rE = oE;
+                rwt = owt;
+#pragma unroll
+                for (int j = 0; j < 6; ++j) ro[j] = o[j];
+                ruid = (uint64_t)batch * (uint64_t)h_total + (uint64_t)h0;
+                rcode = (uint8_t)which;
                 st.add(which ? PSL_STAT(electrons) : PSL_STAT(photons), 1);
                 st.addf(PSL_STAT(e_in), (double)oE * owt);
             }
@@ -343,7 +342,26 @@ k_sample(psl_phsp ps, const int64_t *__restrict__ off, int64_t n_keys,
             if (status == 2) st.add(PSL_STAT(fluence_zero), 1);
             if (status == 3) st.add(PSL_STAT(missed), 1);
         }
-        slots.code[h0] = code;
+        // the chunk's accepted particles packed into its first slots in
+        // history order (the queues keep that order; each carries its
+        // uid), the other slots of the chunk marked empty: the
+        // compaction then reads whole lines of packed slots
+        const uint64_t am = __ballot(acc_ok);
+        if (acc_ok) {
+            const int64_t d = hf + __popcll(am & lanemask_lt());
+            slots.p.E[d] = rE;
+            slots.p.x[d] = ro[0];
+            slots.p.y[d] = ro[1];
+            slots.p.z[d] = ro[2];
+            slots.p.u[d] = ro[3];
+            slots.p.v[d] = ro[4];
+            slots.p.w[d] = ro[5];
+            slots.p.wt[d] = rwt;
+            slots.p.uid[d] = ruid;
+            slots.p.ctr[d] = rcode != 0 ? kSourceElectronCtr : 0u;
+            slots.code[d] = rcode;
+        }
+        if (lane >= __popcll(am)) slots.code[h0] = kEmpty;
     }
     block_stats_write(st, s_red, part);
 }
